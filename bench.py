@@ -1,0 +1,153 @@
+"""Benchmark of the extended-stencil FDTD time step on one MI355X.
+
+Workload (one step = Faraday + Ampere over the whole box, the fused
+out-of-place kernel): 512 x 256 x 256 periodic box, FP32, seed-drawn extended
+coefficient set, Gaussian pulse along x (wavelength 16, waist 32, duration 40
+cells) plus 1e-3 uniform noise; dt = 0.95 x the stability bound.  Inputs are
+synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: Gcell-updates/s, the roofline object of the fused kernel
+(algorithmic 48 B per cell-update against 8 TB/s), and the FP64 CPU oracle
+timed on the host cores on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SHAPE = (256, 256, 512)  # (nz, ny, nx)
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gcell-updates/s & %HBM roofline (fwd), fwd+adjoint time/step vs plain fwd"
+
+
+def make_inputs(shape, dtype):
+    """Seeded pulse workload; coefficients and dt from the library itself."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    import paper_1710_06829_amd as pkg
+
+    beta, delta = S.extended_beta_delta(201)
+    raw = [0.0] * 12
+    for a in range(3):
+        raw[4 * a + 1], raw[4 * a + 2], raw[4 * a + 3] = beta[a, 0], beta[a, 1], delta[a]
+    coeffs = pkg.consistent_alpha(raw)
+    dt_max, _, _ = pkg.cfl_limit(shape, coeffs)
+    dt = 0.95 * dt_max
+    f = S.gaussian_pulse(shape, dt, wavelength=16.0, waist=32.0, duration=40.0)
+    f = S.add_noise(f, 1e-3, 202)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(x)).to(device=dev, dtype=dtype) for x in f]
+    return t, coeffs, dt, f
+
+
+def cpu_baseline(f64_fields, coeffs, dt, steps):
+    """The FP64 C oracle, as it stands, on the full grid for `steps` steps."""
+    import oracle
+
+    cells = f64_fields[0].size
+    t0 = time.perf_counter()
+    oracle.c_run(f64_fields, steps, coeffs, dt)
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {
+        "value": cells * steps / el / 1e9,
+        "unit": "Gcell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} FP64 steps of the full 512x256x256 pulse workload "
+                  f"(plain C oracle, OpenMP, {el:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1710_06829_amd as pkg
+
+    steps = args.steps + (args.steps & 1)  # the fused kernel runs in pairs
+    fields, coeffs, dt, f64 = make_inputs(SHAPE, torch.float32)
+    solver = pkg.Solver(fields, dt, coeffs)
+    cells = SHAPE[0] * SHAPE[1] * SHAPE[2]
+
+    solver.run(args.warmup + (args.warmup & 1))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    solver.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / steps
+    gcells = cells * steps / (ms * 1e-3) / 1e9
+    # every launch in the timed region is the fused kernel (one step each)
+    bytes_per_launch = 48.0 * cells
+    achieved = bytes_per_launch / (ms_step * 1e-3) / 1e9
+    del solver, fields
+    torch.cuda.empty_cache()
+
+    line = {
+        "metric": METRIC,
+        "value": round(gcells, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "512x256x256 periodic box, FP32, extended Faraday stencil "
+                        "(seed-drawn set), Gaussian pulse along x + 1e-3 noise, "
+                        "dt = 0.95 x stability bound, fused step",
+            "grid": [SHAPE[2], SHAPE[1], SHAPE[0]],
+            "cells": cells,
+        },
+        "hbm_roofline_pct": round(100.0 * achieved / HBM_PEAK_GBS, 2),
+        "wall_s": round(wall, 4),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "fused_step_kernel<float, 8>",
+            "bytes_per_launch": bytes_per_launch,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(f64, coeffs, dt, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

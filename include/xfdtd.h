@@ -1,0 +1,192 @@
+/*
+ * libxfdtd — one time step of the 3D staggered-grid (Yee) FDTD Maxwell solver
+ * whose Faraday update uses the extended stencil of Blinne et al.,
+ * "A Systematic Approach to Numerical Dispersion in Maxwell Solvers"
+ * (arXiv:1710.06829), built for AMD Instinct MI355X (gfx950).
+ *
+ * Operations and where the paper defines them:
+ *   - extended difference D*_a with per-axis alpha, beta, delta: Sec. 2,
+ *     the D* equation; consistency condition eq.(alpha);
+ *   - Faraday update with D* and Ampere update with the Yee difference D:
+ *     App. A, eq. update1-6 (vacuum, J = 0);
+ *   - dispersion relation and stability bound: Sec. 3, eq. dispersion_relation
+ *     and eq. constraints; phase and group velocity: Sec. 5;
+ *   - divergence constraints: Sec. 2.1, eq. divstarb and eq. divE.
+ *
+ * Conventions (all functions):
+ *   - c = 1: dt is in the same length unit as dx, dy, dz.
+ *   - Periodic boundaries on all three axes.
+ *   - A field is a contiguous array of nz*ny*nx values, x fastest:
+ *     element (i, j, k) is at index (k*ny + j)*nx + i.  Six separate arrays,
+ *     in the order Ex, Ey, Ez, Bx, By, Bz, all of the handle's dtype.
+ *     Element (i, j, k) of a component sits at the staggered site of the
+ *     update equations: Ex (i+1/2, j, k), Ey (i, j+1/2, k), Ez (i, j, k+1/2),
+ *     Bx (i, j+1/2, k+1/2), By (i+1/2, j, k+1/2), Bz (i+1/2, j+1/2, k).
+ *   - The state is (E^n, B^{n-1/2}); a step is the Faraday update followed by
+ *     the Ampere update, giving (E^{n+1}, B^{n+1/2}).
+ *   - coeffs[12] = { alpha_x, beta_xy, beta_xz, delta_x,
+ *                    alpha_y, beta_yx, beta_yz, delta_y,
+ *                    alpha_z, beta_zx, beta_zy, delta_z },
+ *     beta_ab being the a-derivative's taps shifted along b (Sec. 2).
+ *     All 12 are used as given; alpha is not re-derived.
+ *   - Device memory (fields, scratch, k-vectors, outputs marked "device") is
+ *     owned by the caller and must stay valid while work that uses it may run.
+ *     The library allocates only small internal buffers (reduction partials)
+ *     and frees them in xfdtd_destroy.
+ *   - Every function returns XFDTD_OK (0) or a negative status; the message
+ *     of the last failure on the calling thread is xfdtd_last_error().
+ *     Argument errors are reported before any GPU work is queued.  An
+ *     asynchronous GPU error is reported by the next call that synchronises.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Work is queued on the stream given to xfdtd_bind (a hipStream_t; NULL
+ *     is the default stream).  Functions that return host values synchronise
+ *     that stream; the others return as soon as the work is queued.
+ */
+#ifndef XFDTD_H
+#define XFDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xfdtd_s *xfdtd_t;
+
+/* Grid: cell counts (each >= 1) and spacings (each > 0). */
+typedef struct {
+    int64_t nx, ny, nz;
+    double dx, dy, dz;
+} xfdtd_grid;
+
+enum { XFDTD_F32 = 1, XFDTD_F64 = 2 };
+
+enum {
+    XFDTD_OK = 0,
+    XFDTD_EINVAL = -1,     /* bad argument (size, pointer, dtype, value) */
+    XFDTD_EUNSTABLE = -2,  /* dt beyond the stability bound, or F_min < 0 */
+    XFDTD_ENONFINITE = -3, /* a non-finite value was found */
+    XFDTD_EHIP = -4,       /* a HIP runtime call failed */
+    XFDTD_ESTATE = -5      /* call not valid in the handle's state */
+};
+
+/* Warning bits returned by xfdtd_flags(). */
+enum { XFDTD_WARN_ALPHA = 1 /* coefficients do not satisfy eq.(alpha) to 1e-12 */ };
+
+/* Version of this interface (incremented on incompatible change). */
+int xfdtd_abi_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *xfdtd_last_error(void);
+
+/*
+ * Stability of a coefficient set (eq. constraints, Sec. 3).
+ * Computes F_min and F_max of F(k) = sum_a s_a^2 A_a over the whole zone
+ * 0 <= k_a d_a <= pi (exactly, by enumerating the stationary points of F as a
+ * quadratic in sin^2(k_a d_a / 2)), then dt_max = 1/sqrt(F_max).
+ * Host only; any output pointer may be NULL.  Returns XFDTD_EUNSTABLE if
+ * F_max <= 0 (no finite bound) — dt_max is then +inf.
+ */
+int xfdtd_cfl_limit(const xfdtd_grid *g, const double coeffs[12],
+                    double *dt_max, double *f_min, double *f_max);
+
+/* Fill alpha_x, alpha_y, alpha_z of coeffs in place from eq.(alpha):
+ * alpha_a = 1 - 2 beta_ab - 2 beta_ac - 3 delta_a.  Host only. */
+int xfdtd_consistent_alpha(double coeffs[12]);
+
+/*
+ * Create a solver for grid g, time step dt and coefficients coeffs.
+ * dtype is XFDTD_F32 or XFDTD_F64 (the type of the fields and of the
+ * arithmetic).  Fails with XFDTD_EUNSTABLE if dt^2 F_max > 1 or F_min < 0
+ * (tolerance 1e-12 relative) unless allow_unstable is non-zero.
+ * The folded weights dt*coef/d_a are computed in double and rounded once to
+ * dtype (xfdtd_get_weights reports them).  On success *out owns a handle that
+ * must be released with xfdtd_destroy.  No GPU work is queued.
+ */
+int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dtype,
+                 int allow_unstable, xfdtd_t *out);
+
+/* Release a handle (NULL is ignored).  Waits for the handle's queued work. */
+void xfdtd_destroy(xfdtd_t h);
+
+/* Warning bits (XFDTD_WARN_*) of a handle. */
+int xfdtd_flags(xfdtd_t h);
+
+/*
+ * Bind device memory and a stream.
+ *   fields[6]  : device pointers Ex, Ey, Ez, Bx, By, Bz (nz*ny*nx elements each,
+ *                handle dtype, 16-byte aligned).  They hold the state and receive
+ *                the result of every stepping call.
+ *   scratch[6] : device arrays of the same size, or NULL.  With scratch the
+ *                time loop uses the fused out-of-place step (ping-pong between
+ *                fields and scratch); without it, the in-place unfused pair.
+ *                Scratch contents are undefined after any call.
+ *   stream     : hipStream_t (NULL = default stream).
+ * Arrays must not overlap each other.  May be called again to rebind.
+ */
+int xfdtd_bind(xfdtd_t h, void *const fields[6], void *const scratch[6], void *stream);
+
+/* Faraday update in place on the bound B (App. A, eq. update1-3):
+ * B^{n+1/2} = B^{n-1/2} + dt (D* x E^n) with the signs of the paper. */
+int xfdtd_step_faraday(xfdtd_t h);
+
+/* Ampere update in place on the bound E (eq. update4-6, J = 0):
+ * E^{n+1} = E^n + dt (D x B^{n+1/2}). */
+int xfdtd_step_ampere(xfdtd_t h);
+
+/* n >= 0 full steps (Faraday then Ampere each); the result is in the bound
+ * fields when the queued work completes. */
+int xfdtd_run(xfdtd_t h, int64_t n);
+
+/*
+ * Folded weights actually used, as doubles exactly equal to the dtype values.
+ * w[0..14]: per axis a (x, y, z), five values
+ *   { dt*(alpha_a+delta_a)/d_a, dt*delta_a/d_a, dt*beta_a,t1/d_a, dt*beta_a,t2/d_a,
+ *     dt/d_a }
+ * (t1, t2 the transverse axes in coefficient order).  The extended difference
+ * is applied in the equivalent form
+ *   D*_a X = [(alpha+delta) g(p) + delta (g(p+e_a) + g(p-e_a))
+ *             + sum_t beta_at (g(p+e_t) + g(p-e_t))] / d_a,
+ *   g(q) = X[q+e_a] - X[q],
+ * which is an exact rewrite of the Sec. 2 definition (the delta pair
+ * X[p+2e_a] - X[p-e_a] is the sum of three consecutive g).  nw receives 15.
+ */
+int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw);
+
+/*
+ * Dispersion of the scheme at n wave vectors (Sec. 3 and Sec. 5), on the GPU.
+ *   k     : device, n x 3 doubles (k_x, k_y, k_z) in radians per length unit.
+ *   omega : device, n doubles: principal branch of sin(omega dt/2)/dt = sqrt(F(k)).
+ *   vph   : device, n doubles or NULL: omega/|k| (NaN at k = 0).
+ *   vg    : device, n x 3 doubles or NULL: d omega / d k.
+ *   stream: hipStream_t for the work.
+ * Entries with dt^2 F outside [0, 1] get NaN and the call returns
+ * XFDTD_EUNSTABLE (after synchronising the stream).  Arithmetic in double.
+ */
+int xfdtd_dispersion(const xfdtd_grid *g, double dt, const double coeffs[12],
+                     const double *k, int64_t n, double *omega, double *vph, double *vg,
+                     void *stream);
+
+/*
+ * Divergence diagnostics of the bound fields (eq. divstarb, eq. divE).
+ *   div_star_b : device, nz*ny*nx of the handle dtype, or NULL: D*.B at the
+ *                cell centres, element (i,j,k) at (i+1/2, j+1/2, k+1/2).
+ *   div_e      : device, same size, or NULL: D.E at the nodes (i, j, k).
+ * Queued on the handle's stream.
+ */
+int xfdtd_divergence(xfdtd_t h, void *div_star_b, void *div_e);
+
+/*
+ * max |D*.B - ref_b| and max |D.E - ref_e| over the grid, reduced on the GPU
+ * (ref arrays as written by xfdtd_divergence, or NULL for zero).
+ * Also checks the six fields for non-finite values.  Synchronises the stream.
+ * out[0] = max |D*.B - ref_b|, out[1] = max |D.E - ref_e|,
+ * out[2] = number of non-finite field values.  Returns XFDTD_ENONFINITE when
+ * out[2] > 0 (out is still filled).
+ */
+int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double out[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XFDTD_H */

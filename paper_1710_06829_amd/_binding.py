@@ -1,0 +1,92 @@
+"""ctypes binding of libxfdtd (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module converts torch
+tensors into device pointers and a HIP stream, and raises on error codes.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxfdtd.so")
+
+XFDTD_F32 = 1
+XFDTD_F64 = 2
+STATUS = {0: "XFDTD_OK", -1: "XFDTD_EINVAL", -2: "XFDTD_EUNSTABLE", -3: "XFDTD_ENONFINITE",
+          -4: "XFDTD_EHIP", -5: "XFDTD_ESTATE"}
+WARN_ALPHA = 1
+
+
+class XfdtdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+_lib = None
+
+# name -> (argtypes, restype); every symbol include/xfdtd.h declares
+_vp, _dp, _i64, _int = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int
+_GP = ctypes.POINTER(Grid)
+SIGNATURES = {
+    "xfdtd_abi_version": ([], _int),
+    "xfdtd_last_error": ([], ctypes.c_char_p),
+    "xfdtd_cfl_limit": ([_GP, _dp, _dp, _dp, _dp], _int),
+    "xfdtd_consistent_alpha": ([_dp], _int),
+    "xfdtd_create": ([_GP, ctypes.c_double, _dp, _int, _int, ctypes.POINTER(_vp)], _int),
+    "xfdtd_destroy": ([_vp], None),
+    "xfdtd_flags": ([_vp], _int),
+    "xfdtd_bind": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
+    "xfdtd_step_faraday": ([_vp], _int),
+    "xfdtd_step_ampere": ([_vp], _int),
+    "xfdtd_run": ([_vp, _i64], _int),
+    "xfdtd_get_weights": ([_vp, _dp, ctypes.POINTER(_int)], _int),
+    "xfdtd_dispersion": ([_GP, ctypes.c_double, _dp, _vp, _i64, _vp, _vp, _vp, _vp], _int),
+    "xfdtd_divergence": ([_vp, _vp, _vp], _int),
+    "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),
+}
+
+
+def lib():
+    """The loaded libxfdtd (raises ImportError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"libxfdtd.so not found at {LIB_PATH}: build it with "
+                "`python -m paper_1710_06829_amd.build` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != 0:
+        msg = lib().xfdtd_last_error()
+        raise XfdtdError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def dbl_array(values, n=None):
+    vals = [float(v) for v in values]
+    if n is not None and len(vals) != n:
+        raise ValueError(f"expected {n} values, got {len(vals)}")
+    return (ctypes.c_double * len(vals))(*vals)
+
+
+def make_grid(shape, spacing=(1.0, 1.0, 1.0)) -> Grid:
+    """Grid from a field shape (nz, ny, nx) and spacings (dx, dy, dz)."""
+    nz, ny, nx = (int(v) for v in shape)
+    dx, dy, dz = (float(v) for v in spacing)
+    return Grid(nx, ny, nz, dx, dy, dz)

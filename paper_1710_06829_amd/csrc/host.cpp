@@ -1,0 +1,516 @@
+// Host runtime of libxfdtd: argument checking, coefficient and time-step
+// preparation (eq.(alpha), eq. constraints), weight folding, launch
+// configuration, and the C entry points declared in include/xfdtd.h.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/xfdtd.h"
+#include "xfdtd_internal.h"
+
+using namespace xfdtd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(XFDTD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool grid_ok(const xfdtd_grid *g)
+{
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+    if (g->nx > (1 << 30) || g->ny > (1 << 30) || g->nz > (1 << 30)) return false;
+    if ((double)g->nx * (double)g->ny * (double)g->nz > 4.0e9) return false;
+    if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0)) return false;
+    if (!isfinite(g->dx) || !isfinite(g->dy) || !isfinite(g->dz)) return false;
+    return true;
+}
+
+bool coeffs_ok(const double *c)
+{
+    if (!c) return false;
+    for (int i = 0; i < 12; ++i)
+        if (!isfinite(c[i])) return false;
+    return true;
+}
+
+// Transverse axes of derivative axis a, in coefficient order.
+inline int t1_of(int a) { return a == 0 ? 1 : 0; }
+inline int t2_of(int a) { return a == 2 ? 1 : 2; }
+
+// Extremes of F over the zone.  With u_a = sin^2(k_a d_a / 2) in [0, 1] we have
+// s_a^2 = u_a / d_a^2 and cos(k_a d_a) = 1 - 2 u_a, so
+//   F(u) = sum_a (u_a/d_a^2) (alpha_a + delta_a (3 - 4 u_a) + sum_t 2 beta_at (1 - 2 u_t))
+// is a quadratic  lin.u + u^T Q u  on the unit cube.  Its extremes are at
+// points where the gradient vanishes within some face of the cube; every face
+// is one of 27 patterns (each u_a at 0, at 1, or free).  A face whose Hessian
+// is singular reaches its extremes on its own boundary, so it is skipped.
+void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi)
+{
+    double lin[3] = {0, 0, 0}, Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 3; ++a) {
+        const double inv = 1.0 / (sp[a] * sp[a]);
+        const double al = c[4 * a], b1 = c[4 * a + 1], b2 = c[4 * a + 2], de = c[4 * a + 3];
+        const int t1 = t1_of(a), t2 = t2_of(a);
+        lin[a] += inv * (al + 3.0 * de + 2.0 * b1 + 2.0 * b2);
+        Q[a][a] += -4.0 * de * inv;
+        // cross term -4 beta_at u_a u_t / d_a^2; S = (Q + Q^T)/2 below
+        Q[a][t1] += -4.0 * b1 * inv;
+        Q[a][t2] += -4.0 * b2 * inv;
+    }
+    double S[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = (a == b) ? Q[a][a] : 0.5 * (Q[a][b] + Q[b][a]);
+    auto F = [&](const double u[3]) {
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            v += lin[a] * u[a];
+            for (int b = 0; b < 3; ++b) v += u[a] * S[a][b] * u[b];
+        }
+        return v;
+    };
+    double lo = INFINITY, hi = -INFINITY;
+    for (int pat = 0; pat < 27; ++pat) {
+        int st[3] = {pat % 3, (pat / 3) % 3, pat / 9};  // 0: u=0, 1: u=1, 2: free
+        double u[3];
+        int fr[3], nf = 0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = st[a] == 1 ? 1.0 : 0.0;
+            if (st[a] == 2) fr[nf++] = a;
+        }
+        if (nf > 0) {
+            // 2 S_ff u_f = -(lin_f + 2 S_fx u_x)
+            double M[3][4];
+            double scale = 0.0;
+            for (int r = 0; r < nf; ++r) {
+                double rhs = -lin[fr[r]];
+                for (int a = 0; a < 3; ++a)
+                    if (st[a] != 2) rhs -= 2.0 * S[fr[r]][a] * u[a];
+                for (int q = 0; q < nf; ++q) {
+                    M[r][q] = 2.0 * S[fr[r]][fr[q]];
+                    scale = fmax(scale, fabs(M[r][q]));
+                }
+                M[r][nf] = rhs;
+            }
+            // Gaussian elimination with partial pivoting
+            bool singular = scale == 0.0;
+            for (int col = 0; col < nf && !singular; ++col) {
+                int piv = col;
+                for (int r = col + 1; r < nf; ++r)
+                    if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+                if (fabs(M[piv][col]) <= 1e-13 * scale) {
+                    singular = true;
+                    break;
+                }
+                if (piv != col)
+                    for (int q = 0; q <= nf; ++q) {
+                        double t = M[col][q];
+                        M[col][q] = M[piv][q];
+                        M[piv][q] = t;
+                    }
+                for (int r = 0; r < nf; ++r) {
+                    if (r == col) continue;
+                    const double f = M[r][col] / M[col][col];
+                    for (int q = col; q <= nf; ++q) M[r][q] -= f * M[col][q];
+                }
+            }
+            if (singular) continue;
+            bool feasible = true;
+            for (int r = 0; r < nf; ++r) {
+                double v = M[r][nf] / M[r][r];
+                if (v < -1e-12 || v > 1.0 + 1e-12) feasible = false;
+                u[fr[r]] = fmin(1.0, fmax(0.0, v));
+            }
+            if (!feasible) continue;
+        }
+        const double v = F(u);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    *out_lo = lo;
+    *out_hi = hi;
+}
+
+int pick_tile_y(int dtype) { return dtype == XFDTD_F64 ? 4 : 8; }
+
+int pick_zchunk(const xfdtd_grid &g, int tile_y)
+{
+    const char *env = getenv("XFDTD_ZCHUNK");
+    if (env && atoi(env) > 0) return atoi(env);
+    const int64_t ntx = (g.nx + 63) / 64, nty = (g.ny + tile_y - 1) / tile_y;
+    const int64_t tiles = ntx * nty;
+    // aim for at least ~2048 workgroups (8 per CU), chunks no shorter than 8
+    int64_t nzc = (2048 + tiles - 1) / tiles;
+    if (nzc < 1) nzc = 1;
+    int64_t z = (g.nz + nzc - 1) / nzc;
+    if (z < 8) z = 8;
+    if (z > g.nz) z = g.nz;
+    return (int)z;
+}
+
+}  // namespace
+
+struct xfdtd_s {
+    xfdtd_grid g;
+    double dt;
+    double coeffs[12];
+    int dtype;
+    int flags;
+    double w[15];  // folded weights as doubles equal to the dtype values
+    Weights<float> wf;
+    Weights<double> wd;
+    void *fields[6];
+    void *scratch[6];
+    bool bound;
+    bool have_scratch;
+    hipStream_t stream;
+    int tile_y, zchunk;
+    int device;
+    double *partials;  // device, for reductions
+    int npartials;
+};
+
+namespace {
+
+template <typename T>
+Weights<T> fold(const xfdtd_s &h, double out[15])
+{
+    Weights<T> w;
+    const double sp[3] = {h.g.dx, h.g.dy, h.g.dz};
+    for (int a = 0; a < 3; ++a) {
+        const double *c = h.coeffs + 4 * a;
+        const double s = h.dt / sp[a];
+        w.wc[a] = (T)(s * (c[0] + c[3]));
+        w.wd[a] = (T)(s * c[3]);
+        w.wb[a][0] = (T)(s * c[1]);
+        w.wb[a][1] = (T)(s * c[2]);
+        w.wa[a] = (T)s;
+        out[5 * a + 0] = (double)w.wc[a];
+        out[5 * a + 1] = (double)w.wd[a];
+        out[5 * a + 2] = (double)w.wb[a][0];
+        out[5 * a + 3] = (double)w.wb[a][1];
+        out[5 * a + 4] = (double)w.wa[a];
+    }
+    return w;
+}
+
+template <typename T>
+Fields<T> as_fields(void *const p[6])
+{
+    Fields<T> f;
+    for (int c = 0; c < 6; ++c) f.c[c] = (T *)p[c];
+    return f;
+}
+
+Dims dims_of(const xfdtd_grid &g) { return Dims{(int)g.nx, (int)g.ny, (int)g.nz}; }
+
+int check_bound(xfdtd_t h)
+{
+    if (!h) return fail(XFDTD_EINVAL, "null handle");
+    if (!h->bound) return fail(XFDTD_ESTATE, "no fields bound (call xfdtd_bind first)");
+    return XFDTD_OK;
+}
+
+template <typename T>
+int run_t(xfdtd_t h, int64_t n)
+{
+    const Dims d = dims_of(h->g);
+    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf
+                                                                      : (const void *)&h->wd);
+    Fields<T> f = as_fields<T>(h->fields);
+    if (!h->have_scratch) {
+        for (int64_t s = 0; s < n; ++s) {
+            HIP_TRY(launch_faraday<T>(f, d, w, h->stream), "faraday launch");
+            HIP_TRY(launch_ampere<T>(f, d, w, h->stream), "ampere launch");
+        }
+        return XFDTD_OK;
+    }
+    Fields<T> s = as_fields<T>(h->scratch);
+    int64_t left = n;
+    if (left & 1) {  // odd count: one in-place step keeps the result in `fields`
+        HIP_TRY(launch_faraday<T>(f, d, w, h->stream), "faraday launch");
+        HIP_TRY(launch_ampere<T>(f, d, w, h->stream), "ampere launch");
+        --left;
+    }
+    for (; left > 0; left -= 2) {
+        HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+        HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+    }
+    return XFDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xfdtd_abi_version(void) { return 1; }
+
+const char *xfdtd_last_error(void) { return g_err.c_str(); }
+
+int xfdtd_consistent_alpha(double coeffs[12])
+{
+    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+    for (int a = 0; a < 3; ++a)
+        coeffs[4 * a] = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
+    return XFDTD_OK;
+}
+
+int xfdtd_cfl_limit(const xfdtd_grid *g, const double coeffs[12], double *dt_max, double *f_min,
+                    double *f_max)
+{
+    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
+    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+    const double sp[3] = {g->dx, g->dy, g->dz};
+    double lo, hi;
+    f_range(sp, coeffs, &lo, &hi);
+    if (f_min) *f_min = lo;
+    if (f_max) *f_max = hi;
+    if (!(hi > 0.0)) {
+        if (dt_max) *dt_max = INFINITY;
+        return fail(XFDTD_EUNSTABLE, "F_max = %g <= 0: no stable positive frequency range", hi);
+    }
+    if (dt_max) *dt_max = 1.0 / sqrt(hi);
+    return XFDTD_OK;
+}
+
+int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dtype,
+                 int allow_unstable, xfdtd_t *out)
+{
+    if (!out) return fail(XFDTD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid (sizes >= 1, spacings > 0)");
+    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+    if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
+    if (dtype != XFDTD_F32 && dtype != XFDTD_F64) return fail(XFDTD_EINVAL, "dtype must be XFDTD_F32 or XFDTD_F64");
+    const double sp[3] = {g->dx, g->dy, g->dz};
+    double lo, hi;
+    f_range(sp, coeffs, &lo, &hi);
+    if (!allow_unstable) {
+        const double tol = 1e-12 * fmax(1.0, fabs(hi));
+        if (lo < -tol) return fail(XFDTD_EUNSTABLE, "F_min = %.17g < 0: dispersion relation ill-defined", lo);
+        if (dt * dt * hi > 1.0 + 1e-12)
+            return fail(XFDTD_EUNSTABLE, "dt = %.17g exceeds the stability bound %.17g", dt, 1.0 / sqrt(hi));
+    }
+    xfdtd_s *h = new (std::nothrow) xfdtd_s();
+    if (!h) return fail(XFDTD_EINVAL, "out of host memory");
+    h->g = *g;
+    h->dt = dt;
+    memcpy(h->coeffs, coeffs, sizeof h->coeffs);
+    h->dtype = dtype;
+    h->flags = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double al = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
+        if (fabs(al - coeffs[4 * a]) > 1e-12) h->flags |= XFDTD_WARN_ALPHA;
+    }
+    if (dtype == XFDTD_F32)
+        h->wf = fold<float>(*h, h->w);
+    else
+        h->wd = fold<double>(*h, h->w);
+    h->bound = false;
+    h->have_scratch = false;
+    h->stream = nullptr;
+    h->tile_y = pick_tile_y(dtype);
+    const char *ty = getenv("XFDTD_TILE_Y");
+    if (ty && (atoi(ty) == 4 || atoi(ty) == 8)) h->tile_y = atoi(ty);
+    h->zchunk = pick_zchunk(*g, h->tile_y);
+    h->device = -1;
+    h->partials = nullptr;
+    h->npartials = 0;
+    *out = h;
+    return XFDTD_OK;
+}
+
+void xfdtd_destroy(xfdtd_t h)
+{
+    if (!h) return;
+    if (h->partials) {
+        hipStreamSynchronize(h->stream);
+        hipFree(h->partials);
+    }
+    delete h;
+}
+
+int xfdtd_flags(xfdtd_t h) { return h ? h->flags : 0; }
+
+int xfdtd_bind(xfdtd_t h, void *const fields[6], void *const scratch[6], void *stream)
+{
+    if (!h) return fail(XFDTD_EINVAL, "null handle");
+    if (!fields) return fail(XFDTD_EINVAL, "fields is null");
+    const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
+    const size_t bytes = (size_t)h->g.nx * h->g.ny * h->g.nz * esz;
+    void *all[12];
+    int nall = 0;
+    for (int c = 0; c < 6; ++c) {
+        if (!fields[c]) return fail(XFDTD_EINVAL, "fields[%d] is null", c);
+        if ((uintptr_t)fields[c] % 16) return fail(XFDTD_EINVAL, "fields[%d] not 16-byte aligned", c);
+        all[nall++] = fields[c];
+    }
+    if (scratch) {
+        for (int c = 0; c < 6; ++c) {
+            if (!scratch[c]) return fail(XFDTD_EINVAL, "scratch[%d] is null (pass scratch = NULL for none)", c);
+            if ((uintptr_t)scratch[c] % 16) return fail(XFDTD_EINVAL, "scratch[%d] not 16-byte aligned", c);
+            all[nall++] = scratch[c];
+        }
+    }
+    for (int a = 0; a < nall; ++a)
+        for (int b = a + 1; b < nall; ++b) {
+            const uintptr_t pa = (uintptr_t)all[a], pb = (uintptr_t)all[b];
+            if (pa < pb + bytes && pb < pa + bytes) return fail(XFDTD_EINVAL, "bound arrays %d and %d overlap", a, b);
+        }
+    for (int c = 0; c < 6; ++c) {
+        h->fields[c] = fields[c];
+        h->scratch[c] = scratch ? scratch[c] : nullptr;
+    }
+    h->have_scratch = scratch != nullptr;
+    h->stream = (hipStream_t)stream;
+    h->bound = true;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    h->device = dev;
+    return XFDTD_OK;
+}
+
+int xfdtd_step_faraday(xfdtd_t h)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const Dims d = dims_of(h->g);
+    if (h->dtype == XFDTD_F32)
+        HIP_TRY(launch_faraday<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "faraday launch");
+    else
+        HIP_TRY(launch_faraday<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "faraday launch");
+    return XFDTD_OK;
+}
+
+int xfdtd_step_ampere(xfdtd_t h)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const Dims d = dims_of(h->g);
+    if (h->dtype == XFDTD_F32)
+        HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "ampere launch");
+    else
+        HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "ampere launch");
+    return XFDTD_OK;
+}
+
+int xfdtd_run(xfdtd_t h, int64_t n)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+    return h->dtype == XFDTD_F32 ? run_t<float>(h, n) : run_t<double>(h, n);
+}
+
+int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw)
+{
+    if (!h || !w) return fail(XFDTD_EINVAL, "null argument");
+    memcpy(w, h->w, sizeof h->w);
+    if (nw) *nw = 15;
+    return XFDTD_OK;
+}
+
+int xfdtd_dispersion(const xfdtd_grid *g, double dt, const double coeffs[12], const double *k, int64_t n,
+                     double *omega, double *vph, double *vg, void *stream)
+{
+    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
+    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+    if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
+    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+    if (n == 0) return XFDTD_OK;
+    if (!k || !omega) return fail(XFDTD_EINVAL, "k and omega must be device pointers");
+    if (n > ((int64_t)1 << 38)) return fail(XFDTD_EINVAL, "n too large");
+    hipStream_t s = (hipStream_t)stream;
+    const double sp[3] = {g->dx, g->dy, g->dz};
+    unsigned int *bad = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&bad, sizeof(unsigned int), s), "hipMallocAsync");
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s), "hipMemsetAsync");
+    hipError_t e = launch_dispersion(k, n, dt, coeffs, sp, omega, vph, vg, bad, s);
+    unsigned int nbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFreeAsync(bad, s);
+    if (e != hipSuccess) return hip_fail(e, "dispersion");
+    if (nbad) return fail(XFDTD_EUNSTABLE, "%u wave vectors have dt^2 F outside [0, 1] (omega = NaN there)", nbad);
+    return XFDTD_OK;
+}
+
+int xfdtd_divergence(xfdtd_t h, void *div_star_b, void *div_e)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
+    const Dims d = dims_of(h->g);
+    if (h->dtype == XFDTD_F32)
+        HIP_TRY(launch_divergence<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (float *)div_star_b,
+                                         (float *)div_e, h->stream), "divergence launch");
+    else
+        HIP_TRY(launch_divergence<double>(as_fields<double>(h->fields), d, h->coeffs, sp, (double *)div_star_b,
+                                          (double *)div_e, h->stream), "divergence launch");
+    return XFDTD_OK;
+}
+
+int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double out[3])
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!out) return fail(XFDTD_EINVAL, "out is null");
+    const int nblocks = 1024;
+    if (!h->partials) {
+        HIP_TRY(hipMalloc((void **)&h->partials, sizeof(double) * 3 * nblocks), "hipMalloc");
+        h->npartials = nblocks;
+    }
+    const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
+    const Dims d = dims_of(h->g);
+    if (h->dtype == XFDTD_F32)
+        HIP_TRY(launch_divergence_max<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (const float *)ref_b,
+                                             (const float *)ref_e, h->partials, nblocks, h->stream),
+                "divergence_max launch");
+    else
+        HIP_TRY(launch_divergence_max<double>(as_fields<double>(h->fields), d, h->coeffs, sp,
+                                              (const double *)ref_b, (const double *)ref_e, h->partials,
+                                              nblocks, h->stream),
+                "divergence_max launch");
+    double host[3 * 1024];
+    HIP_TRY(hipMemcpyAsync(host, h->partials, sizeof(double) * 3 * nblocks, hipMemcpyDeviceToHost, h->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    out[0] = out[1] = out[2] = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        out[0] = fmax(out[0], host[3 * b]);
+        out[1] = fmax(out[1], host[3 * b + 1]);
+        out[2] += host[3 * b + 2];
+    }
+    if (out[2] > 0) return fail(XFDTD_ENONFINITE, "%.0f non-finite field values", out[2]);
+    return XFDTD_OK;
+}
+
+}  // extern "C"

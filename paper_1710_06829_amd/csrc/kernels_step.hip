@@ -1,0 +1,350 @@
+// Time-step kernels of libxfdtd for gfx950 (CDNA4, wave64).
+//
+// One step advances (E^n, B^{n-1/2}) to (E^{n+1}, B^{n+1/2}): the Faraday
+// update with the extended difference D* (App. A, eq. update1-3; D* from
+// Sec. 2) followed by the Yee Ampere update (eq. update4-6, J = 0).
+//
+// The extended difference is evaluated as a 7-point "star" of the plain
+// forward difference g(q) = X[q+e_a] - X[q] (see Weights in
+// xfdtd_internal.h): per B component two stars, each of 7 g values, instead
+// of 2 x 12 raw taps.  The regrouping is exact in real arithmetic.
+//
+//   faraday_kernel / ampere_kernel : one thread per cell, in place, periodic
+//       indexing; neighbours come through the L1/L2 caches.
+//   fused_step_kernel : out of place.  A workgroup owns a 64 x TY tile of
+//       (x, y) columns and marches a chunk of z-planes.  Per plane it stages
+//       the next E plane (with a 2-cell halo) in LDS, forms the six g fields
+//       on the tile plus a 2/1-cell halo, evaluates B^{n+1/2} on the tile plus
+//       a 1-cell halo on the low x and y sides (redundantly with the
+//       neighbouring tile), and then E^{n+1} on the tile.  Values a lane needs
+//       along z (g at k-1, k, k+1; E at k, k+1, k+2; B^{n+1/2} at k-1) are kept
+//       in registers, so z-neighbours never touch LDS.  Each of the 12 field
+//       values per cell is read and written once from HBM (halo re-reads hit
+//       L2): 48 B (FP32) / 96 B (FP64) per cell-update.
+
+#include "xfdtd_internal.h"
+
+namespace xfdtd {
+
+namespace {
+
+__device__ __forceinline__ int wrap(int v, int n)
+{
+    int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
+// S_a[g](p) for one g field: centre, along-axis pair, two transverse pairs.
+template <typename T>
+__device__ __forceinline__ T star(T wc, T wd, T wb0, T wb1, T c, T ap, T am, T t1p, T t1m, T t2p,
+                                  T t2m)
+{
+    return wc * c + wd * (ap + am) + wb0 * (t1p + t1m) + wb1 * (t2p + t2m);
+}
+
+// One Ampere component: e + wa1 (b1 - b1m) - wa2 (b2 - b2m)
+template <typename T>
+__device__ __forceinline__ T ampere_eval(T e, T wa1, T b1, T b1m, T wa2, T b2, T b2m)
+{
+    return e + (wa1 * (b1 - b1m) - wa2 * (b2 - b2m));
+}
+
+template <typename T>
+__device__ __forceinline__ void nt_store(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// ---------------------------------------------------------------------------
+// unfused Faraday: B += S(D* E) in place
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void faraday_kernel(Fields<T> f, Dims d, Weights<T> w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return;
+    // wrapped coordinates for offsets -1..+2
+    int xs[4], ys[4], zs[4];
+    for (int o = 0; o < 4; ++o) {
+        xs[o] = wrap(i + o - 1, d.nx);
+        ys[o] = wrap(j + o - 1, d.ny);
+        zs[o] = wrap(k + o - 1, d.nz);
+    }
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+    auto at = [&](const T *X, int ox, int oy, int oz) -> T {
+        return X[(int64_t)zs[oz + 1] * nxy + (int64_t)ys[oy + 1] * d.nx + xs[ox + 1]];
+    };
+    // forward difference along axis a of X, at offset (ox, oy, oz)
+    auto g = [&](const T *X, int a, int ox, int oy, int oz) -> T {
+        return at(X, ox + (a == 0), oy + (a == 1), oz + (a == 2)) - at(X, ox, oy, oz);
+    };
+    // star S_a of component X at p; transverse axes in coefficient order
+    auto S = [&](const T *X, int a) -> T {
+        int e[3] = {0, 0, 0}, u[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        e[a] = 1;
+        const int t1 = (a == 0) ? 1 : 0, t2 = (a == 2) ? 1 : 2;
+        u[t1] = 1;
+        v[t2] = 1;
+        return star(w.wc[a], w.wd[a], w.wb[a][0], w.wb[a][1], g(X, a, 0, 0, 0),
+                    g(X, a, e[0], e[1], e[2]), g(X, a, -e[0], -e[1], -e[2]),
+                    g(X, a, u[0], u[1], u[2]), g(X, a, -u[0], -u[1], -u[2]),
+                    g(X, a, v[0], v[1], v[2]), g(X, a, -v[0], -v[1], -v[2]));
+    };
+    const T *Ex = f.c[0], *Ey = f.c[1], *Ez = f.c[2];
+    const T bx = S(Ey, 2) - S(Ez, 1);
+    const T by = S(Ez, 0) - S(Ex, 2);
+    const T bz = S(Ex, 1) - S(Ey, 0);
+    const int64_t p = (int64_t)k * nxy + (int64_t)j * d.nx + i;
+    f.c[3][p] = f.c[3][p] + bx;
+    f.c[4][p] = f.c[4][p] + by;
+    f.c[5][p] = f.c[5][p] + bz;
+}
+
+// ---------------------------------------------------------------------------
+// unfused Ampere: E += dt (D x B) in place
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weights<T> w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return;
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const int64_t p = (int64_t)k * nxy + (int64_t)j * d.nx + i;
+    const int64_t pxm = (int64_t)k * nxy + (int64_t)j * d.nx + wrap(i - 1, d.nx);
+    const int64_t pym = (int64_t)k * nxy + (int64_t)wrap(j - 1, d.ny) * d.nx + i;
+    const int64_t pzm = (int64_t)wrap(k - 1, d.nz) * nxy + (int64_t)j * d.nx + i;
+    const T *Bx = f.c[3], *By = f.c[4], *Bz = f.c[5];
+    const T bx = Bx[p], by = By[p], bz = Bz[p];
+    f.c[0][p] = ampere_eval(f.c[0][p], w.wa[1], bz, Bz[pym], w.wa[2], by, By[pzm]);
+    f.c[1][p] = ampere_eval(f.c[1][p], w.wa[2], bx, Bx[pzm], w.wa[0], bz, Bz[pxm]);
+    f.c[2][p] = ampere_eval(f.c[2][p], w.wa[0], by, By[pxm], w.wa[1], bx, Bx[pym]);
+}
+
+// ---------------------------------------------------------------------------
+// fused step, z-march (see the file header)
+// ---------------------------------------------------------------------------
+constexpr int TILE_X = 64;
+
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in, Fields<T> out,
+                                                                    Dims d, Weights<T> w,
+                                                                    int zchunk, int ntx, int nty)
+{
+    constexpr int PX = TILE_X + 4;  // LDS row pitch: x in [-2, 66)
+    constexpr int PY = TY + 4;      // rows y in [-2, TY + 2)
+    constexpr int P = PX * PY;
+    __shared__ T Ebuf[2][3][P];  // E(k+1), E(k+2)
+    __shared__ T Gbuf[2][6][P];  // g(k), g(k+1)
+    __shared__ T Bbuf[3][P];     // B^{n+1/2}(k)
+
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of tiles so that halo re-reads stay in its L2.
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
+    const int logical = xcd * q + min(xcd, r) + (bid >> 3);
+    const int tx = logical % ntx;
+    const int rest = logical / ntx;
+    const int ty = rest % nty;
+    const int zc = rest / nty;
+    const int x0 = tx * TILE_X, y0 = ty * TY, k0 = zc * zchunk;
+    const int TXe = min(TILE_X, d.nx - x0), TYe = min(TY, d.ny - y0);
+    const int KZe = min(zchunk, d.nz - k0);
+
+    // Lane roles.  Waves 0..TY+3 own the rows y = -2..TY+1 of the tile
+    // (lane = x); the last wave owns the four halo columns
+    // x = -2, -1, TXe, TXe+1 over the same rows.
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int rx = 0, ry = 0;
+    bool valid;
+    if (wave < TY + 4) {
+        ry = wave - 2;
+        rx = lane;
+        valid = rx < TXe && ry < TYe + 2;
+    } else {
+        const int sel = lane / PY;
+        ry = lane % PY - 2;
+        rx = sel == 0 ? -2 : sel == 1 ? -1 : sel == 2 ? TXe : TXe + 1;
+        valid = sel < 4 && ry < TYe + 2;
+    }
+    const bool isE = valid;                                     // loads E
+    const bool isG = valid && rx < TXe + 1 && ry < TYe + 1;     // forms g
+    const bool isB = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;  // B^{n+1/2}
+    const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;    // outputs
+
+    const int li = (ry + 2) * PX + (rx + 2);
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const int64_t col = valid ? (int64_t)wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+    auto plane = [&](int k) -> int64_t { return (int64_t)wrap(k, d.nz) * nxy + col; };
+
+    T e0[3] = {0, 0, 0}, e1[3] = {0, 0, 0}, epf[3] = {0, 0, 0}, bpf[3] = {0, 0, 0};
+    T gm[6] = {0, 0, 0, 0, 0, 0}, gc[6] = {0, 0, 0, 0, 0, 0};
+    T bprev[2] = {0, 0};
+    int eb = 0, gb = 0;
+
+    // prologue: E(k0-2) into registers and LDS, prefetch E(k0-1)
+    if (isE) {
+        const int64_t pa = plane(k0 - 2), pb = plane(k0 - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            e1[c] = in.c[c][pa];
+            epf[c] = in.c[c][pb];
+            Ebuf[0][c][li] = e1[c];
+        }
+    }
+
+    const int klast = k0 + KZe - 1;
+    for (int k = k0 - 3; k <= klast; ++k) {
+        T e2[3] = {0, 0, 0}, bo[3] = {0, 0, 0};
+        if (isE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e2[c] = epf[c];
+            if (k + 3 <= klast + 2) {
+                const int64_t pn = plane(k + 3);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) epf[c] = in.c[c][pn];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ebuf[eb ^ 1][c][li] = e2[c];
+        }
+        const bool doStar = k >= k0 - 1;
+        if (isB) {
+            if (doStar) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bo[c] = bpf[c];
+            }
+            if (k + 1 >= k0 - 1 && k + 1 <= klast) {
+                const int64_t pn = plane(k + 1);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bpf[c] = in.c[3 + c][pn];
+            }
+        }
+        __syncthreads();
+
+        // g(k+1) at this lane's column
+        T gn[6] = {0, 0, 0, 0, 0, 0};
+        if (isG) {
+            const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
+            gn[0] = e2[1] - e1[1];          // g_z[Ey] -> Bx (+S_z)
+            gn[1] = Ez1[li + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
+            gn[2] = Ez1[li + 1] - e1[2];    // g_x[Ez] -> By (+S_x)
+            gn[3] = e2[0] - e1[0];          // g_z[Ex] -> By (-S_z)
+            gn[4] = Ex1[li + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
+            gn[5] = Ey1[li + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li] = gn[m];
+        }
+
+        // B^{n+1/2}(k): stars of g(k); z-neighbours from registers
+        T bn[3] = {0, 0, 0};
+        if (isB && doStar) {
+            const T(*G)[P] = Gbuf[gb];
+            // star argument order: centre, along-axis pair, t1 pair, t2 pair
+            const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[0], gn[0], gm[0],
+                               G[0][li + 1], G[0][li - 1], G[0][li + PX], G[0][li - PX]);
+            const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[1], G[1][li + PX],
+                               G[1][li - PX], G[1][li + 1], G[1][li - 1], gn[1], gm[1]);
+            const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[2], G[2][li + 1],
+                               G[2][li - 1], G[2][li + PX], G[2][li - PX], gn[2], gm[2]);
+            const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[3], gn[3], gm[3],
+                               G[3][li + 1], G[3][li - 1], G[3][li + PX], G[3][li - PX]);
+            const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[4], G[4][li + PX],
+                               G[4][li - PX], G[4][li + 1], G[4][li - 1], gn[4], gm[4]);
+            const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[5], G[5][li + 1],
+                               G[5][li - 1], G[5][li + PX], G[5][li - PX], gn[5], gm[5]);
+            bn[0] = bo[0] + (sz0 - sy1);
+            bn[1] = bo[1] + (sx2 - sz3);
+            bn[2] = bo[2] + (sy4 - sx5);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Bbuf[c][li] = bn[c];
+            if (isO && k >= k0) {
+                const int64_t po = plane(k);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[c]);
+            }
+        }
+        __syncthreads();
+
+        // E^{n+1}(k)
+        if (isO && k >= k0) {
+            const T ex = ampere_eval(e0[0], w.wa[1], bn[2], Bbuf[2][li - PX], w.wa[2], bn[1], bprev[1]);
+            const T ey = ampere_eval(e0[1], w.wa[2], bn[0], bprev[0], w.wa[0], bn[2], Bbuf[2][li - 1]);
+            const T ez = ampere_eval(e0[2], w.wa[0], bn[1], Bbuf[1][li - 1], w.wa[1], bn[0], Bbuf[0][li - PX]);
+            const int64_t po = plane(k);
+            nt_store(out.c[0] + po, ex);
+            nt_store(out.c[1] + po, ey);
+            nt_store(out.c[2] + po, ez);
+        }
+
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            e0[c] = e1[c];
+            e1[c] = e2[c];
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            gm[m] = gc[m];
+            gc[m] = gn[m];
+        }
+        bprev[0] = bn[0];
+        bprev[1] = bn[1];
+        eb ^= 1;
+        gb ^= 1;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s)
+{
+    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    hipLaunchKernelGGL(faraday_kernel<T>, grd, blk, 0, s, f, d, w);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s)
+{
+    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    hipLaunchKernelGGL(ampere_kernel<T>, grd, blk, 0, s, f, d, w);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
+                        int tile_y, int zchunk, hipStream_t s)
+{
+    const int ntx = (d.nx + TILE_X - 1) / TILE_X;
+    const int nty = (d.ny + tile_y - 1) / tile_y;
+    const int nzc = (d.nz + zchunk - 1) / zchunk;
+    const int64_t nb = (int64_t)ntx * nty * nzc;
+    if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    switch (tile_y) {
+    case 4:
+        hipLaunchKernelGGL((fused_step_kernel<T, 4>), dim3((unsigned)nb), dim3(64 * 9), 0, s, in,
+                           out, d, w, zchunk, ntx, nty);
+        break;
+    case 8:
+        hipLaunchKernelGGL((fused_step_kernel<T, 8>), dim3((unsigned)nb), dim3(64 * 13), 0, s, in,
+                           out, d, w, zchunk, ntx, nty);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_faraday<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
+template hipError_t launch_faraday<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
+template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
+template hipError_t launch_ampere<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
+template hipError_t launch_fused<float>(const Fields<float> &, const Fields<float> &, Dims,
+                                        const Weights<float> &, int, int, hipStream_t);
+template hipError_t launch_fused<double>(const Fields<double> &, const Fields<double> &, Dims,
+                                         const Weights<double> &, int, int, hipStream_t);
+
+}  // namespace xfdtd

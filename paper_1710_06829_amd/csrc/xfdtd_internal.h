@@ -1,0 +1,58 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libxfdtd.  Not part of the public interface (include/xfdtd.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xfdtd {
+
+// Folded weights of one step, in the arithmetic type T.
+//   wc[a] = dt (alpha_a + delta_a) / d_a   centre weight of the smoothing star
+//   wd[a] = dt delta_a / d_a               along-axis neighbours of the star
+//   wb[a][0/1] = dt beta_a,t / d_a         transverse neighbours (t1, t2)
+//   wa[a] = dt / d_a                       Yee difference of the Ampere update
+// The Faraday increment of a B component is a difference of two "stars"
+//   S_a[g](p) = wc g(p) + wd (g(p+e_a) + g(p-e_a)) + sum_t wb_t (g(p+e_t) + g(p-e_t))
+// applied to the plain forward difference g(q) = X[q+e_a] - X[q] of an E
+// component; this is the extended difference D*_a of Sec. 2 regrouped (the
+// delta pair X[p+2e_a] - X[p-e_a] is the sum of three consecutive g).
+template <typename T>
+struct Weights {
+    T wc[3], wd[3], wb[3][2], wa[3];
+};
+
+// Pointers of one state (six components) of a box.
+template <typename T>
+struct Fields {
+    T *c[6];  // Ex, Ey, Ez, Bx, By, Bz
+};
+
+struct Dims {
+    int nx, ny, nz;
+};
+
+// Launchers (kernels_step.hip).  All return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s);
+template <typename T>
+hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s);
+// One fused step from `in` to `out` (distinct buffers).  tile_y: rows per
+// tile (4 or 8), zchunk: planes per workgroup (>= 1).
+template <typename T>
+hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
+                        int tile_y, int zchunk, hipStream_t s);
+
+// Diagnostics (kernels_diag.hip).
+template <typename T>
+hipError_t launch_divergence(const Fields<T> &f, Dims d, const double coeffs[12],
+                             const double sp[3], T *div_star_b, T *div_e, hipStream_t s);
+template <typename T>
+hipError_t launch_divergence_max(const Fields<T> &f, Dims d, const double coeffs[12],
+                                 const double sp[3], const T *ref_b, const T *ref_e,
+                                 double *partials, int nblocks, hipStream_t s);
+hipError_t launch_dispersion(const double *k, int64_t n, double dt, const double coeffs[12],
+                             const double sp[3], double *omega, double *vph, double *vg,
+                             unsigned int *bad, hipStream_t s);
+
+}  // namespace xfdtd

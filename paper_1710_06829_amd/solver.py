@@ -1,0 +1,152 @@
+"""Torch-facing wrapper of libxfdtd.  PyTorch provides device memory and the
+stream; every numerical step runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _binding as B
+
+_DT = {torch.float32: B.XFDTD_F32, torch.float64: B.XFDTD_F64}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def consistent_alpha(coeffs):
+    """Return the 12 coefficients with alpha_x, alpha_y, alpha_z set by
+    eq.(alpha): alpha_a = 1 - 2 beta_ab - 2 beta_ac - 3 delta_a."""
+    arr = B.dbl_array(coeffs, 12)
+    B.check(B.lib().xfdtd_consistent_alpha(arr))
+    return [arr[i] for i in range(12)]
+
+
+def cfl_limit(shape, coeffs, spacing=(1.0, 1.0, 1.0)):
+    """(dt_max, F_min, F_max) of eq. constraints over the whole zone."""
+    g = B.make_grid(shape, spacing)
+    dtm, fmn, fmx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    B.check(B.lib().xfdtd_cfl_limit(ctypes.byref(g), B.dbl_array(coeffs, 12), ctypes.byref(dtm),
+                                    ctypes.byref(fmn), ctypes.byref(fmx)))
+    return dtm.value, fmn.value, fmx.value
+
+
+def dispersion(k: torch.Tensor, dt: float, coeffs, spacing=(1.0, 1.0, 1.0), want_vg=True,
+               allow_unstable=False):
+    """omega, v_ph, v_g at wave vectors k (device tensor (n, 3), float64)."""
+    if not (k.is_cuda and k.dtype == torch.float64 and k.dim() == 2 and k.shape[1] == 3):
+        raise ValueError("k must be a float64 CUDA tensor of shape (n, 3)")
+    k = k.contiguous()
+    n = k.shape[0]
+    om = torch.empty(n, dtype=torch.float64, device=k.device)
+    vph = torch.empty(n, dtype=torch.float64, device=k.device)
+    vg = torch.empty((n, 3), dtype=torch.float64, device=k.device) if want_vg else None
+    g = B.make_grid((1, 1, 1), spacing)
+    rc = B.lib().xfdtd_dispersion(ctypes.byref(g), float(dt), B.dbl_array(coeffs, 12), _ptr(k), n,
+                                  _ptr(om), _ptr(vph), _ptr(vg) if vg is not None else None,
+                                  _stream_handle(k.device))
+    if rc != 0 and not (allow_unstable and rc == -2):
+        B.check(rc)
+    return om, vph, vg
+
+
+class Solver:
+    """One periodic box advanced by the extended-stencil FDTD step.
+
+    ``fields`` are six tensors (Ex, Ey, Ez, Bx, By, Bz) of shape (nz, ny, nx)
+    on one HIP device, all float32 or all float64; the solver updates them in
+    place.  ``scratch=True`` allocates six more arrays so that ``run`` uses
+    the fused out-of-place kernel.
+    """
+
+    def __init__(self, fields, dt, coeffs, spacing=(1.0, 1.0, 1.0), scratch=True,
+                 allow_unstable=False):
+        fields = list(fields)
+        if len(fields) != 6:
+            raise ValueError("need six field tensors")
+        t0 = fields[0]
+        if t0.dtype not in _DT:
+            raise ValueError("fields must be float32 or float64")
+        for t in fields:
+            if not t.is_cuda or t.dtype != t0.dtype or t.shape != t0.shape or t.dim() != 3:
+                raise ValueError("fields must be CUDA tensors of one dtype and shape (nz, ny, nx)")
+            if not t.is_contiguous():
+                raise ValueError("fields must be contiguous")
+            if t.device != t0.device:
+                raise ValueError("fields must be on one device")
+        self.shape = tuple(t0.shape)
+        self.dtype = t0.dtype
+        self.device = t0.device
+        self.dt = float(dt)
+        self.coeffs = [float(c) for c in coeffs]
+        self.spacing = tuple(float(s) for s in spacing)
+        self.fields = fields
+        self.grid = B.make_grid(self.shape, self.spacing)
+        h = ctypes.c_void_p()
+        B.check(B.lib().xfdtd_create(ctypes.byref(self.grid), self.dt, B.dbl_array(self.coeffs, 12),
+                                     _DT[self.dtype], int(bool(allow_unstable)), ctypes.byref(h)))
+        self._h = h
+        self.scratch = [torch.empty_like(t) for t in fields] if scratch else None
+        self._bind()
+
+    def _bind(self):
+        arr = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in self.fields])
+        sarr = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in self.scratch]) if self.scratch else None
+        with torch.cuda.device(self.device):
+            B.check(B.lib().xfdtd_bind(self._h, arr, sarr, _stream_handle(self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            B.lib().xfdtd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def flags(self):
+        return B.lib().xfdtd_flags(self._h)
+
+    def step_faraday(self):
+        self._bind()
+        B.check(B.lib().xfdtd_step_faraday(self._h))
+
+    def step_ampere(self):
+        self._bind()
+        B.check(B.lib().xfdtd_step_ampere(self._h))
+
+    def run(self, n: int):
+        self._bind()
+        B.check(B.lib().xfdtd_run(self._h, int(n)))
+
+    def weights(self):
+        w = (ctypes.c_double * 15)()
+        nw = ctypes.c_int()
+        B.check(B.lib().xfdtd_get_weights(self._h, w, ctypes.byref(nw)))
+        return [w[i] for i in range(nw.value)]
+
+    def divergence(self):
+        """(D*.B, D.E) as new tensors of the field dtype."""
+        self._bind()
+        db = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        de = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        B.check(B.lib().xfdtd_divergence(self._h, _ptr(db), _ptr(de)))
+        return db, de
+
+    def divergence_max(self, ref_b=None, ref_e=None, raise_nonfinite=True):
+        """(max|D*.B - ref_b|, max|D.E - ref_e|, #non-finite) reduced on the GPU."""
+        self._bind()
+        out = (ctypes.c_double * 3)()
+        rc = B.lib().xfdtd_divergence_max(self._h, _ptr(ref_b) if ref_b is not None else None,
+                                          _ptr(ref_e) if ref_e is not None else None, out)
+        if rc != 0 and (raise_nonfinite or rc != -3):
+            B.check(rc)
+        return out[0], out[1], int(out[2])

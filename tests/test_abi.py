@@ -1,0 +1,166 @@
+"""The C interface on the host: library loads, every declared symbol is
+exported, and the host-only logic (stability bound, eq.(alpha), argument
+checks, weight folding) matches the oracle.  No GPU work is issued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import fdtd as O
+from paper_1710_06829_amd import _binding as B
+import paper_1710_06829_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"\b(xfdtd_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding wraps exactly these
+    assert set(names) <= set(B.SIGNATURES), set(names) - set(B.SIGNATURES)
+
+
+def test_abi_version():
+    assert B.lib().xfdtd_abi_version() >= 1
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_cfl_limit_matches_oracle(seed):
+    g = S.rng(3000 + seed)
+    beta = g.uniform(-0.05, 0.2, (3, 2))
+    delta = g.uniform(-0.2, 0.05, 3)
+    c = O.coeffs_from(beta, delta)
+    d = tuple(g.uniform(0.5, 2.0, 3))
+    dtm, fmn, fmx = pkg.cfl_limit((4, 4, 4), c, d)
+    omn, omx = O.stability_range(c, d)
+    assert abs(fmx - omx) < 1e-12 * abs(omx)
+    assert abs(fmn - omn) < 1e-12 * max(1.0, abs(omx))
+    assert abs(dtm - 1 / np.sqrt(omx)) < 1e-12
+
+
+def test_consistent_alpha():
+    beta, delta = S.distinct_beta_delta(5)
+    c = O.coeffs_from(beta, delta)
+    raw = c.copy()
+    raw[[0, 4, 8]] = 7.0
+    assert np.allclose(pkg.consistent_alpha(raw), c, atol=1e-15, rtol=0)
+
+
+def _create(shape=(4, 5, 6), dt=0.3, coeffs=None, dtype=B.XFDTD_F64, allow=0, spacing=(1, 1, 1)):
+    g = B.make_grid(shape, spacing)
+    h = ctypes.c_void_p()
+    c = O.yee_coeffs() if coeffs is None else coeffs
+    rc = B.lib().xfdtd_create(ctypes.byref(g), dt, B.dbl_array(c, 12), dtype, allow, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_rejects_unstable_dt_and_bad_arguments():
+    beta, delta = S.extended_beta_delta(6)
+    c = O.coeffs_from(beta, delta)
+    cfl = O.cfl_dt(c)
+    rc, h = _create(dt=cfl * 1.001, coeffs=c)
+    assert rc == -2 and not h.value
+    assert b"stability" in B.lib().xfdtd_last_error()
+    rc, h = _create(dt=cfl * 1.001, coeffs=c, allow=1)
+    assert rc == 0
+    B.lib().xfdtd_destroy(h)
+    rc, h = _create(dt=cfl * 0.999, coeffs=c)
+    assert rc == 0
+    B.lib().xfdtd_destroy(h)
+    assert _create(shape=(0, 4, 4))[0] == -1
+    assert _create(dt=-1.0)[0] == -1
+    assert _create(dt=float("nan"))[0] == -1
+    assert _create(dtype=3)[0] == -1
+    assert _create(spacing=(1, 0, 1))[0] == -1
+    bad = O.yee_coeffs()
+    bad[5] = float("inf")
+    assert _create(coeffs=bad)[0] == -1
+    # F_min < 0 (strongly negative delta) is rejected as ill-defined
+    neg = O.coeffs_from([[0.5, 0.5], [0.0, 0.0], [0.0, 0.0]], [0.0, 0.0, 0.0])
+    assert O.stability_range(neg)[0] < 0
+    assert _create(dt=0.01, coeffs=neg)[0] == -2
+
+
+def test_alpha_warning_flag():
+    c = O.yee_coeffs()
+    rc, h = _create(coeffs=c)
+    assert rc == 0 and B.lib().xfdtd_flags(h) == 0
+    B.lib().xfdtd_destroy(h)
+    c[0] = 0.9
+    rc, h = _create(coeffs=c, dt=0.2)
+    assert rc == 0 and B.lib().xfdtd_flags(h) & B.WARN_ALPHA
+    B.lib().xfdtd_destroy(h)
+
+
+@pytest.mark.parametrize("dtype,npdt", [(B.XFDTD_F32, np.float32), (B.XFDTD_F64, np.float64)])
+def test_weight_folding(dtype, npdt):
+    beta, delta = S.distinct_beta_delta(8)
+    c = O.coeffs_from(beta, delta)
+    sp = (1.0, 0.7, 1.3)
+    dt = 0.9 * O.cfl_dt(c, sp)
+    rc, h = _create(coeffs=c, dt=dt, dtype=dtype, spacing=sp)
+    assert rc == 0
+    w = (ctypes.c_double * 15)()
+    nw = ctypes.c_int()
+    assert B.lib().xfdtd_get_weights(h, w, ctypes.byref(nw)) == 0 and nw.value == 15
+    B.lib().xfdtd_destroy(h)
+    for a in range(3):
+        s = dt / sp[a]
+        exp = [s * (c[4 * a] + c[4 * a + 3]), s * c[4 * a + 3], s * c[4 * a + 1], s * c[4 * a + 2], s]
+        for m in range(5):
+            assert w[5 * a + m] == float(npdt(exp[m]))
+
+
+def test_calls_without_bound_fields_are_state_errors():
+    rc, h = _create()
+    assert rc == 0
+    assert B.lib().xfdtd_run(h, 3) == -5
+    assert B.lib().xfdtd_step_faraday(h) == -5
+    out = (ctypes.c_double * 3)()
+    assert B.lib().xfdtd_divergence_max(h, None, None, out) == -5
+    B.lib().xfdtd_destroy(h)
+    assert B.lib().xfdtd_run(None, 1) == -1
+
+
+def test_bind_checks_pointers_before_any_device_call():
+    rc, h = _create(shape=(4, 4, 4))
+    assert rc == 0
+    nbytes = 64 * 8
+    base = 1 << 40
+    f = (ctypes.c_void_p * 6)(*[base + i * nbytes for i in range(6)])
+    f_overlap = (ctypes.c_void_p * 6)(*[base + i * (nbytes // 2) for i in range(6)])
+    f_misaligned = (ctypes.c_void_p * 6)(*[base + 8 + i * nbytes for i in range(6)])
+    f_null = (ctypes.c_void_p * 6)(*[base + i * nbytes if i != 3 else 0 for i in range(6)])
+    assert B.lib().xfdtd_bind(h, f_overlap, None, None) == -1
+    assert B.lib().xfdtd_bind(h, f_misaligned, None, None) == -1
+    assert B.lib().xfdtd_bind(h, f_null, None, None) == -1
+    s_overlap = (ctypes.c_void_p * 6)(*[base + 3 * nbytes + i * nbytes for i in range(6)])
+    assert B.lib().xfdtd_bind(h, f, s_overlap, None) == -1
+    assert B.lib().xfdtd_bind(h, None, None, None) == -1
+    B.lib().xfdtd_destroy(h)
+
+
+def test_package_has_no_cpu_fallback():
+    """The GPU entry points refuse CPU tensors instead of computing on the host."""
+    import torch
+    f = [torch.zeros((4, 4, 4), dtype=torch.float64) for _ in range(6)]
+    with pytest.raises(ValueError):
+        pkg.Solver(f, 0.3, O.yee_coeffs())
+    with pytest.raises(ValueError):
+        pkg.dispersion(torch.zeros((3, 3), dtype=torch.float64), 0.3, O.yee_coeffs())
