@@ -175,58 +175,72 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
     const bool isB = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;  // B^{n+1/2}
     const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;    // outputs
 
-    const int li = (ry + 2) * PX + (rx + 2);
+    const int li = valid ? (ry + 2) * PX + (rx + 2) : 0;
     const int64_t nxy = (int64_t)d.nx * d.ny;
-    const int64_t col = valid ? (int64_t)wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
-    auto plane = [&](int k) -> int64_t { return (int64_t)wrap(k, d.nz) * nxy + col; };
+    // column offset of this lane; idle lanes use column 0 so that every lane
+    // can load unconditionally (in bounds, value unused)
+    const int col = valid ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+    const int nz = d.nz;
+    auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
 
-    T e0[3] = {0, 0, 0}, e1[3] = {0, 0, 0}, epf[3] = {0, 0, 0}, bpf[3] = {0, 0, 0};
-    T gm[6] = {0, 0, 0, 0, 0, 0}, gc[6] = {0, 0, 0, 0, 0, 0};
-    T bprev[2] = {0, 0};
+    T e0[3], e1[3], epf[3], bpf[3], gm[6], gc[6], bprev[2];
     int eb = 0, gb = 0;
 
-    // prologue: E(k0-2) into registers and LDS, prefetch E(k0-1)
-    if (isE) {
-        const int64_t pa = plane(k0 - 2), pb = plane(k0 - 1);
+    // wrapped plane indices (uniform): k+3 for the E prefetch, k+1 for the B
+    // prefetch, k for the outputs; k starts at k0 - 3
+    int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), w0 = wrap(k0 - 3, nz);
+
+    // prologue: E(k0-2) into registers and LDS, prefetch E(k0-1), B(k0-3)
+    {
+        const int64_t pa = (int64_t)wrap(k0 - 2, nz) * nxy, pb = (int64_t)wrap(k0 - 1, nz) * nxy;
+        const int64_t pc = (int64_t)w1 * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            e1[c] = in.c[c][pa];
-            epf[c] = in.c[c][pb];
-            Ebuf[0][c][li] = e1[c];
+            e1[c] = in.c[c][pa + col];
+            epf[c] = in.c[c][pb + col];
+            bpf[c] = in.c[3 + c][pc + col];
+        }
+        if (isE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ebuf[0][c][li] = e1[c];
         }
     }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) gm[m] = gc[m] = T(0);
+    e0[0] = e0[1] = e0[2] = T(0);
+    bprev[0] = bprev[1] = T(0);
 
     const int klast = k0 + KZe - 1;
     for (int k = k0 - 3; k <= klast; ++k) {
-        T e2[3] = {0, 0, 0}, bo[3] = {0, 0, 0};
-        if (isE) {
+        // consume the prefetched E(k+2) and B(k+1 of the previous round = k),
+        // then issue the next prefetch unconditionally
+        T e2[3], bo[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) e2[c] = epf[c];
-            if (k + 3 <= klast + 2) {
-                const int64_t pn = plane(k + 3);
+        for (int c = 0; c < 3; ++c) {
+            e2[c] = epf[c];
+            bo[c] = bpf[c];
+        }
+        {
+            const T *const *src = in.c;
+            const int64_t p3 = (int64_t)w3 * nxy;
+            w1 = inc(w1);
+            const int64_t p1 = (int64_t)w1 * nxy;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) epf[c] = in.c[c][pn];
+            for (int c = 0; c < 3; ++c) {
+                epf[c] = src[c][p3 + col];
+                bpf[c] = src[3 + c][p1 + col];
             }
+        }
+        if (isE) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) Ebuf[eb ^ 1][c][li] = e2[c];
         }
         const bool doStar = k >= k0 - 1;
-        if (isB) {
-            if (doStar) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) bo[c] = bpf[c];
-            }
-            if (k + 1 >= k0 - 1 && k + 1 <= klast) {
-                const int64_t pn = plane(k + 1);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) bpf[c] = in.c[3 + c][pn];
-            }
-        }
         __syncthreads();
 
         // g(k+1) at this lane's column
-        T gn[6] = {0, 0, 0, 0, 0, 0};
-        if (isG) {
+        T gn[6];
+        {
             const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
             gn[0] = e2[1] - e1[1];          // g_z[Ey] -> Bx (+S_z)
             gn[1] = Ez1[li + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
@@ -234,12 +248,14 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
             gn[3] = e2[0] - e1[0];          // g_z[Ex] -> By (-S_z)
             gn[4] = Ex1[li + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
             gn[5] = Ey1[li + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
+        }
+        if (isG) {
 #pragma unroll
             for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li] = gn[m];
         }
 
         // B^{n+1/2}(k): stars of g(k); z-neighbours from registers
-        T bn[3] = {0, 0, 0};
+        T bn[3] = {T(0), T(0), T(0)};
         if (isB && doStar) {
             const T(*G)[P] = Gbuf[gb];
             // star argument order: centre, along-axis pair, t1 pair, t2 pair
@@ -261,7 +277,7 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
 #pragma unroll
             for (int c = 0; c < 3; ++c) Bbuf[c][li] = bn[c];
             if (isO && k >= k0) {
-                const int64_t po = plane(k);
+                const int64_t po = (int64_t)w0 * nxy + col;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[c]);
             }
@@ -273,7 +289,7 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
             const T ex = ampere_eval(e0[0], w.wa[1], bn[2], Bbuf[2][li - PX], w.wa[2], bn[1], bprev[1]);
             const T ey = ampere_eval(e0[1], w.wa[2], bn[0], bprev[0], w.wa[0], bn[2], Bbuf[2][li - 1]);
             const T ez = ampere_eval(e0[2], w.wa[0], bn[1], Bbuf[1][li - 1], w.wa[1], bn[0], Bbuf[0][li - PX]);
-            const int64_t po = plane(k);
+            const int64_t po = (int64_t)w0 * nxy + col;
             nt_store(out.c[0] + po, ex);
             nt_store(out.c[1] + po, ey);
             nt_store(out.c[2] + po, ez);
@@ -293,6 +309,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
         bprev[1] = bn[1];
         eb ^= 1;
         gb ^= 1;
+        w3 = inc(w3);
+        w0 = inc(w0);
     }
 }
 
