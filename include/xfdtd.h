@@ -186,6 +186,49 @@ int xfdtd_divergence(xfdtd_t h, void *div_star_b, void *div_e);
  */
 int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double out[3]);
 
+/*
+ * Reverse-mode differentiation (adjoint of the step; not in the paper: the
+ * transposes of its update equations).  The forward step is
+ *   B' = B + K E   (Faraday increment, extended difference D*),
+ *   E' = E + L B'  (Ampere increment, Yee difference),
+ * so its adjoint maps (lE', lB') to
+ *   mu = lB' + L^T lE',  lE = lE' + K^T mu,  lB = mu,
+ * and adds <mu, (dK/dcoeff) E> to the gradient of each of the 12 coefficients
+ * (all 12 treated as independent inputs, alpha included).
+ *
+ * One reverse step on the handle's stream:
+ *   lam_in[6]  : device, dL/d(E^{n+1}, B^{n+1/2}) (Ex..Bz), read only.
+ *   lam_out[6] : device, receives dL/d(E^n, B^{n-1/2}); must not overlap lam_in.
+ *   e_n[3]     : device, the step's primal input E^n.
+ *   grad       : device, 12 doubles; this step's coefficient gradient is added.
+ * Arrays have the handle's grid and dtype.  Requires xfdtd_bind (for the
+ * stream; the bound fields are not touched).
+ */
+int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
+                       const void *const e_n[3], double *grad);
+
+/*
+ * Checkpointed gradient of n steps.  The forward pass stores the state every
+ * `seg` steps (seg <= 0 selects ceil(sqrt(n))); the backward pass recomputes
+ * each segment from its checkpoint, keeping the E of every step of the
+ * segment, and runs the adjoint steps in reverse.  Memory: ceil(n/seg) + 2
+ * states plus (seg - 1) E fields.
+ *
+ * xfdtd_grad_workspace: bytes of device workspace for (n, seg).
+ * xfdtd_grad_forward:   n steps from the bound fields; the final state is in
+ *                       the bound fields, checkpoints in ws (caller-owned,
+ *                       ws_bytes >= the workspace size, 256-byte aligned).
+ * xfdtd_grad_backward:  lam[6] (device, handle dtype) holds dL/d(final state)
+ *                       on entry and dL/d(initial state) on return; grad
+ *                       (host, 12 doubles) receives dL/dcoeffs.  ws must be
+ *                       the workspace filled by xfdtd_grad_forward with the
+ *                       same n and seg.  Synchronises the stream.
+ */
+int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes);
+int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes);
+int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes,
+                        void *const lam[6], double grad[12]);
+
 #ifdef __cplusplus
 }
 #endif

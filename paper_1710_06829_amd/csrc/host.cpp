@@ -199,6 +199,9 @@ struct xfdtd_s {
     int device;
     double *partials;  // device, for reductions
     int npartials;
+    double *apartials;  // device, adjoint per-workgroup gradient sums
+    int napartials;
+    double *grad_acc;   // device, 12 doubles
 };
 
 namespace {
@@ -347,6 +350,9 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->device = -1;
     h->partials = nullptr;
     h->npartials = 0;
+    h->apartials = nullptr;
+    h->napartials = 0;
+    h->grad_acc = nullptr;
     *out = h;
     return XFDTD_OK;
 }
@@ -354,10 +360,10 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
 void xfdtd_destroy(xfdtd_t h)
 {
     if (!h) return;
-    if (h->partials) {
-        hipStreamSynchronize(h->stream);
-        hipFree(h->partials);
-    }
+    if (h->partials || h->apartials || h->grad_acc) hipStreamSynchronize(h->stream);
+    if (h->partials) hipFree(h->partials);
+    if (h->apartials) hipFree(h->apartials);
+    if (h->grad_acc) hipFree(h->grad_acc);
     delete h;
 }
 
@@ -514,6 +520,241 @@ int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double
     }
     if (out[2] > 0) return fail(XFDTD_ENONFINITE, "%.0f non-finite field values", out[2]);
     return XFDTD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// adjoint and checkpointed gradient
+// ---------------------------------------------------------------------------
+namespace {
+
+int adjoint_tile_y(const xfdtd_s *h) { return h->dtype == XFDTD_F64 ? 4 : h->tile_y; }
+
+int ensure_adjoint_buffers(xfdtd_t h)
+{
+    const int nb = adjoint_blocks(dims_of(h->g), adjoint_tile_y(h), h->zchunk);
+    if (h->napartials < nb) {
+        if (h->apartials) {
+            HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+            HIP_TRY(hipFree(h->apartials), "hipFree");
+            h->apartials = nullptr;
+        }
+        HIP_TRY(hipMalloc((void **)&h->apartials, sizeof(double) * 12 * (size_t)nb), "hipMalloc");
+        h->napartials = nb;
+    }
+    if (!h->grad_acc) HIP_TRY(hipMalloc((void **)&h->grad_acc, sizeof(double) * 12), "hipMalloc");
+    return XFDTD_OK;
+}
+
+Scale12 grad_scale(const xfdtd_s *h)
+{
+    Scale12 sc;
+    const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
+    for (int j = 0; j < 12; ++j) sc.s[j] = h->dt / sp[j / 4];
+    return sc;
+}
+
+template <typename T>
+int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], double *grad)
+{
+    const Dims d = dims_of(h->g);
+    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const int ty = adjoint_tile_y(h);
+    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->zchunk, h->apartials, h->stream), "adjoint launch");
+    HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->zchunk), grad_scale(h), grad, h->stream),
+            "reduce launch");
+    return XFDTD_OK;
+}
+
+size_t field_bytes(const xfdtd_s *h)
+{
+    const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
+    const size_t b = (size_t)h->g.nx * h->g.ny * h->g.nz * esz;
+    return (b + 255) / 256 * 256;
+}
+
+int64_t default_seg(int64_t n, int64_t seg)
+{
+    if (seg > 0) return seg;
+    int64_t s = (int64_t)ceil(sqrt((double)(n > 0 ? n : 1)));
+    return s < 1 ? 1 : s;
+}
+
+// Workspace layout, in units of one field array (field_bytes):
+//   [0, 6*nck)            checkpoints, state m at step m*seg
+//   [6*nck, 6*nck+6)      state A (forward ping-pong; backward: B ping-pong)
+//   [6*nck+6, 6*nck+12)   state B (forward ping-pong; backward: lambda scratch)
+//   [6*nck+12, ...)       (seg-1) E snapshots (3 arrays each)
+uint64_t ws_arrays(int64_t n, int64_t seg)
+{
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    return (uint64_t)(6 * nck + 12 + 3 * (seg - 1));
+}
+
+template <typename T>
+Fields<T> state_at(char *ws, size_t fb, int64_t first)
+{
+    Fields<T> f;
+    for (int c = 0; c < 6; ++c) f.c[c] = (T *)(ws + (size_t)(first + c) * fb);
+    return f;
+}
+
+template <typename T>
+int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
+{
+    const size_t fb = field_bytes(h);
+    const Dims d = dims_of(h->g);
+    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    const size_t raw = (size_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
+    Fields<T> fields = as_fields<T>(h->fields);
+    Fields<T> ck0 = state_at<T>(ws, fb, 0);
+    for (int c = 0; c < 6; ++c)
+        HIP_TRY(hipMemcpyAsync(ck0.c[c], fields.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
+    Fields<T> A = state_at<T>(ws, fb, 6 * nck), B = state_at<T>(ws, fb, 6 * nck + 6);
+    Fields<T> cur = ck0;
+    for (int64_t s = 0; s < n; ++s) {
+        Fields<T> dst;
+        if (s + 1 == n)
+            dst = fields;
+        else if ((s + 1) % seg == 0)
+            dst = state_at<T>(ws, fb, 6 * ((s + 1) / seg));
+        else
+            dst = (cur.c[0] == A.c[0]) ? B : A;
+        HIP_TRY(launch_fused<T>(cur, dst, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+        cur = dst;
+    }
+    return XFDTD_OK;
+}
+
+template <typename T>
+int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam[6], double grad[12])
+{
+    int rc = ensure_adjoint_buffers(h);
+    if (rc) return rc;
+    const size_t fb = field_bytes(h);
+    const Dims d = dims_of(h->g);
+    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    const size_t raw = (size_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
+    HIP_TRY(hipMemsetAsync(h->grad_acc, 0, sizeof(double) * 12, h->stream), "hipMemsetAsync");
+    Fields<T> segB = state_at<T>(ws, fb, 6 * nck);   // two B buffers: comps 0..2 and 3..5
+    Fields<T> lamS = state_at<T>(ws, fb, 6 * nck + 6);
+    Fields<T> lamU = as_fields<T>(lam);
+    auto segE = [&](int64_t i) {  // E snapshot of step s0 + i, i in [1, seg)
+        T *const *p = nullptr;
+        (void)p;
+        Fields<T> f;
+        for (int c = 0; c < 3; ++c) f.c[c] = (T *)(ws + (size_t)(6 * nck + 12 + 3 * (i - 1) + c) * fb);
+        return f;
+    };
+    Fields<T> lcur = lamU, lnext = lamS;
+    for (int64_t m = nck - 1; m >= 0 && n > 0; --m) {
+        const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        Fields<T> ck = state_at<T>(ws, fb, 6 * m);
+        // recompute the segment, keeping E of every step
+        Fields<T> in = ck;
+        for (int64_t s = s0; s + 1 < s1; ++s) {
+            Fields<T> out;
+            Fields<T> e = segE(s + 1 - s0);
+            for (int c = 0; c < 3; ++c) out.c[c] = e.c[c];
+            for (int c = 0; c < 3; ++c) out.c[3 + c] = segB.c[3 * ((s - s0) & 1) + c];
+            HIP_TRY(launch_fused<T>(in, out, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+            in = out;
+        }
+        // reverse through the segment
+        for (int64_t s = s1 - 1; s >= s0; --s) {
+            const T *en[3];
+            if (s == s0) {
+                for (int c = 0; c < 3; ++c) en[c] = ck.c[c];
+            } else {
+                Fields<T> e = segE(s - s0);
+                for (int c = 0; c < 3; ++c) en[c] = e.c[c];
+            }
+            rc = adjoint_one<T>(h, lcur, lnext, en, h->grad_acc);
+            if (rc) return rc;
+            Fields<T> t = lcur;
+            lcur = lnext;
+            lnext = t;
+        }
+    }
+    if (lcur.c[0] != lamU.c[0])
+        for (int c = 0; c < 6; ++c)
+            HIP_TRY(hipMemcpyAsync(lamU.c[c], lcur.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
+    HIP_TRY(hipMemcpyAsync(grad, h->grad_acc, sizeof(double) * 12, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return XFDTD_OK;
+}
+
+int check_ws(xfdtd_t h, int64_t n, int64_t seg, const void *ws, uint64_t ws_bytes)
+{
+    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+    if (!ws) return fail(XFDTD_EINVAL, "workspace is null");
+    if ((uintptr_t)ws % 256) return fail(XFDTD_EINVAL, "workspace must be 256-byte aligned");
+    const uint64_t need = ws_arrays(n, seg) * field_bytes(h);
+    if (ws_bytes < need) return fail(XFDTD_EINVAL, "workspace too small: %llu < %llu bytes",
+                                     (unsigned long long)ws_bytes, (unsigned long long)need);
+    return XFDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6], const void *const e_n[3],
+                       double *grad)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
+    for (int c = 0; c < 6; ++c)
+        if (!lam_in[c] || !lam_out[c] || lam_in[c] == lam_out[c]) return fail(XFDTD_EINVAL, "bad lambda arrays");
+    for (int c = 0; c < 3; ++c)
+        if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
+    rc = ensure_adjoint_buffers(h);
+    if (rc) return rc;
+    if (h->dtype == XFDTD_F32) {
+        const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
+        return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad);
+    }
+    const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
+    return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad);
+}
+
+int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes)
+{
+    if (!h || !bytes) return fail(XFDTD_EINVAL, "null argument");
+    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+    seg = default_seg(n, seg);
+    *bytes = ws_arrays(n, seg) * field_bytes(h);
+    return XFDTD_OK;
+}
+
+int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes)
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    seg = default_seg(n, seg);
+    rc = check_ws(h, n, seg, ws, ws_bytes);
+    if (rc) return rc;
+    return h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
+                                 : grad_forward_t<double>(h, n, seg, (char *)ws);
+}
+
+int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes, void *const lam[6],
+                        double grad[12])
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!lam || !grad) return fail(XFDTD_EINVAL, "null argument");
+    for (int c = 0; c < 6; ++c)
+        if (!lam[c]) return fail(XFDTD_EINVAL, "lam[%d] is null", c);
+    seg = default_seg(n, seg);
+    rc = check_ws(h, n, seg, ws, ws_bytes);
+    if (rc) return rc;
+    return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
+                                 : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
 }
 
 }  // extern "C"

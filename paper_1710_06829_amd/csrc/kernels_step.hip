@@ -238,16 +238,18 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
         const bool doStar = k >= k0 - 1;
         __syncthreads();
 
-        // g(k+1) at this lane's column
+        // g(k+1) at this lane's column (lanes outside the g region read the
+        // neighbours of slot 0: in bounds, value unused)
         T gn[6];
         {
             const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
+            const int lg = isG ? li : 0;
             gn[0] = e2[1] - e1[1];          // g_z[Ey] -> Bx (+S_z)
-            gn[1] = Ez1[li + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
-            gn[2] = Ez1[li + 1] - e1[2];    // g_x[Ez] -> By (+S_x)
+            gn[1] = Ez1[lg + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
+            gn[2] = Ez1[lg + 1] - e1[2];    // g_x[Ez] -> By (+S_x)
             gn[3] = e2[0] - e1[0];          // g_z[Ex] -> By (-S_z)
-            gn[4] = Ex1[li + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
-            gn[5] = Ey1[li + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
+            gn[4] = Ex1[lg + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
+            gn[5] = Ey1[lg + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
         }
         if (isG) {
 #pragma unroll

@@ -43,6 +43,21 @@ template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
                         int tile_y, int zchunk, hipStream_t s);
 
+// Adjoint step (kernels_adjoint.hip): lin -> lout (distinct buffers), primal
+// E of the step in en[3]; per-workgroup unscaled gradient sums in partials
+// (adjoint_blocks(...) x 12 doubles).
+struct Scale12 {
+    double s[12];
+};
+int adjoint_blocks(Dims d, int tile_y, int zchunk);
+template <typename T>
+hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
+                          const Weights<T> &w, int tile_y, int zchunk, double *partials,
+                          hipStream_t s);
+// grad[j] += sc.s[j] * sum over blocks of partials[b*12 + j]
+hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
+                                  hipStream_t s);
+
 // Diagnostics (kernels_diag.hip).
 template <typename T>
 hipError_t launch_divergence(const Fields<T> &f, Dims d, const double coeffs[12],

@@ -133,6 +133,33 @@ class Solver:
         B.check(B.lib().xfdtd_get_weights(self._h, w, ctypes.byref(nw)))
         return [w[i] for i in range(nw.value)]
 
+    def adjoint_step(self, lam_in, lam_out, e_n, grad):
+        """One reverse step: lam_out = adjoint(lam_in) with primal input E ``e_n``;
+        adds this step's coefficient gradient to ``grad`` (float64 CUDA (12,))."""
+        self._bind()
+        li = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam_in])
+        lo = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam_out])
+        en = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in e_n])
+        B.check(B.lib().xfdtd_adjoint_step(self._h, li, lo, en, _ptr(grad)))
+
+    def grad_workspace_bytes(self, n, seg=0):
+        b = ctypes.c_uint64()
+        B.check(B.lib().xfdtd_grad_workspace(self._h, int(n), int(seg), ctypes.byref(b)))
+        return b.value
+
+    def grad_forward(self, n, ws, seg=0):
+        self._bind()
+        B.check(B.lib().xfdtd_grad_forward(self._h, int(n), int(seg), _ptr(ws), ws.numel()))
+
+    def grad_backward(self, n, ws, lam, seg=0):
+        """lam: six tensors, dL/d(final state) in, dL/d(initial state) out.
+        Returns dL/dcoeffs as 12 floats."""
+        self._bind()
+        arr = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam])
+        g = (ctypes.c_double * 12)()
+        B.check(B.lib().xfdtd_grad_backward(self._h, int(n), int(seg), _ptr(ws), ws.numel(), arr, g))
+        return [g[i] for i in range(12)]
+
     def divergence(self):
         """(D*.B, D.E) as new tensors of the field dtype."""
         self._bind()

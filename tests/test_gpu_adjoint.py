@@ -1,0 +1,159 @@
+"""GPU parity of the adjoint step, the checkpointed gradient schedule and the
+autograd wrapper against the oracle's scatter-form adjoint and finite
+differences."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from oracle import fdtd as O
+import paper_1710_06829_amd as pkg
+from tests import workloads as W
+from tests._gpu import DEV, max_rel, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _coeffs(seed):
+    beta, delta = S.distinct_beta_delta(seed)
+    return O.coeffs_from(beta, delta)
+
+
+@pytest.mark.parametrize("shape", [(20, 18, 70), (7, 9, 130), (5, 4, 3), (1, 3, 1), (3, 1, 66)])
+def test_adjoint_step_matches_oracle_fp64(shape):
+    c = _coeffs(601)
+    sp = (1.0, 0.8, 1.3)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    lam = S.uniform_fields(shape, 602)
+    En = S.uniform_fields(shape, 603)[:3]
+    exp, gexp = O.adjoint_step(lam, En, c, dt, sp)
+    li, lo, en = to_dev(lam), to_dev([np.zeros(shape)] * 6), to_dev(En)
+    grad = torch.zeros(12, dtype=torch.float64, device=DEV)
+    s = pkg.Solver(to_dev(S.uniform_fields(shape, 604)), dt, c, spacing=sp, scratch=False)
+    s.adjoint_step(li, lo, en, grad)
+    got = to_host(lo)
+    assert rel_l2(got, exp) < 1e-13
+    g = grad.cpu().numpy()
+    assert np.abs(g - gexp).max() <= 1e-12 * np.abs(gexp).max()
+
+
+def test_adjoint_dot_product_gpu_fp64():
+    shape = (16, 12, 80)
+    c = _coeffs(611)
+    dt = 0.95 * O.cfl_dt(c)
+    x = S.uniform_fields(shape, 612)
+    y = S.uniform_fields(shape, 613)
+    tx = to_dev(x)
+    pkg.Solver(tx, dt, c).run(1)          # fused path is odd-count: in-place pair
+    Mx = to_host(tx)
+    ly, lo = to_dev(y), to_dev([np.zeros(shape)] * 6)
+    grad = torch.zeros(12, dtype=torch.float64, device=DEV)
+    s = pkg.Solver(to_dev(x), dt, c, scratch=False)
+    s.adjoint_step(ly, lo, to_dev(x[:3]), grad)
+    MTy = to_host(lo)
+    lhs = sum(float(np.sum(a * b)) for a, b in zip(Mx, y))
+    rhs = sum(float(np.sum(a * b)) for a, b in zip(x, MTy))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def _probe_grad_out(xp, tgt):
+    def g(fN):
+        out = [np.zeros_like(f) for f in fN]
+        for a in range(3):
+            out[a][:, :, xp] = fN[a][:, :, xp] - tgt[a]
+        return out
+    return g
+
+
+@pytest.mark.parametrize("seg", [0, 1, 5, 13, 40])
+def test_grad_schedule_matches_oracle_fp64(seg):
+    shape = (12, 10, 70)
+    n = 13
+    c = _coeffs(621)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 622)
+    tgt = [S.uniform_fields(shape, 623)[a][:, :, 5] for a in range(3)]
+    fN, g0, gc = O.run_with_adjoint(f0, n, c, dt, sp, _probe_grad_out(5, tgt))
+    t = to_dev(f0)
+    s = pkg.Solver(t, dt, c, spacing=sp, scratch=False)
+    ws = torch.empty(s.grad_workspace_bytes(n, seg), dtype=torch.uint8, device=DEV)
+    s.grad_forward(n, ws, seg)
+    got = to_host(t)
+    assert rel_l2(got, fN) < 1e-13
+    lam = to_dev(_probe_grad_out(5, tgt)(got))
+    gcoef = s.grad_backward(n, ws, lam, seg)
+    assert rel_l2(to_host(lam), g0) < 1e-12
+    assert np.abs(np.asarray(gcoef) - gc).max() <= 1e-11 * np.abs(gc).max()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_grad_schedule_short_runs(n):
+    shape = (6, 5, 66)
+    c = _coeffs(631)
+    dt = 0.9 * O.cfl_dt(c)
+    f0 = S.uniform_fields(shape, 632)
+    lamN = S.uniform_fields(shape, 633)
+    fN, g0, gc = O.run_with_adjoint(f0, n, c, dt, (1, 1, 1), lambda f: lamN)
+    t = to_dev(f0)
+    s = pkg.Solver(t, dt, c, scratch=False)
+    ws = torch.empty(max(256, s.grad_workspace_bytes(n)), dtype=torch.uint8, device=DEV)
+    s.grad_forward(n, ws)
+    assert rel_l2(to_host(t), fN) < 1e-13
+    lam = to_dev(lamN)
+    gcoef = s.grad_backward(n, ws, lam)
+    assert rel_l2(to_host(lam), g0) < 1e-12
+    if n:
+        assert np.abs(np.asarray(gcoef) - gc).max() <= 1e-11 * np.abs(gc).max()
+    else:
+        assert np.all(np.asarray(gcoef) == 0)
+
+
+def test_autograd_propagate_fp64_24cube_pulse():
+    """The 24^3 copy of the differentiation workload against the oracle's
+    adjoint: gradients w.r.t. the 12 coefficients and the initial fields."""
+    shape, n = (24, 24, 24), 200
+    f0, c, dt, sp, xp, tgt = W.c4_inputs(shape, n, scale=24 / 128)
+    fN, g0, gc = O.run_with_adjoint(f0, n, c, dt, sp, _probe_grad_out(xp, tgt))
+    fields = [x.requires_grad_() for x in to_dev(f0)]
+    coeffs = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+    out = pkg.propagate(fields, coeffs, n, dt, sp)
+    tg = [torch.from_numpy(x).to(DEV) for x in tgt]
+    loss = 0.5 * sum(((out[a][:, :, xp] - tg[a]) ** 2).sum() for a in range(3))
+    loss.backward()
+    assert abs(loss.item() - W.probe_loss(fN, xp, tgt)) < 1e-12 * abs(loss.item())
+    gcoef = coeffs.grad.numpy()
+    assert np.abs(gcoef - gc).max() <= 1e-10 * np.abs(gc).max()
+    gf = to_host([f.grad for f in fields])
+    assert rel_l2(gf, g0) < 1e-11
+
+
+def test_c4_fp32_gradients_vs_fp64_finite_differences():
+    """128^3 FP32, 200 steps, sqrt(N) checkpoints: gradients w.r.t. the 12
+    coefficients and the initial E within 1e-4 of FP64 central differences
+    of the oracle (stored by tests/golden/make_c4_fd.py)."""
+    path = os.path.join(GOLD, "c4_fd.npz")
+    if not os.path.exists(path):
+        pytest.skip("c4_fd.npz not generated")
+    ref = np.load(path)
+    f0, c, dt, sp, xp, tgt = W.c4_inputs()
+    assert np.array_equal(ref["coeffs"], c) and ref["dt"] == dt
+    fields = [x.requires_grad_() for x in to_dev(f0, torch.float32)]
+    coeffs = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+    out = pkg.propagate(fields, coeffs, 200, dt, sp)
+    tg = [torch.from_numpy(x).to(device=DEV, dtype=torch.float32) for x in tgt]
+    loss = 0.5 * sum(((out[a][:, :, xp].double() - tg[a].double()) ** 2).sum() for a in range(3))
+    loss.backward()
+    g = coeffs.grad.numpy()
+    fd = ref["grad_coeffs"]
+    scale = np.abs(fd).max()
+    rel = np.abs(g - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+    assert rel.max() < 1e-4, (rel, g, fd)
+    u = [S.unit_vector(503 + a, f0[a].size).reshape(f0[a].shape) for a in range(3)]
+    gE = to_host([f.grad for f in fields[:3]])
+    dE = sum(float(np.sum(gE[a] * u[a])) for a in range(3))
+    assert abs(dE - float(ref["dir_e0"])) < 1e-4 * abs(float(ref["dir_e0"]))

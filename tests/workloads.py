@@ -20,3 +20,47 @@ def c2_inputs(shape=C2_SHAPE):
     f = S.gaussian_pulse(shape, dt, wavelength=16.0, waist=32.0, duration=40.0)
     f = S.add_noise(f, 1e-3, 202)
     return f, c, dt, sp
+
+
+def pulse_target_loss_setup(shape, steps, wavelength, waist, duration, x0, dt):
+    """Probe plane and target of the field-misfit loss.
+
+    The target is the initial continuum pulse rigidly translated by steps*dt
+    along x (the analytic vacuum pulse, c = 1), sampled at the E sites; the
+    probe plane is the y-z plane at x-index round(x0 + steps*dt) mod nx.
+    Returns (probe_index, [Ex*, Ey*, Ez*] on that plane, each (nz, ny)).
+    """
+    nz, ny, nx = shape
+    shift = x0 + steps * dt
+    xc = shift % nx
+    tgt = S.gaussian_pulse(shape, dt, wavelength=wavelength, waist=waist, duration=duration, x0=xc)
+    xp = int(round(shift)) % nx
+    return xp, [t[:, :, xp].copy() for t in tgt[:3]]
+
+
+def c4_inputs(shape=(128, 128, 128), steps=200, scale=1.0):
+    """128^3 box: extended set (seed 501), Gaussian pulse along x with
+    wavelength 12, waist 24, duration 30 cells (the 512x256x256 pulse scaled
+    to wavelength 12), x0 = nx/4, plus 1e-3 noise (seed 502); dt = 0.95 x
+    the stability bound.  ``scale`` shrinks waist and duration for smaller
+    copies of the box (the 24^3 copy uses waist 4.5, duration 7.5)."""
+    beta, delta = S.extended_beta_delta(501)
+    c = O.coeffs_from(beta, delta)
+    sp = (1.0, 1.0, 1.0)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    nz, ny, nx = shape
+    x0 = 0.25 * nx
+    lam, w0, dur = 12.0, 24.0 * scale, 30.0 * scale
+    if scale != 1.0:
+        w0, dur = 4.5, 7.5
+    f = S.gaussian_pulse(shape, dt, wavelength=lam, waist=w0, duration=dur, x0=x0)
+    f = S.add_noise(f, 1e-3, 502)
+    xp, tgt = pulse_target_loss_setup(shape, steps, lam, w0, dur, x0, dt)
+    return f, c, dt, sp, xp, tgt
+
+
+def probe_loss(fields, xp, tgt):
+    """L = 1/2 sum over the probe plane and the three E components of the
+    squared misfit (numpy)."""
+    import numpy as np
+    return 0.5 * sum(float(np.sum((fields[a][:, :, xp] - tgt[a]) ** 2)) for a in range(3))
