@@ -69,6 +69,81 @@ def cpu_baseline(f64_fields, coeffs, dt, steps):
     }
 
 
+def fwd_adj_ratio(steps=200):
+    """Time of the checkpointed forward + adjoint over the plain forward, on the
+    128^3 FP32 differentiation workload (Gaussian pulse, wavelength 12, probe
+    plane loss), sqrt(N) checkpoints."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    import paper_1710_06829_amd as pkg
+
+    shape = (128, 128, 128)
+    beta, delta = S.extended_beta_delta(501)
+    raw = [0.0] * 12
+    for a in range(3):
+        raw[4 * a + 1], raw[4 * a + 2], raw[4 * a + 3] = beta[a, 0], beta[a, 1], delta[a]
+    coeffs = pkg.consistent_alpha(raw)
+    dt = 0.95 * pkg.cfl_limit(shape, coeffs)[0]
+    f = S.add_noise(S.gaussian_pulse(shape, dt, 12.0, 24.0, 30.0), 1e-3, 502)
+    dev = torch.device("cuda:0")
+    f32 = [torch.from_numpy(np.ascontiguousarray(x)).to(device=dev, dtype=torch.float32) for x in f]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    plain = [x.clone() for x in f32]
+    sp = pkg.Solver(plain, dt, coeffs)
+    sp.run(10)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    sp.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1)
+
+    seg = int(math.ceil(math.sqrt(steps)))
+    work = [x.clone() for x in f32]
+    sg = pkg.Solver(work, dt, coeffs, scratch=False)
+    ws = torch.empty(sg.grad_workspace_bytes(steps, seg), dtype=torch.uint8, device=dev)
+    lam = [torch.zeros_like(x) for x in work]
+    xp = int(round(0.25 * shape[2] + steps * dt)) % shape[2]
+    times = []
+    for rep in range(2):
+        for a in range(6):
+            work[a].copy_(f32[a])
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        sg.grad_forward(steps, ws, seg)
+        for a in range(6):
+            lam[a].zero_()
+        for a in range(3):
+            lam[a][:, :, xp] = work[a][:, :, xp]
+        sg.grad_backward(steps, ws, lam, seg)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    t_fa = min(times)
+    return {"ratio": round(t_fa / t_fwd, 3), "fwd_ms": round(t_fwd, 3), "fwd_adj_ms": round(t_fa, 3),
+            "steps": steps, "segment": seg, "workload": "128^3 FP32 Gaussian pulse (wavelength 12), "
+            "probe-plane misfit loss, gradients w.r.t. 12 coefficients and initial fields"}
+
+
+def calib_copy(gib=1.0, reps=5):
+    """A plain device copy of known size (for scaling rocprofv3 byte counters)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return n * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +151,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-adj", action="store_true")
+    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -144,6 +221,10 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if not args.no_adj:
+        line["fwd_adj"] = fwd_adj_ratio()
+    if args.calib:
+        line["calib_copy_bytes"] = calib_copy()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f64, coeffs, dt, args.cpu_steps)
     print(json.dumps(line), flush=True)

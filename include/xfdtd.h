@@ -229,6 +229,42 @@ int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_
 int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes,
                         void *const lam[6], double grad[12]);
 
+/*
+ * Batches: m independent periodic boxes of any sizes, each with its own
+ * coefficients and time step (each box obeys the conventions above), advanced
+ * together.  A step is one launch of a persistent kernel over a work list of
+ * (box, tile) items; xfdtd_batch_run captures its n launches once into a HIP
+ * graph and replays it.  Not thread-safe per handle.
+ *
+ * xfdtd_batch_create: grids[m], dts[m], coeffs[m*12]; validated like
+ *     xfdtd_create (stability per box unless allow_unstable).
+ * xfdtd_batch_bind: fields[m*6] and scratch[m*6] (device, box-major, Ex..Bz
+ *     per box, handle dtype, 16-byte aligned, no overlaps); stream as in
+ *     xfdtd_bind.  Builds the work list (small internal device buffers).
+ * xfdtd_batch_tune: times a candidate set of launch configurations (tile
+ *     height 4/8, z-split 1/2/4, persistent grid of 1x/2x the CU count or one
+ *     workgroup per item) with steps that read the state and write only the
+ *     scratch arrays, keeps the fastest, and caches it per set of box shapes
+ *     (force = 1 re-times).  best_ms (nullable) receives the best time per
+ *     step (-1 when taken from the cache).  Synchronises the stream.
+ * xfdtd_batch_set_config / get_config: choose / report the configuration
+ *     (grid 0 = one workgroup per work item); nitems = work-list length.
+ * xfdtd_batch_run: n >= 0 steps of every box through the cached graph (the
+ *     graph is re-captured when n or the configuration changes); the result
+ *     is in the bound fields when the queued work completes.
+ * xfdtd_batch_run_eager: the same launches without a graph.
+ */
+typedef struct xfdtd_batch_s *xfdtd_batch_t;
+int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double *coeffs, int64_t m,
+                       int dtype, int allow_unstable, xfdtd_batch_t *out);
+void xfdtd_batch_destroy(xfdtd_batch_t b);
+int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch, void *stream);
+int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms);
+int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_y, int zsplit, int grid);
+int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_y, int *zsplit, int *grid, int *nitems);
+int xfdtd_batch_run(xfdtd_batch_t b, int64_t n);
+int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

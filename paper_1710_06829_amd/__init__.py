@@ -8,5 +8,6 @@ the built library raises ImportError (there is no CPU fallback).
 from ._binding import XfdtdError, lib  # noqa: F401
 from .solver import Solver, cfl_limit, consistent_alpha, dispersion  # noqa: F401
 from .autograd import propagate  # noqa: F401
+from .batch import Batch  # noqa: F401
 
-__all__ = ["Solver", "cfl_limit", "consistent_alpha", "dispersion", "propagate", "XfdtdError", "lib"]
+__all__ = ["Batch", "Solver", "cfl_limit", "consistent_alpha", "dispersion", "propagate", "XfdtdError", "lib"]

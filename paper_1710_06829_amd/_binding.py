@@ -55,6 +55,15 @@ SIGNATURES = {
     "xfdtd_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),
     "xfdtd_grad_forward": ([_vp, _i64, _i64, _vp, ctypes.c_uint64], _int),
     "xfdtd_grad_backward": ([_vp, _i64, _i64, _vp, ctypes.c_uint64, ctypes.POINTER(_vp), _dp], _int),
+    "xfdtd_batch_create": ([_GP, _dp, _dp, _i64, _int, _int, ctypes.POINTER(_vp)], _int),
+    "xfdtd_batch_destroy": ([_vp], None),
+    "xfdtd_batch_bind": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
+    "xfdtd_batch_tune": ([_vp, _int, _dp], _int),
+    "xfdtd_batch_set_config": ([_vp, _int, _int, _int], _int),
+    "xfdtd_batch_get_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                ctypes.POINTER(_int)], _int),
+    "xfdtd_batch_run": ([_vp, _i64], _int),
+    "xfdtd_batch_run_eager": ([_vp, _i64], _int),
 }
 
 

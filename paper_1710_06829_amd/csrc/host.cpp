@@ -32,6 +32,21 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+int xfdtd::set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what)
 {
     return fail(XFDTD_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -73,7 +88,9 @@ inline int t2_of(int a) { return a == 2 ? 1 : 2; }
 // points where the gradient vanishes within some face of the cube; every face
 // is one of 27 patterns (each u_a at 0, at 1, or free).  A face whose Hessian
 // is singular reaches its extremes on its own boundary, so it is skipped.
-void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi)
+}  // namespace
+
+void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double *out_hi)
 {
     double lin[3] = {0, 0, 0}, Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int a = 0; a < 3; ++a) {
@@ -159,6 +176,8 @@ void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi
     *out_hi = hi;
 }
 
+namespace {
+
 int pick_tile_y(int dtype) { return dtype == XFDTD_F64 ? 4 : 8; }
 
 int pick_zchunk(const xfdtd_grid &g, int tile_y)
@@ -209,23 +228,8 @@ namespace {
 template <typename T>
 Weights<T> fold(const xfdtd_s &h, double out[15])
 {
-    Weights<T> w;
     const double sp[3] = {h.g.dx, h.g.dy, h.g.dz};
-    for (int a = 0; a < 3; ++a) {
-        const double *c = h.coeffs + 4 * a;
-        const double s = h.dt / sp[a];
-        w.wc[a] = (T)(s * (c[0] + c[3]));
-        w.wd[a] = (T)(s * c[3]);
-        w.wb[a][0] = (T)(s * c[1]);
-        w.wb[a][1] = (T)(s * c[2]);
-        w.wa[a] = (T)s;
-        out[5 * a + 0] = (double)w.wc[a];
-        out[5 * a + 1] = (double)w.wd[a];
-        out[5 * a + 2] = (double)w.wb[a][0];
-        out[5 * a + 3] = (double)w.wb[a][1];
-        out[5 * a + 4] = (double)w.wa[a];
-    }
-    return w;
+    return fold_weights<T>(h.dt, h.coeffs, sp, out);
 }
 
 template <typename T>

@@ -43,6 +43,22 @@ template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
                         int tile_y, int zchunk, hipStream_t s);
 
+// One box of a batch: state f and scratch s (the step alternates between
+// them), its grid, weights and tiling (64 x tile_y x zchunk, ntx x nty tiles
+// per z-chunk).
+template <typename T>
+struct BoxDesc {
+    Fields<T> f, s;
+    Dims d;
+    Weights<T> w;
+    int zchunk, ntx, nty, pad;
+};
+// Batched fused step over a work list of (box, tile) pairs (device arrays).
+// grid: persistent workgroup count (<= 0: one per item).
+template <typename T>
+hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_y,
+                          int grid, hipStream_t s);
+
 // Adjoint step (kernels_adjoint.hip): lin -> lout (distinct buffers), primal
 // E of the step in en[3]; per-workgroup unscaled gradient sums in partials
 // (adjoint_blocks(...) x 12 doubles).
@@ -69,5 +85,35 @@ hipError_t launch_divergence_max(const Fields<T> &f, Dims d, const double coeffs
 hipError_t launch_dispersion(const double *k, int64_t n, double dt, const double coeffs[12],
                              const double sp[3], double *omega, double *vph, double *vg,
                              unsigned int *bad, hipStream_t s);
+
+// Host helpers shared by the single-box and batched front ends (host.cpp).
+// F_min, F_max of the dispersion right-hand side over the whole zone.
+void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi);
+// Fold dt*coef/d_a into the star weights, computed in double and rounded
+// once to T; out15 receives the T values as doubles (xfdtd_get_weights order).
+template <typename T>
+Weights<T> fold_weights(double dt, const double *coeffs, const double sp[3], double out15[15])
+{
+    Weights<T> w;
+    for (int a = 0; a < 3; ++a) {
+        const double *c = coeffs + 4 * a;
+        const double s = dt / sp[a];
+        w.wc[a] = (T)(s * (c[0] + c[3]));
+        w.wd[a] = (T)(s * c[3]);
+        w.wb[a][0] = (T)(s * c[1]);
+        w.wb[a][1] = (T)(s * c[2]);
+        w.wa[a] = (T)s;
+        if (out15) {
+            out15[5 * a + 0] = (double)w.wc[a];
+            out15[5 * a + 1] = (double)w.wd[a];
+            out15[5 * a + 2] = (double)w.wb[a][0];
+            out15[5 * a + 3] = (double)w.wb[a][1];
+            out15[5 * a + 4] = (double)w.wa[a];
+        }
+    }
+    return w;
+}
+// Record an error message (thread-local) and return code.
+int set_error(int code, const char *fmt, ...);
 
 }  // namespace xfdtd

@@ -1,0 +1,87 @@
+"""Parity at the full 512x256x256 size, in the launch configuration the
+benchmark times (fused kernel, default tiles and z-chunks):
+
+* 1000 steps of the Gaussian-pulse workload against sampled outputs of the
+  FP64 oracle (stored by tests/golden/make_c2_samples.py): FP64 to 1e-12,
+  FP32 to 1e-5 relative L2 (FP32 convention of tests/_fp32.py);
+* 3 steps, full field, against the C oracle;
+* 1000 steps of an exact discrete eigenmode against its closed form.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import fdtd as O
+import paper_1710_06829_amd as pkg
+from tests import _fp32
+from tests import workloads as W
+from tests._gpu import DEV, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _sampled(tensors, idx):
+    torch.cuda.synchronize()
+    ii = torch.from_numpy(idx).to(DEV)
+    return np.stack([t.reshape(-1)[ii].double().cpu().numpy() for t in tensors], axis=1)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dtype,variant,tol", [(torch.float64, "exact", 1e-12),
+                                               (torch.float32, "fp32", 1e-5)])
+def test_c2_pulse_1000_steps_vs_oracle_samples(dtype, variant, tol):
+    path = os.path.join(GOLD, f"c2_pulse_{variant}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    ref = np.load(path)
+    f0, c, dt, sp = W.c2_inputs()
+    assert np.array_equal(ref["coeffs"], c) and float(ref["dt"]) == dt
+    t = to_dev(f0, dtype)
+    del f0
+    s = pkg.Solver(t, dt, c, spacing=sp)
+    s.run(int(ref["steps"]))
+    got = _sampled(t, ref["idx"])
+    err = _rel(got, ref["vals"])
+    print(f"c2 {variant}: sampled rel L2 = {err:.3e}")
+    assert err < tol
+
+
+def test_c2_three_steps_full_field_fp32():
+    f0, c, dt, sp = W.c2_inputs()
+    t = to_dev(f0, torch.float32)
+    pkg.Solver(t, dt, c, spacing=sp).run(3)
+    got = to_host(t)
+    ce, spe = _fp32.effective(c, dt, sp)
+    exp = oracle.c_run(_fp32.round_fields(f0), 3, ce, dt, spe)
+    err = rel_l2(got, exp)
+    print(f"c2 3 steps fp32 full field rel L2 = {err:.3e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+def test_c2_eigenmode_1000_steps(dtype, tol):
+    shape = W.C2_SHAPE
+    f0_, c, dt, sp = W.c2_inputs((4, 4, 4))  # coefficients and dt of the workload
+    if dtype == torch.float32:
+        ce, spe = _fp32.effective(c, dt, sp)
+    else:
+        ce, spe = c, sp
+    modes = (32, 5, 3)  # wavelength 16 cells along x, oblique
+    f0, *_ = O.plane_wave(shape, modes, dt, ce, spe)
+    if dtype == torch.float32:
+        f0 = _fp32.round_fields(f0)
+    t = to_dev(f0, dtype)
+    del f0
+    pkg.Solver(t, dt, c, spacing=sp).run(1000)
+    exp = O.plane_wave_at(shape, modes, dt, ce, 1000, spe)
+    got = to_host(t)
+    err = rel_l2(got, exp)
+    print(f"eigenmode {dtype}: rel L2 = {err:.3e}")
+    assert err < tol

@@ -64,3 +64,17 @@ def probe_loss(fields, xp, tgt):
     squared misfit (numpy)."""
     import numpy as np
     return 0.5 * sum(float(np.sum((fields[a][:, :, xp] - tgt[a]) ** 2)) for a in range(3))
+
+
+def c3_boxes(count=64):
+    """64 boxes with edges iid in {32, 48, 64, 96, 128} (seed 301); box b has
+    its own extended set (seed 302 + b), U(-1, 1) fields (seed 400 + b) and
+    dt = 0.95 x its stability bound.  Returns [(shape, fields, coeffs, dt)]."""
+    out = []
+    for b, (nx, ny, nz) in enumerate(S.box_edges(count, 301)):
+        beta, delta = S.extended_beta_delta(302 + b)
+        c = O.coeffs_from(beta, delta)
+        dt = 0.95 * O.cfl_dt(c)
+        shape = (nz, ny, nx)
+        out.append((shape, S.uniform_fields(shape, 400 + b), c, dt))
+    return out
