@@ -559,15 +559,21 @@ Scale12 grad_scale(const xfdtd_s *h)
     return sc;
 }
 
+// One adjoint launch.  accumulate = 0 overwrites the per-workgroup gradient
+// sums, 1 adds to them; reduce != 0 then adds their scaled total to grad.
 template <typename T>
-int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], double *grad)
+int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], double *grad,
+                int accumulate, int reduce)
 {
     const Dims d = dims_of(h->g);
     const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
     const int ty = adjoint_tile_y(h);
-    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->zchunk, h->apartials, h->stream), "adjoint launch");
-    HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->zchunk), grad_scale(h), grad, h->stream),
-            "reduce launch");
+    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->zchunk, h->apartials, accumulate, h->stream),
+            "adjoint launch");
+    if (reduce)
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->zchunk), grad_scale(h), grad,
+                                       h->stream),
+                "reduce launch");
     return XFDTD_OK;
 }
 
@@ -654,6 +660,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
         return f;
     };
     Fields<T> lcur = lamU, lnext = lamS;
+    bool first = true;
     for (int64_t m = nck - 1; m >= 0 && n > 0; --m) {
         const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
         Fields<T> ck = state_at<T>(ws, fb, 6 * m);
@@ -676,13 +683,19 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
                 Fields<T> e = segE(s - s0);
                 for (int c = 0; c < 3; ++c) en[c] = e.c[c];
             }
-            rc = adjoint_one<T>(h, lcur, lnext, en, h->grad_acc);
+            // the workgroup sums accumulate over all steps; one reduction at the end
+            rc = adjoint_one<T>(h, lcur, lnext, en, h->grad_acc, first ? 0 : 1, 0);
             if (rc) return rc;
+            first = false;
             Fields<T> t = lcur;
             lcur = lnext;
             lnext = t;
         }
     }
+    if (!first)
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, adjoint_tile_y(h), h->zchunk), grad_scale(h),
+                                       h->grad_acc, h->stream),
+                "reduce launch");
     if (lcur.c[0] != lamU.c[0])
         for (int c = 0; c < 6; ++c)
             HIP_TRY(hipMemcpyAsync(lamU.c[c], lcur.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
@@ -720,10 +733,10 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
     if (rc) return rc;
     if (h->dtype == XFDTD_F32) {
         const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
-        return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad);
+        return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1);
     }
     const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
-    return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad);
+    return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
 }
 
 int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes)

@@ -16,8 +16,9 @@
 // those the stars use, so the gradient costs a few FMAs per cell.
 //
 // The kernel mirrors fused_step_kernel: a workgroup owns a 64 x TY tile,
-// marches a chunk of z-planes, stages lE, mu, the stars and the primal E in
-// LDS for x/y neighbours and keeps z-neighbours in registers.  HBM traffic
+// marches a chunk of z-planes, stages lE', mu and the stars in LDS for x/y
+// neighbours and keeps z-neighbours in registers; the primal E neighbours
+// that the gradient needs (x+1, y+1) are re-read through L1/L2.  HBM traffic
 // per cell: read lE', lB', E (9 values), write lE, lB (6 values).
 // Per-workgroup gradient sums (unscaled, FP64) go to `partials`.
 
@@ -42,19 +43,22 @@ __device__ __forceinline__ void nt_store_a(T *p, T v)
 constexpr int ATILE_X = 64;
 
 // gradient slots: the 12-coefficient order (alpha, beta_t1, beta_t2, delta per axis)
+// One workgroup barrier per plane: iteration k forms mu(k+1) and the stars of
+// plane k, and outputs plane k-1 (whose stars' neighbours were written in
+// iteration k-1).  accumulate != 0 adds this step's sums to `partials`
+// (each workgroup owns its 12 slots), else overwrites them.
 template <typename T, int TY>
 __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
     Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
     const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
-    double *__restrict__ partials)
+    double *__restrict__ partials, int accumulate)
 {
     constexpr int PX = ATILE_X + 4;
     constexpr int PY = TY + 4;
     constexpr int P = PX * PY;
     __shared__ T LEbuf[2][3][P];  // lE'(k+1), lE'(k+2)
     __shared__ T Mbuf[2][3][P];   // mu(k), mu(k+1)
-    __shared__ T Sbuf[6][P];      // stars of mu at plane k
-    __shared__ T Nbuf[2][3][P];   // primal E(k), E(k+1)
+    __shared__ T Sbuf[2][6][P];   // stars of mu at planes k-1, k
     __shared__ double red[12][TY + 5];
 
     const int nb = gridDim.x, bid = blockIdx.x;
@@ -85,82 +89,98 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
     const bool isG = valid && rx < TXe + 1 && ry < TYe + 1;                   // forms mu
     const bool isB = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;   // stars
     const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;     // outputs
-    const bool isN = valid && rx >= 0 && rx <= TXe && ry >= 0 && ry <= TYe;   // primal E
 
     const int li = valid ? (ry + 2) * PX + (rx + 2) : 0;
     const int64_t nxy = (int64_t)d.nx * d.ny;
-    const int col = valid ? wrapa(y0 + ry, d.ny) * d.nx + wrapa(x0 + rx, d.nx) : 0;
+    const int gyc = valid ? wrapa(y0 + ry, d.ny) : 0, gxc = valid ? wrapa(x0 + rx, d.nx) : 0;
+    const int col = gyc * d.nx + gxc;
+    // the primal E neighbours the gradient needs (x+1 and y+1 columns)
+    const int colx1 = isO ? gyc * d.nx + wrapa(x0 + rx + 1, d.nx) : 0;
+    const int coly1 = isO ? wrapa(y0 + ry + 1, d.ny) * d.nx + gxc : 0;
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
     const T *en[3] = {en_x, en_y, en_z};
 
-    T le0[3], le1[3], epf[3], bpf[3], npf[3], n0[3];
-    T mm[3], mc[3], sprev0 = T(0), sprev3 = T(0);
+    // own-column queues: la = lE'(k-1), l0 = lE'(k), l1 = lE'(k+1);
+    // mm, mc = mu(k-1), mu(k); sp0/sp3 and sq0/sq3 = stars 0 and 3 at k-1 and
+    // k-2; n0 = E(k), nn = E(k) neighbours (x+1: Ez, Ey; y+1: Ez, Ex)
+    T la[3], l0[3], l1[3], epf[3], bpf[3], npf[3], nnpf[4], n0[3], nn[4];
+    T mm[3], mc[3], sp0 = T(0), sp3 = T(0), sq0 = T(0), sq3 = T(0);
     double acc[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) acc[j] = 0.0;
-    int eb = 0, mb = 0, nbf = 0;
+    int eb = 0, mb = 0, sb = 0;
 
-    // plane trackers: lE' prefetch at k+3, lB' prefetch at k+2, primal E
-    // prefetch at k+2, outputs at k; k starts at k0 - 3
-    int w3 = wrapa(k0, nz), wb = wrapa(k0 - 2, nz), wn = wrapa(k0 - 2, nz), w0 = wrapa(k0 - 3, nz);
+    // plane trackers (k starts at k0 - 3): w3 = k+3 (lE' prefetch),
+    // wb = k+1 -> k+2 (lB' prefetch), wn = k+1 -> k+2 (primal E prefetch:
+    // neighbours of plane k+1, own value of plane k+2), wm = k-1 (outputs)
+    int w3 = wrapa(k0, nz), wb = wrapa(k0 - 2, nz), wn = wrapa(k0 - 2, nz), wm = wrapa(k0 - 4, nz);
     {
         const int64_t pa = (int64_t)wrapa(k0 - 2, nz) * nxy, pb = (int64_t)wrapa(k0 - 1, nz) * nxy;
+        const int64_t pn = (int64_t)wrapa(k0 - 3, nz) * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            le1[c] = lin.c[c][pa + col];
+            l1[c] = lin.c[c][pa + col];
             epf[c] = lin.c[c][pb + col];
             bpf[c] = lin.c[3 + c][pa + col];
             npf[c] = en[c][pa + col];
+            n0[c] = en[c][pn + col];
         }
+        nnpf[0] = en_z[pn + colx1];
+        nnpf[1] = en_y[pn + colx1];
+        nnpf[2] = en_z[pn + coly1];
+        nnpf[3] = en_x[pn + coly1];
         if (isE) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) LEbuf[0][c][li] = le1[c];
+            for (int c = 0; c < 3; ++c) LEbuf[0][c][li] = l1[c];
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mm[c] = mc[c] = le0[c] = n0[c] = T(0);
+    for (int c = 0; c < 3; ++c) la[c] = l0[c] = mm[c] = mc[c] = T(0);
+    __syncthreads();
 
     const int klast = k0 + KZe - 1;
-    for (int k = k0 - 3; k <= klast; ++k) {
-        T e2[3], bo[3], n1[3];
+    for (int k = k0 - 3; k <= klast + 1; ++k) {
+        T l2[3], bo[3], n1[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            e2[c] = epf[c];  // lE'(k+2)
+            l2[c] = epf[c];  // lE'(k+2)
             bo[c] = bpf[c];  // lB'(k+1)
             n1[c] = npf[c];  // E(k+1)
         }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) nn[m] = nnpf[m];  // E(k) neighbours
         {
             const int64_t p3 = (int64_t)w3 * nxy;
+            const int64_t pn1 = (int64_t)wn * nxy;  // wn = k+1: neighbours of E(k+1)
             wb = inc(wb);
             wn = inc(wn);
-            const int64_t pb = (int64_t)wb * nxy, pn = (int64_t)wn * nxy;
+            const int64_t pb = (int64_t)wb * nxy, pn2 = (int64_t)wn * nxy;  // k+2: own E
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 epf[c] = lin.c[c][p3 + col];
                 bpf[c] = lin.c[3 + c][pb + col];
-                npf[c] = en[c][pn + col];
+                npf[c] = en[c][pn2 + col];
             }
+            nnpf[0] = en_z[pn1 + colx1];
+            nnpf[1] = en_y[pn1 + colx1];
+            nnpf[2] = en_z[pn1 + coly1];
+            nnpf[3] = en_x[pn1 + coly1];
         }
         if (isE) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) LEbuf[eb ^ 1][c][li] = e2[c];
-        }
-        __syncthreads();
-        if (isN) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Nbuf[nbf ^ 1][c][li] = n1[c];
+            for (int c = 0; c < 3; ++c) LEbuf[eb ^ 1][c][li] = l2[c];
         }
 
-        // mu(k+1) = lB'(k+1) + L^T lE' at this lane's column (lanes outside
-        // the mu region read neighbours of slot 0: in bounds, value unused)
+        // mu(k+1) = lB'(k+1) + L^T lE' (lanes outside the mu region read the
+        // neighbours of slot 0: in bounds, value unused)
         T mn[3];
         {
             const int lg = isG ? li : 0;
             const T *Lx = LEbuf[eb][0], *Ly = LEbuf[eb][1], *Lz = LEbuf[eb][2];
-            const T fzy = e2[1] - le1[1], fzx = e2[0] - le1[0];
-            const T fyz = Lz[lg + PX] - le1[2], fyx = Lx[lg + PX] - le1[0];
-            const T fxz = Lz[lg + 1] - le1[2], fxy = Ly[lg + 1] - le1[1];
+            const T fzy = l2[1] - l1[1], fzx = l2[0] - l1[0];
+            const T fyz = Lz[lg + PX] - l1[2], fyx = Lx[lg + PX] - l1[0];
+            const T fxz = Lz[lg + 1] - l1[2], fxy = Ly[lg + 1] - l1[1];
             mn[0] = bo[0] + (w.wa[1] * fyz - w.wa[2] * fzy);
             mn[1] = bo[1] + (w.wa[2] * fzx - w.wa[0] * fxz);
             mn[2] = bo[2] + (w.wa[0] * fxy - w.wa[1] * fyx);
@@ -170,10 +190,10 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
             for (int c = 0; c < 3; ++c) Mbuf[mb ^ 1][c][li] = mn[c];
         }
 
-        const bool doStar = k >= k0 - 1;
+        // stars of mu at plane k
         T s[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        T px[3], py[3], pz[3];
-        if (isB && doStar) {
+        T px[3] = {T(0), T(0), T(0)}, py[3] = {T(0), T(0), T(0)}, pz[3] = {T(0), T(0), T(0)};
+        if (isB && k >= k0 - 1 && k <= klast) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T *M = Mbuf[mb][c];
@@ -181,7 +201,6 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
                 py[c] = M[li + PX] + M[li - PX];
                 pz[c] = mn[c] + mm[c];
             }
-            // stars (centre, along-axis pair, t1 pair, t2 pair)
             s[0] = w.wc[2] * mc[0] + w.wd[2] * pz[0] + w.wb[2][0] * px[0] + w.wb[2][1] * py[0];  // S_z mu_x
             s[1] = w.wc[1] * mc[0] + w.wd[1] * py[0] + w.wb[1][0] * px[0] + w.wb[1][1] * pz[0];  // S_y mu_x
             s[2] = w.wc[0] * mc[1] + w.wd[0] * px[1] + w.wb[0][0] * py[1] + w.wb[0][1] * pz[1];  // S_x mu_y
@@ -189,59 +208,63 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
             s[4] = w.wc[1] * mc[2] + w.wd[1] * py[2] + w.wb[1][0] * px[2] + w.wb[1][1] * pz[2];  // S_y mu_z
             s[5] = w.wc[0] * mc[2] + w.wd[0] * px[2] + w.wb[0][0] * py[2] + w.wb[0][1] * pz[2];  // S_x mu_z
 #pragma unroll
-            for (int m = 0; m < 6; ++m) Sbuf[m][li] = s[m];
+            for (int m = 0; m < 6; ++m) Sbuf[sb][m][li] = s[m];
+            if (isO && k >= k0) {
+                // coefficient gradient at plane k: forward differences of E(k)
+                const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
+                const T gxEz = nn[0] - n0[2], gxEy = nn[1] - n0[1];
+                const T gyEz = nn[2] - n0[2], gyEx = nn[3] - n0[0];
+                // axis x (slots 0..3): +g_x[Ez] with mu_y, -g_x[Ey] with mu_z
+                acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
+                acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
+                acc[2] += (double)(gxEz * pz[1] - gxEy * pz[2]);
+                acc[3] += (double)(gxEz * (mc[1] + px[1]) - gxEy * (mc[2] + px[2]));
+                // axis y (slots 4..7): -g_y[Ez] with mu_x, +g_y[Ex] with mu_z
+                acc[4] += (double)(gyEx * mc[2] - gyEz * mc[0]);
+                acc[5] += (double)(gyEx * px[2] - gyEz * px[0]);
+                acc[6] += (double)(gyEx * pz[2] - gyEz * pz[0]);
+                acc[7] += (double)(gyEx * (mc[2] + py[2]) - gyEz * (mc[0] + py[0]));
+                // axis z (slots 8..11): +g_z[Ey] with mu_x, -g_z[Ex] with mu_y
+                acc[8] += (double)(gzEy * mc[0] - gzEx * mc[1]);
+                acc[9] += (double)(gzEy * px[0] - gzEx * px[1]);
+                acc[10] += (double)(gzEy * py[0] - gzEx * py[1]);
+                acc[11] += (double)(gzEy * (mc[0] + pz[0]) - gzEx * (mc[1] + pz[1]));
+            }
         }
-        __syncthreads();
 
-        if (isO && k >= k0) {
-            const int64_t po = (int64_t)w0 * nxy + col;
-            // lE = lE' + K^T mu (backward differences of the stars)
-            const T lx = le0[0] + ((s[3] - sprev3) - (s[4] - Sbuf[4][li - PX]));
-            const T ly = le0[1] + ((s[5] - Sbuf[5][li - 1]) - (s[0] - sprev0));
-            const T lz = le0[2] + ((s[1] - Sbuf[1][li - PX]) - (s[2] - Sbuf[2][li - 1]));
+        // outputs of plane k-1: lE = lE' + backward differences of its stars
+        if (isO && k - 1 >= k0) {
+            const T(*Sp)[P] = Sbuf[sb ^ 1];
+            const int64_t po = (int64_t)wm * nxy + col;
+            const T lx = la[0] + ((sp3 - sq3) - (Sp[4][li] - Sp[4][li - PX]));
+            const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (sp0 - sq0));
+            const T lz = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
             nt_store_a(lout.c[0] + po, lx);
             nt_store_a(lout.c[1] + po, ly);
             nt_store_a(lout.c[2] + po, lz);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) nt_store_a(lout.c[3 + c] + po, mc[c]);
-
-            // coefficient gradient: forward differences of the primal E(k)
-            const T *Nx = Nbuf[nbf][0], *Ny = Nbuf[nbf][1], *Nz = Nbuf[nbf][2];
-            const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
-            const T gyEz = Nz[li + PX] - n0[2], gyEx = Nx[li + PX] - n0[0];
-            const T gxEz = Nz[li + 1] - n0[2], gxEy = Ny[li + 1] - n0[1];
-            // axis x (slots 0..3): +g_x[Ez] with mu_y, -g_x[Ey] with mu_z
-            acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
-            acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
-            acc[2] += (double)(gxEz * pz[1] - gxEy * pz[2]);
-            acc[3] += (double)(gxEz * (mc[1] + px[1]) - gxEy * (mc[2] + px[2]));
-            // axis y (slots 4..7): -g_y[Ez] with mu_x, +g_y[Ex] with mu_z
-            acc[4] += (double)(gyEx * mc[2] - gyEz * mc[0]);
-            acc[5] += (double)(gyEx * px[2] - gyEz * px[0]);
-            acc[6] += (double)(gyEx * pz[2] - gyEz * pz[0]);
-            acc[7] += (double)(gyEx * (mc[2] + py[2]) - gyEz * (mc[0] + py[0]));
-            // axis z (slots 8..11): +g_z[Ey] with mu_x, -g_z[Ex] with mu_y
-            acc[8] += (double)(gzEy * mc[0] - gzEx * mc[1]);
-            acc[9] += (double)(gzEy * px[0] - gzEx * px[1]);
-            acc[10] += (double)(gzEy * py[0] - gzEx * py[1]);
-            acc[11] += (double)(gzEy * (mc[0] + pz[0]) - gzEx * (mc[1] + pz[1]));
+            for (int c = 0; c < 3; ++c) nt_store_a(lout.c[3 + c] + po, mm[c]);
         }
+        __syncthreads();
 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            le0[c] = le1[c];
-            le1[c] = e2[c];
+            la[c] = l0[c];
+            l0[c] = l1[c];
+            l1[c] = l2[c];
             mm[c] = mc[c];
             mc[c] = mn[c];
             n0[c] = n1[c];
         }
-        sprev0 = s[0];
-        sprev3 = s[3];
+        sq0 = sp0;
+        sq3 = sp3;
+        sp0 = s[0];
+        sp3 = s[3];
         eb ^= 1;
         mb ^= 1;
-        nbf ^= 1;
+        sb ^= 1;
         w3 = inc(w3);
-        w0 = inc(w0);
+        wm = inc(wm);
     }
 
     // workgroup reduction of the 12 gradient sums (FP64)
@@ -255,7 +278,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
     if (threadIdx.x < 12) {
         double v = 0.0;
         for (int wv = 0; wv < TY + 5; ++wv) v += red[threadIdx.x][wv];
-        partials[(int64_t)blockIdx.x * 12 + threadIdx.x] = v;
+        double *slot = partials + (int64_t)blockIdx.x * 12 + threadIdx.x;
+        *slot = accumulate ? *slot + v : v;
     }
 }
 
@@ -291,7 +315,7 @@ int adjoint_blocks(Dims d, int tile_y, int zchunk)
 
 template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
-                          const Weights<T> &w, int tile_y, int zchunk, double *partials,
+                          const Weights<T> &w, int tile_y, int zchunk, double *partials, int accumulate,
                           hipStream_t s)
 {
     const int ntx = (d.nx + ATILE_X - 1) / ATILE_X;
@@ -300,11 +324,11 @@ hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *
     switch (tile_y) {
     case 4:
         hipLaunchKernelGGL((adjoint_step_kernel<T, 4>), dim3(nb), dim3(64 * 9), 0, s, lin, lout, en[0],
-                           en[1], en[2], d, w, zchunk, ntx, nty, partials);
+                           en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
         break;
     case 8:
         hipLaunchKernelGGL((adjoint_step_kernel<T, 8>), dim3(nb), dim3(64 * 13), 0, s, lin, lout, en[0],
-                           en[1], en[2], d, w, zchunk, ntx, nty, partials);
+                           en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
         break;
     default:
         return hipErrorInvalidValue;
@@ -320,9 +344,9 @@ hipError_t launch_reduce_partials(const double *partials, int nblocks, const Sca
 }
 
 template hipError_t launch_adjoint<float>(const Fields<float> &, const Fields<float> &, const float *const[3],
-                                          Dims, const Weights<float> &, int, int, double *, hipStream_t);
+                                          Dims, const Weights<float> &, int, int, double *, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const Fields<double> &, const Fields<double> &,
                                            const double *const[3], Dims, const Weights<double> &, int, int,
-                                           double *, hipStream_t);
+                                           double *, int, hipStream_t);
 
 }  // namespace xfdtd

@@ -18,7 +18,8 @@
 //       a 1-cell halo on the low x and y sides (redundantly with the
 //       neighbouring tile), and then E^{n+1} on the tile.  Values a lane needs
 //       along z (g at k-1, k, k+1; E at k, k+1, k+2; B^{n+1/2} at k-1) are kept
-//       in registers, so z-neighbours never touch LDS.  Each of the 12 field
+//       in registers, so z-neighbours never touch LDS.  One barrier per plane
+//       (the Ampere update lags one plane).  Each of the 12 field
 //       values per cell is read and written once from HBM (halo re-reads hit
 //       L2): 48 B (FP32) / 96 B (FP64) per cell-update.
 
@@ -131,206 +132,11 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
 // ---------------------------------------------------------------------------
 constexpr int TILE_X = 64;
 
-// LDS of one workgroup of the fused step
+// LDS of one workgroup of the fused step.  B^{n+1/2} is double-buffered so
+// that the Ampere update can lag one plane behind and read the previous
+// plane's B after the single barrier per plane.
 template <typename T, int TY>
 struct FusedSmem {
-    static constexpr int PX = TILE_X + 4;  // row pitch: x in [-2, 66)
-    static constexpr int PY = TY + 4;      // rows y in [-2, TY + 2)
-    static constexpr int P = PX * PY;
-    T Ebuf[2][3][P];  // E(k+1), E(k+2)
-    T Gbuf[2][6][P];  // g(k), g(k+1)
-    T Bbuf[3][P];     // B^{n+1/2}(k)
-};
-
-// One tile of the fused step: tile number `logical` of a box tiled as
-// ntx x nty x (z-chunks), x fastest.  All threads of the workgroup call it.
-template <typename T, int TY>
-__device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
-                                           const Weights<T> &w, int zchunk, int ntx, int nty,
-                                           int logical, FusedSmem<T, TY> &sm)
-{
-    constexpr int PX = FusedSmem<T, TY>::PX;
-    constexpr int PY = FusedSmem<T, TY>::PY;
-    constexpr int P = FusedSmem<T, TY>::P;
-    auto &Ebuf = sm.Ebuf;
-    auto &Gbuf = sm.Gbuf;
-    auto &Bbuf = sm.Bbuf;
-    const int tx = logical % ntx;
-    const int rest = logical / ntx;
-    const int ty = rest % nty;
-    const int zc = rest / nty;
-    const int x0 = tx * TILE_X, y0 = ty * TY, k0 = zc * zchunk;
-    const int TXe = min(TILE_X, d.nx - x0), TYe = min(TY, d.ny - y0);
-    const int KZe = min(zchunk, d.nz - k0);
-
-    // Lane roles.  Waves 0..TY+3 own the rows y = -2..TY+1 of the tile
-    // (lane = x); the last wave owns the four halo columns
-    // x = -2, -1, TXe, TXe+1 over the same rows.
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int rx = 0, ry = 0;
-    bool valid;
-    if (wave < TY + 4) {
-        ry = wave - 2;
-        rx = lane;
-        valid = rx < TXe && ry < TYe + 2;
-    } else {
-        const int sel = lane / PY;
-        ry = lane % PY - 2;
-        rx = sel == 0 ? -2 : sel == 1 ? -1 : sel == 2 ? TXe : TXe + 1;
-        valid = sel < 4 && ry < TYe + 2;
-    }
-    const bool isE = valid;                                     // loads E
-    const bool isG = valid && rx < TXe + 1 && ry < TYe + 1;     // forms g
-    const bool isB = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;  // B^{n+1/2}
-    const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;    // outputs
-
-    const int li = valid ? (ry + 2) * PX + (rx + 2) : 0;
-    const int64_t nxy = (int64_t)d.nx * d.ny;
-    // column offset of this lane; idle lanes use column 0 so that every lane
-    // can load unconditionally (in bounds, value unused)
-    const int col = valid ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
-    const int nz = d.nz;
-    auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
-
-    T e0[3], e1[3], epf[3], bpf[3], gm[6], gc[6], bprev[2];
-    int eb = 0, gb = 0;
-
-    // wrapped plane indices (uniform): k+3 for the E prefetch, k+1 for the B
-    // prefetch, k for the outputs; k starts at k0 - 3
-    int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), w0 = wrap(k0 - 3, nz);
-
-    // prologue: E(k0-2) into registers and LDS, prefetch E(k0-1), B(k0-3)
-    {
-        const int64_t pa = (int64_t)wrap(k0 - 2, nz) * nxy, pb = (int64_t)wrap(k0 - 1, nz) * nxy;
-        const int64_t pc = (int64_t)w1 * nxy;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            e1[c] = in.c[c][pa + col];
-            epf[c] = in.c[c][pb + col];
-            bpf[c] = in.c[3 + c][pc + col];
-        }
-        if (isE) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Ebuf[0][c][li] = e1[c];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 6; ++m) gm[m] = gc[m] = T(0);
-    e0[0] = e0[1] = e0[2] = T(0);
-    bprev[0] = bprev[1] = T(0);
-
-    const int klast = k0 + KZe - 1;
-    for (int k = k0 - 3; k <= klast; ++k) {
-        // consume the prefetched E(k+2) and B(k+1 of the previous round = k),
-        // then issue the next prefetch unconditionally
-        T e2[3], bo[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            e2[c] = epf[c];
-            bo[c] = bpf[c];
-        }
-        {
-            const T *const *src = in.c;
-            const int64_t p3 = (int64_t)w3 * nxy;
-            w1 = inc(w1);
-            const int64_t p1 = (int64_t)w1 * nxy;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                epf[c] = src[c][p3 + col];
-                bpf[c] = src[3 + c][p1 + col];
-            }
-        }
-        if (isE) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Ebuf[eb ^ 1][c][li] = e2[c];
-        }
-        const bool doStar = k >= k0 - 1;
-        __syncthreads();
-
-        // g(k+1) at this lane's column (lanes outside the g region read the
-        // neighbours of slot 0: in bounds, value unused)
-        T gn[6];
-        {
-            const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
-            const int lg = isG ? li : 0;
-            gn[0] = e2[1] - e1[1];          // g_z[Ey] -> Bx (+S_z)
-            gn[1] = Ez1[lg + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
-            gn[2] = Ez1[lg + 1] - e1[2];    // g_x[Ez] -> By (+S_x)
-            gn[3] = e2[0] - e1[0];          // g_z[Ex] -> By (-S_z)
-            gn[4] = Ex1[lg + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
-            gn[5] = Ey1[lg + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
-        }
-        if (isG) {
-#pragma unroll
-            for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li] = gn[m];
-        }
-
-        // B^{n+1/2}(k): stars of g(k); z-neighbours from registers
-        T bn[3] = {T(0), T(0), T(0)};
-        if (isB && doStar) {
-            const T(*G)[P] = Gbuf[gb];
-            // star argument order: centre, along-axis pair, t1 pair, t2 pair
-            const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[0], gn[0], gm[0],
-                               G[0][li + 1], G[0][li - 1], G[0][li + PX], G[0][li - PX]);
-            const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[1], G[1][li + PX],
-                               G[1][li - PX], G[1][li + 1], G[1][li - 1], gn[1], gm[1]);
-            const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[2], G[2][li + 1],
-                               G[2][li - 1], G[2][li + PX], G[2][li - PX], gn[2], gm[2]);
-            const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[3], gn[3], gm[3],
-                               G[3][li + 1], G[3][li - 1], G[3][li + PX], G[3][li - PX]);
-            const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[4], G[4][li + PX],
-                               G[4][li - PX], G[4][li + 1], G[4][li - 1], gn[4], gm[4]);
-            const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[5], G[5][li + 1],
-                               G[5][li - 1], G[5][li + PX], G[5][li - PX], gn[5], gm[5]);
-            bn[0] = bo[0] + (sz0 - sy1);
-            bn[1] = bo[1] + (sx2 - sz3);
-            bn[2] = bo[2] + (sy4 - sx5);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Bbuf[c][li] = bn[c];
-            if (isO && k >= k0) {
-                const int64_t po = (int64_t)w0 * nxy + col;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[c]);
-            }
-        }
-        __syncthreads();
-
-        // E^{n+1}(k)
-        if (isO && k >= k0) {
-            const T ex = ampere_eval(e0[0], w.wa[1], bn[2], Bbuf[2][li - PX], w.wa[2], bn[1], bprev[1]);
-            const T ey = ampere_eval(e0[1], w.wa[2], bn[0], bprev[0], w.wa[0], bn[2], Bbuf[2][li - 1]);
-            const T ez = ampere_eval(e0[2], w.wa[0], bn[1], Bbuf[1][li - 1], w.wa[1], bn[0], Bbuf[0][li - PX]);
-            const int64_t po = (int64_t)w0 * nxy + col;
-            nt_store(out.c[0] + po, ex);
-            nt_store(out.c[1] + po, ey);
-            nt_store(out.c[2] + po, ez);
-        }
-
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            e0[c] = e1[c];
-            e1[c] = e2[c];
-        }
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            gm[m] = gc[m];
-            gc[m] = gn[m];
-        }
-        bprev[0] = bn[0];
-        bprev[1] = bn[1];
-        eb ^= 1;
-        gb ^= 1;
-        w3 = inc(w3);
-        w0 = inc(w0);
-    }
-}
-
-
-// LDS of the single-barrier variant: B^{n+1/2} is double-buffered so that the
-// Ampere update can lag one plane behind and read the previous plane's B
-// after the one barrier per plane.
-template <typename T, int TY>
-struct FusedSmem1 {
     static constexpr int PX = TILE_X + 4;
     static constexpr int PY = TY + 4;
     static constexpr int P = PX * PY;
@@ -339,17 +145,20 @@ struct FusedSmem1 {
     T Bbuf[2][3][P];  // B^{n+1/2}(k-1), B^{n+1/2}(k)
 };
 
-// Same tile as fused_tile with one workgroup barrier per plane: iteration k
-// forms g(k+1), B^{n+1/2}(k) and E^{n+1}(k-1); everything it reads from LDS
-// was written in iteration k-1.
+// One tile of the fused step: tile number `logical` of a box tiled as
+// ntx x nty x (z-chunks), x fastest.  All threads of the workgroup call it.
+// Lane roles: waves 0..TY+3 own the rows y = -2..TY+1 of the tile (lane = x);
+// the last wave owns the four halo columns x = -2, -1, TXe, TXe+1.
+// One workgroup barrier per plane: iteration k forms g(k+1), B^{n+1/2}(k) and
+// E^{n+1}(k-1); everything it reads from LDS was written in iteration k-1.
 template <typename T, int TY>
-__device__ __forceinline__ void fused_tile1(const Fields<T> &in, const Fields<T> &out, const Dims &d,
-                                            const Weights<T> &w, int zchunk, int ntx, int nty,
-                                            int logical, FusedSmem1<T, TY> &sm)
+__device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
+                                           const Weights<T> &w, int zchunk, int ntx, int nty,
+                                           int logical, FusedSmem<T, TY> &sm)
 {
-    constexpr int PX = FusedSmem1<T, TY>::PX;
-    constexpr int PY = FusedSmem1<T, TY>::PY;
-    constexpr int P = FusedSmem1<T, TY>::P;
+    constexpr int PX = FusedSmem<T, TY>::PX;
+    constexpr int PY = FusedSmem<T, TY>::PY;
+    constexpr int P = FusedSmem<T, TY>::P;
     auto &Ebuf = sm.Ebuf;
     auto &Gbuf = sm.Gbuf;
     auto &Bbuf = sm.Bbuf;
@@ -534,15 +343,6 @@ __global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in,
     fused_tile<T, TY>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
 }
 
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void fused_step1_kernel(Fields<T> in, Fields<T> out,
-                                                                     Dims d, Weights<T> w,
-                                                                     int zchunk, int ntx, int nty)
-{
-    __shared__ FusedSmem1<T, TY> sm;
-    fused_tile1<T, TY>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
-}
-
 // Batched step: every box of a batch advances one step.  Work item i is tile
 // items[i].y of box items[i].x; a persistent grid walks the list in rounds of
 // gridDim.x items (XCD-aware within a round).  parity 0: f -> s, 1: s -> f.
@@ -592,23 +392,13 @@ hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const
     const int nzc = (d.nz + zchunk - 1) / zchunk;
     const int64_t nb = (int64_t)ntx * nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
-    const char *ob = getenv("XFDTD_ONEBAR");
-    const int onebar = ob ? atoi(ob) : 0;
-    switch (tile_y + (onebar ? 100 : 0)) {
+    switch (tile_y) {
     case 4:
         hipLaunchKernelGGL((fused_step_kernel<T, 4>), dim3((unsigned)nb), dim3(64 * 9), 0, s, in,
                            out, d, w, zchunk, ntx, nty);
         break;
     case 8:
         hipLaunchKernelGGL((fused_step_kernel<T, 8>), dim3((unsigned)nb), dim3(64 * 13), 0, s, in,
-                           out, d, w, zchunk, ntx, nty);
-        break;
-    case 104:
-        hipLaunchKernelGGL((fused_step1_kernel<T, 4>), dim3((unsigned)nb), dim3(64 * 9), 0, s, in,
-                           out, d, w, zchunk, ntx, nty);
-        break;
-    case 108:
-        hipLaunchKernelGGL((fused_step1_kernel<T, 8>), dim3((unsigned)nb), dim3(64 * 13), 0, s, in,
                            out, d, w, zchunk, ntx, nty);
         break;
     default:

@@ -66,9 +66,10 @@ struct Scale12 {
     double s[12];
 };
 int adjoint_blocks(Dims d, int tile_y, int zchunk);
+// accumulate != 0: add to the per-workgroup slots instead of overwriting.
 template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
-                          const Weights<T> &w, int tile_y, int zchunk, double *partials,
+                          const Weights<T> &w, int tile_y, int zchunk, double *partials, int accumulate,
                           hipStream_t s);
 // grad[j] += sc.s[j] * sum over blocks of partials[b*12 + j]
 hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
