@@ -25,6 +25,27 @@ sys.path.insert(0, ROOT)
 
 SHAPE = (256, 256, 512)  # (nz, ny, nx)
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_06829_amd", "csrc", "kernels_step.hip")
+PROFILE = os.path.join(ROOT, "profiles", "fused_step_512x256x256_fp32.md")
+TILE_NAMES = {4: "TileCfg<1,8>", 8: "TileCfg<1,12>", 16: "TileCfg<2,10>"}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the kernel source has changed since those counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(PROFILE).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"kernel_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return float(m_b.group(1))
 METRIC = "Gcell-updates/s & %HBM roofline (fwd), fwd+adjoint time/step vs plain fwd"
 
 
@@ -133,15 +154,22 @@ def fwd_adj_ratio(steps=200):
 
 
 def calib_copy(gib=1.0, reps=5):
-    """A plain device copy of known size (for scaling rocprofv3 byte counters)."""
+    """A plain device copy of known size (for scaling rocprofv3 byte counters);
+    returns its size and achieved bandwidth (read + write bytes per second)."""
     import torch
     n = int(gib * (1 << 30)) // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(reps):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    return n * 4
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes": n * 4, "copy_GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
 
 
 def main():
@@ -153,6 +181,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-adj", action="store_true")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
+    ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -163,9 +192,13 @@ def main():
 
     import paper_1710_06829_amd as pkg
 
+    if args.adj_only:
+        print(json.dumps({"fwd_adj": fwd_adj_ratio()}), flush=True)
+        return
     steps = args.steps + (args.steps & 1)  # the fused kernel runs in pairs
     fields, coeffs, dt, f64 = make_inputs(SHAPE, torch.float32)
     solver = pkg.Solver(fields, dt, coeffs)
+    lc = solver.launch_config()
     cells = SHAPE[0] * SHAPE[1] * SHAPE[2]
 
     solver.run(args.warmup + (args.warmup & 1))
@@ -215,8 +248,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "fused_step_kernel<float, 8>",
+            "traffic": measured_traffic(),
+            "kernel": f"fused_step_kernel<float, {TILE_NAMES.get(lc['tile_y'], lc['tile_y'])}>",
+            "launch": lc,
             "bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": None,
@@ -224,7 +258,7 @@ def main():
     if not args.no_adj:
         line["fwd_adj"] = fwd_adj_ratio()
     if args.calib:
-        line["calib_copy_bytes"] = calib_copy()
+        line["calib_copy"] = calib_copy()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(f64, coeffs, dt, args.cpu_steps)
     print(json.dumps(line), flush=True)

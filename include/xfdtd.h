@@ -153,6 +153,13 @@ int xfdtd_run(xfdtd_t h, int64_t n);
  */
 int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw);
 
+/* Launch configuration of the fused step chosen for this handle: tile height
+ * (rows of the 64-wide (x, y) tile), z-planes per workgroup, and workgroups
+ * per launch.  Any pointer may be NULL.  The choice depends on grid and
+ * dtype only (overridable with the XFDTD_TILE_Y / XFDTD_ZCHUNK environment
+ * variables read at xfdtd_create). */
+int xfdtd_launch_config(xfdtd_t h, int *tile_y, int *zchunk, int *workgroups);
+
 /*
  * Dispersion of the scheme at n wave vectors (Sec. 3 and Sec. 5), on the GPU.
  *   k     : device, n x 3 doubles (k_x, k_y, k_z) in radians per length unit.

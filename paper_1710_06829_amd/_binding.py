@@ -48,6 +48,7 @@ SIGNATURES = {
     "xfdtd_step_ampere": ([_vp], _int),
     "xfdtd_run": ([_vp, _i64], _int),
     "xfdtd_get_weights": ([_vp, _dp, ctypes.POINTER(_int)], _int),
+    "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "xfdtd_dispersion": ([_GP, ctypes.c_double, _dp, _vp, _i64, _vp, _vp, _vp, _vp], _int),
     "xfdtd_divergence": ([_vp, _vp, _vp], _int),
     "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),

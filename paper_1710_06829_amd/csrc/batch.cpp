@@ -266,7 +266,8 @@ int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch,
 int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_y, int zsplit, int grid)
 {
     if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if ((tile_y != 4 && tile_y != 8) || zsplit < 1 || zsplit > 1024 || grid < 0)
+    if ((tile_y != 4 && tile_y != 8 && tile_y != 16) || zsplit < 1 || zsplit > 1024 || grid < 0 ||
+        (tile_y == 16 && b->dtype != XFDTD_F32))
         return set_error(XFDTD_EINVAL, "bad configuration");
     b->cfg.tile_y = tile_y;
     b->cfg.zsplit = zsplit;
@@ -301,9 +302,9 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
     }
     const int ncu = cus();
     std::vector<Config> cands;
-    const int tys[2] = {4, 8};
+    const int tys[3] = {4, 8, 16};
     for (int ty : tys) {
-        if (b->dtype == XFDTD_F64 && ty == 8) continue;
+        if (b->dtype == XFDTD_F64 && ty != 4) continue;
         for (int zs : {1, 2, 4})
             for (int gm : {0, 1, 2}) {
                 Config c;

@@ -132,13 +132,28 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
 // ---------------------------------------------------------------------------
 constexpr int TILE_X = 64;
 
+// Tiling of the fused step: a workgroup of NW row waves plus one halo wave
+// owns a 64 x TY tile with TY = R*NW - 4.  Row wave w owns the rows
+// y = R*w - 2 .. R*w - 2 + R - 1 (lane = x, R positions per lane); the halo
+// wave owns the four halo columns x = -2, -1, TXe, TXe+1 over the same rows,
+// R rows per lane.
+template <int R_, int NW_>
+struct TileCfg {
+    static constexpr int R = R_;
+    static constexpr int NW = NW_;
+    static constexpr int TY = R_ * NW_ - 4;
+    static constexpr int THREADS = 64 * (NW_ + 1);
+    static_assert(TY > 0, "tile height");
+    static_assert(4 * NW_ <= 64, "halo wave must cover 4 columns x NW row groups");
+};
+
 // LDS of one workgroup of the fused step.  B^{n+1/2} is double-buffered so
 // that the Ampere update can lag one plane behind and read the previous
 // plane's B after the single barrier per plane.
 template <typename T, int TY>
 struct FusedSmem {
-    static constexpr int PX = TILE_X + 4;
-    static constexpr int PY = TY + 4;
+    static constexpr int PX = TILE_X + 4;  // row pitch: x in [-2, 66)
+    static constexpr int PY = TY + 4;      // rows y in [-2, TY + 2)
     static constexpr int P = PX * PY;
     T Ebuf[2][3][P];  // E(k+1), E(k+2)
     T Gbuf[2][6][P];  // g(k), g(k+1)
@@ -147,17 +162,16 @@ struct FusedSmem {
 
 // One tile of the fused step: tile number `logical` of a box tiled as
 // ntx x nty x (z-chunks), x fastest.  All threads of the workgroup call it.
-// Lane roles: waves 0..TY+3 own the rows y = -2..TY+1 of the tile (lane = x);
-// the last wave owns the four halo columns x = -2, -1, TXe, TXe+1.
 // One workgroup barrier per plane: iteration k forms g(k+1), B^{n+1/2}(k) and
 // E^{n+1}(k-1); everything it reads from LDS was written in iteration k-1.
-template <typename T, int TY>
+// Values a position needs along z stay in that lane's registers.
+template <typename T, typename C>
 __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
                                            const Weights<T> &w, int zchunk, int ntx, int nty,
-                                           int logical, FusedSmem<T, TY> &sm)
+                                           int logical, FusedSmem<T, C::TY> &sm)
 {
+    constexpr int R = C::R, NW = C::NW, TY = C::TY;
     constexpr int PX = FusedSmem<T, TY>::PX;
-    constexpr int PY = FusedSmem<T, TY>::PY;
     constexpr int P = FusedSmem<T, TY>::P;
     auto &Ebuf = sm.Ebuf;
     auto &Gbuf = sm.Gbuf;
@@ -171,151 +185,185 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     const int KZe = min(zchunk, d.nz - k0);
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int rx = 0, ry = 0;
-    bool valid;
-    if (wave < TY + 4) {
-        ry = wave - 2;
+    int rx = 0, ry0 = 0;
+    bool lane_ok;
+    if (wave < NW) {
         rx = lane;
-        valid = rx < TXe && ry < TYe + 2;
+        ry0 = R * wave - 2;
+        lane_ok = rx < TXe;
     } else {
-        const int sel = lane / PY;
-        ry = lane % PY - 2;
+        const int sel = lane / NW;
+        ry0 = R * (lane % NW) - 2;
         rx = sel == 0 ? -2 : sel == 1 ? -1 : sel == 2 ? TXe : TXe + 1;
-        valid = sel < 4 && ry < TYe + 2;
+        lane_ok = sel < 4;
     }
-    const bool isE = valid;
-    const bool isG = valid && rx < TXe + 1 && ry < TYe + 1;
-    const bool isB = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;
-    const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;
-
-    const int li = valid ? (ry + 2) * PX + (rx + 2) : 0;
+    bool isE[R], isG[R], isB[R], isO[R];
+    int li[R], col[R];
     const int64_t nxy = (int64_t)d.nx * d.ny;
-    const int col = valid ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int ry = ry0 + r;
+        const bool valid = lane_ok && ry < TYe + 2;
+        isE[r] = valid;                                                  // loads E
+        isG[r] = valid && rx < TXe + 1 && ry < TYe + 1;                  // forms g
+        isB[r] = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;  // B^{n+1/2}
+        isO[r] = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;    // outputs
+        li[r] = valid ? (ry + 2) * PX + (rx + 2) : 0;
+        // idle positions use column 0 so that every lane can load
+        // unconditionally (in bounds, value unused)
+        col[r] = valid ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+    }
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
 
-    // own-column queues: ea = E(k-1), e0 = E(k), e1 = E(k+1); g at k-1, k;
+    // per position: ea = E(k-1), e0 = E(k), e1 = E(k+1); g at k-1, k;
     // b1 = B^{n+1/2}(k-1), b2 = B^{n+1/2}(k-2) (x, y components)
-    T ea[3], e0[3], e1[3], epf[3], bpf[3], gm[6], gc[6], b1[3], b2[2];
+    T ea[R][3], e0[R][3], e1[R][3], epf[R][3], bpf[R][3], gm[R][6], gc[R][6], b1[R][3], b2[R][2];
     int eb = 0, gb = 0, bb = 0;
     int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), w0 = wrap(k0 - 3, nz), wm = wrap(k0 - 4, nz);
     {
         const int64_t pa = (int64_t)wrap(k0 - 2, nz) * nxy, pb = (int64_t)wrap(k0 - 1, nz) * nxy;
         const int64_t pc = (int64_t)w1 * nxy;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            e1[c] = in.c[c][pa + col];
-            epf[c] = in.c[c][pb + col];
-            bpf[c] = in.c[3 + c][pc + col];
-        }
-        if (isE) {
+        for (int r = 0; r < R; ++r) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Ebuf[0][c][li] = e1[c];
+            for (int c = 0; c < 3; ++c) {
+                e1[r][c] = in.c[c][pa + col[r]];
+                epf[r][c] = in.c[c][pb + col[r]];
+                bpf[r][c] = in.c[3 + c][pc + col[r]];
+            }
+            if (isE[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Ebuf[0][c][li[r]] = e1[r][c];
+            }
+#pragma unroll
+            for (int m = 0; m < 6; ++m) gm[r][m] = gc[r][m] = T(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ea[r][c] = e0[r][c] = b1[r][c] = T(0);
+            b2[r][0] = b2[r][1] = T(0);
         }
     }
-#pragma unroll
-    for (int m = 0; m < 6; ++m) gm[m] = gc[m] = T(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ea[c] = e0[c] = b1[c] = T(0);
-    b2[0] = b2[1] = T(0);
     __syncthreads();
 
     const int klast = k0 + KZe - 1;
     for (int k = k0 - 3; k <= klast + 1; ++k) {
-        T e2[3], bo[3];
+        T e2[R][3], bo[R][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            e2[c] = epf[c];
-            bo[c] = bpf[c];
-        }
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                e2[r][c] = epf[r][c];
+                bo[r][c] = bpf[r][c];
+            }
         {
             const int64_t p3 = (int64_t)w3 * nxy;
             w1 = inc(w1);
             const int64_t p1 = (int64_t)w1 * nxy;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                epf[c] = in.c[c][p3 + col];
-                bpf[c] = in.c[3 + c][p1 + col];
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    epf[r][c] = in.c[c][p3 + col[r]];
+                    bpf[r][c] = in.c[3 + c][p1 + col[r]];
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (isE[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Ebuf[eb ^ 1][c][li[r]] = e2[r][c];
+            }
+
+        // g(k+1) (positions outside the g region read the neighbours of slot
+        // 0: in bounds, value unused)
+        T gn[R][6];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
+            const int lg = isG[r] ? li[r] : 0;
+            gn[r][0] = e2[r][1] - e1[r][1];          // g_z[Ey] -> Bx (+S_z)
+            gn[r][1] = Ez1[lg + PX] - e1[r][2];      // g_y[Ez] -> Bx (-S_y)
+            gn[r][2] = Ez1[lg + 1] - e1[r][2];       // g_x[Ez] -> By (+S_x)
+            gn[r][3] = e2[r][0] - e1[r][0];          // g_z[Ex] -> By (-S_z)
+            gn[r][4] = Ex1[lg + PX] - e1[r][0];      // g_y[Ex] -> Bz (+S_y)
+            gn[r][5] = Ey1[lg + 1] - e1[r][1];       // g_x[Ey] -> Bz (-S_x)
+            if (isG[r]) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li[r]] = gn[r][m];
             }
         }
-        if (isE) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Ebuf[eb ^ 1][c][li] = e2[c];
-        }
 
-        // g(k+1)
-        T gn[6];
-        {
-            const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
-            const int lg = isG ? li : 0;
-            gn[0] = e2[1] - e1[1];
-            gn[1] = Ez1[lg + PX] - e1[2];
-            gn[2] = Ez1[lg + 1] - e1[2];
-            gn[3] = e2[0] - e1[0];
-            gn[4] = Ex1[lg + PX] - e1[0];
-            gn[5] = Ey1[lg + 1] - e1[1];
-        }
-        if (isG) {
+        // B^{n+1/2}(k): stars of g(k); z-neighbours from registers
+        T bn[R][3];
+        const bool doStar = k >= k0 - 1 && k <= klast;
 #pragma unroll
-            for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li] = gn[m];
-        }
-
-        // B^{n+1/2}(k)
-        T bn[3] = {T(0), T(0), T(0)};
-        if (isB && k >= k0 - 1 && k <= klast) {
-            const T(*G)[P] = Gbuf[gb];
-            const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[0], gn[0], gm[0],
-                               G[0][li + 1], G[0][li - 1], G[0][li + PX], G[0][li - PX]);
-            const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[1], G[1][li + PX],
-                               G[1][li - PX], G[1][li + 1], G[1][li - 1], gn[1], gm[1]);
-            const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[2], G[2][li + 1],
-                               G[2][li - 1], G[2][li + PX], G[2][li - PX], gn[2], gm[2]);
-            const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[3], gn[3], gm[3],
-                               G[3][li + 1], G[3][li - 1], G[3][li + PX], G[3][li - PX]);
-            const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[4], G[4][li + PX],
-                               G[4][li - PX], G[4][li + 1], G[4][li - 1], gn[4], gm[4]);
-            const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[5], G[5][li + 1],
-                               G[5][li - 1], G[5][li + PX], G[5][li - PX], gn[5], gm[5]);
-            bn[0] = bo[0] + (sz0 - sy1);
-            bn[1] = bo[1] + (sx2 - sz3);
-            bn[2] = bo[2] + (sy4 - sx5);
+        for (int r = 0; r < R; ++r) {
+            bn[r][0] = bn[r][1] = bn[r][2] = T(0);
+            if (isB[r] && doStar) {
+                const T(*G)[P] = Gbuf[gb];
+                const int l = li[r];
+                // star argument order: centre, along-axis pair, t1 pair, t2 pair
+                const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[r][0], gn[r][0], gm[r][0],
+                                   G[0][l + 1], G[0][l - 1], G[0][l + PX], G[0][l - PX]);
+                const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[r][1], G[1][l + PX],
+                                   G[1][l - PX], G[1][l + 1], G[1][l - 1], gn[r][1], gm[r][1]);
+                const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[r][2], G[2][l + 1],
+                                   G[2][l - 1], G[2][l + PX], G[2][l - PX], gn[r][2], gm[r][2]);
+                const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[r][3], gn[r][3], gm[r][3],
+                                   G[3][l + 1], G[3][l - 1], G[3][l + PX], G[3][l - PX]);
+                const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[r][4], G[4][l + PX],
+                                   G[4][l - PX], G[4][l + 1], G[4][l - 1], gn[r][4], gm[r][4]);
+                const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[r][5], G[5][l + 1],
+                                   G[5][l - 1], G[5][l + PX], G[5][l - PX], gn[r][5], gm[r][5]);
+                bn[r][0] = bo[r][0] + (sz0 - sy1);
+                bn[r][1] = bo[r][1] + (sx2 - sz3);
+                bn[r][2] = bo[r][2] + (sy4 - sx5);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Bbuf[bb][c][li] = bn[c];
-            if (isO && k >= k0) {
-                const int64_t po = (int64_t)w0 * nxy + col;
+                for (int c = 0; c < 3; ++c) Bbuf[bb][c][l] = bn[r][c];
+                if (isO[r] && k >= k0) {
+                    const int64_t po = (int64_t)w0 * nxy + col[r];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[c]);
+                    for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[r][c]);
+                }
             }
         }
 
         // E^{n+1}(k-1) from B^{n+1/2}(k-1) (LDS, written last iteration)
-        if (isO && k - 1 >= k0) {
+        if (k - 1 >= k0) {
             const T(*Bp)[P] = Bbuf[bb ^ 1];
-            const T ex = ampere_eval(ea[0], w.wa[1], b1[2], Bp[2][li - PX], w.wa[2], b1[1], b2[1]);
-            const T ey = ampere_eval(ea[1], w.wa[2], b1[0], b2[0], w.wa[0], b1[2], Bp[2][li - 1]);
-            const T ez = ampere_eval(ea[2], w.wa[0], b1[1], Bp[1][li - 1], w.wa[1], b1[0], Bp[0][li - PX]);
-            const int64_t po = (int64_t)wm * nxy + col;
-            nt_store(out.c[0] + po, ex);
-            nt_store(out.c[1] + po, ey);
-            nt_store(out.c[2] + po, ez);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!isO[r]) continue;
+                const int l = li[r];
+                const T ex = ampere_eval(ea[r][0], w.wa[1], b1[r][2], Bp[2][l - PX], w.wa[2], b1[r][1], b2[r][1]);
+                const T ey = ampere_eval(ea[r][1], w.wa[2], b1[r][0], b2[r][0], w.wa[0], b1[r][2], Bp[2][l - 1]);
+                const T ez = ampere_eval(ea[r][2], w.wa[0], b1[r][1], Bp[1][l - 1], w.wa[1], b1[r][0], Bp[0][l - PX]);
+                const int64_t po = (int64_t)wm * nxy + col[r];
+                nt_store(out.c[0] + po, ex);
+                nt_store(out.c[1] + po, ey);
+                nt_store(out.c[2] + po, ez);
+            }
         }
         __syncthreads();
 
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            ea[c] = e0[c];
-            e0[c] = e1[c];
-            e1[c] = e2[c];
-        }
+        for (int r = 0; r < R; ++r) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            gm[m] = gc[m];
-            gc[m] = gn[m];
-        }
-        b2[0] = b1[0];
-        b2[1] = b1[1];
+            for (int c = 0; c < 3; ++c) {
+                ea[r][c] = e0[r][c];
+                e0[r][c] = e1[r][c];
+                e1[r][c] = e2[r][c];
+            }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) b1[c] = bn[c];
+            for (int m = 0; m < 6; ++m) {
+                gm[r][m] = gc[r][m];
+                gc[r][m] = gn[r][m];
+            }
+            b2[r][0] = b1[r][0];
+            b2[r][1] = b1[r][1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b1[r][c] = bn[r][c];
+        }
         eb ^= 1;
         gb ^= 1;
         bb ^= 1;
@@ -334,24 +382,23 @@ __device__ __forceinline__ int xcd_order(int bid, int nb)
     return xcd * q + min(xcd, r) + (bid >> 3);
 }
 
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void fused_step_kernel(Fields<T> in, Fields<T> out,
-                                                                    Dims d, Weights<T> w,
-                                                                    int zchunk, int ntx, int nty)
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void fused_step_kernel(Fields<T> in, Fields<T> out, Dims d,
+                                                                Weights<T> w, int zchunk, int ntx, int nty)
 {
-    __shared__ FusedSmem<T, TY> sm;
-    fused_tile<T, TY>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
+    __shared__ FusedSmem<T, C::TY> sm;
+    fused_tile<T, C>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
 }
 
 // Batched step: every box of a batch advances one step.  Work item i is tile
 // items[i].y of box items[i].x; a persistent grid walks the list in rounds of
 // gridDim.x items (XCD-aware within a round).  parity 0: f -> s, 1: s -> f.
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void batched_step_kernel(const BoxDesc<T> *__restrict__ boxes,
-                                                                      const int2 *__restrict__ items,
-                                                                      int nitems, int parity)
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<T> *__restrict__ boxes,
+                                                                  const int2 *__restrict__ items,
+                                                                  int nitems, int parity)
 {
-    __shared__ FusedSmem<T, TY> sm;
+    __shared__ FusedSmem<T, C::TY> sm;
     const int slot = xcd_order(blockIdx.x, gridDim.x);
     for (int base = 0; base < nitems; base += gridDim.x) {
         const int i = base + slot;
@@ -360,10 +407,15 @@ __global__ __launch_bounds__(64 * (TY + 5)) void batched_step_kernel(const BoxDe
         const BoxDesc<T> &b = boxes[it.x];
         const Fields<T> &in = parity ? b.s : b.f;
         const Fields<T> &out = parity ? b.f : b.s;
-        fused_tile<T, TY>(in, out, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
+        fused_tile<T, C>(in, out, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
         __syncthreads();  // LDS is reused by the next item
     }
 }
+
+// tile heights: 4 and 8 with one row per lane, 16 with two rows per lane
+using Tile4 = TileCfg<1, 8>;
+using Tile8 = TileCfg<1, 12>;
+using Tile16 = TileCfg<2, 10>;
 
 }  // namespace
 
@@ -394,12 +446,19 @@ hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
     switch (tile_y) {
     case 4:
-        hipLaunchKernelGGL((fused_step_kernel<T, 4>), dim3((unsigned)nb), dim3(64 * 9), 0, s, in,
-                           out, d, w, zchunk, ntx, nty);
+        hipLaunchKernelGGL((fused_step_kernel<T, Tile4>), dim3((unsigned)nb), dim3(Tile4::THREADS), 0, s,
+                           in, out, d, w, zchunk, ntx, nty);
         break;
     case 8:
-        hipLaunchKernelGGL((fused_step_kernel<T, 8>), dim3((unsigned)nb), dim3(64 * 13), 0, s, in,
-                           out, d, w, zchunk, ntx, nty);
+        hipLaunchKernelGGL((fused_step_kernel<T, Tile8>), dim3((unsigned)nb), dim3(Tile8::THREADS), 0, s,
+                           in, out, d, w, zchunk, ntx, nty);
+        break;
+    case 16:  // two rows per lane; FP64 would exceed the LDS of a CU
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((fused_step_kernel<T, Tile16>), dim3((unsigned)nb), dim3(Tile16::THREADS), 0, s,
+                               in, out, d, w, zchunk, ntx, nty);
+        else
+            return hipErrorInvalidValue;
         break;
     default:
         return hipErrorInvalidValue;
@@ -415,12 +474,19 @@ hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems
     if (grid <= 0 || grid > nitems) grid = nitems;
     switch (tile_y) {
     case 4:
-        hipLaunchKernelGGL((batched_step_kernel<T, 4>), dim3(grid), dim3(64 * 9), 0, s, boxes, items, nitems,
-                           parity);
+        hipLaunchKernelGGL((batched_step_kernel<T, Tile4>), dim3(grid), dim3(Tile4::THREADS), 0, s, boxes, items,
+                           nitems, parity);
         break;
     case 8:
-        hipLaunchKernelGGL((batched_step_kernel<T, 8>), dim3(grid), dim3(64 * 13), 0, s, boxes, items, nitems,
-                           parity);
+        hipLaunchKernelGGL((batched_step_kernel<T, Tile8>), dim3(grid), dim3(Tile8::THREADS), 0, s, boxes, items,
+                           nitems, parity);
+        break;
+    case 16:
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((batched_step_kernel<T, Tile16>), dim3(grid), dim3(Tile16::THREADS), 0, s, boxes,
+                               items, nitems, parity);
+        else
+            return hipErrorInvalidValue;
         break;
     default:
         return hipErrorInvalidValue;

@@ -127,6 +127,12 @@ class Solver:
         self._bind()
         B.check(B.lib().xfdtd_run(self._h, int(n)))
 
+    def launch_config(self):
+        """{'tile_y', 'zchunk', 'workgroups'} of the fused step for this box."""
+        v = [ctypes.c_int() for _ in range(3)]
+        B.check(B.lib().xfdtd_launch_config(self._h, *[ctypes.byref(x) for x in v]))
+        return {"tile_y": v[0].value, "zchunk": v[1].value, "workgroups": v[2].value}
+
     def weights(self):
         w = (ctypes.c_double * 15)()
         nw = ctypes.c_int()

@@ -164,3 +164,46 @@ def test_package_has_no_cpu_fallback():
         pkg.Solver(f, 0.3, O.yee_coeffs())
     with pytest.raises(ValueError):
         pkg.dispersion(torch.zeros((3, 3), dtype=torch.float64), 0.3, O.yee_coeffs())
+
+
+def test_batch_create_validates_every_box():
+    beta, delta = S.extended_beta_delta(9)
+    c = O.coeffs_from(beta, delta)
+    dt = 0.9 * O.cfl_dt(c)
+    grids = (B.Grid * 3)(B.make_grid((4, 5, 6)), B.make_grid((8, 8, 8)), B.make_grid((3, 2, 1)))
+    dts = (ctypes.c_double * 3)(dt, dt, dt)
+    cc = (ctypes.c_double * 36)(*(list(c) * 3))
+    h = ctypes.c_void_p()
+    assert B.lib().xfdtd_batch_create(grids, dts, cc, 3, B.XFDTD_F32, 0, ctypes.byref(h)) == 0
+    B.lib().xfdtd_batch_destroy(h)
+    bad = (ctypes.c_double * 3)(dt, dt * 1.2, dt)
+    assert B.lib().xfdtd_batch_create(grids, bad, cc, 3, B.XFDTD_F32, 0, ctypes.byref(h)) == -2
+    assert b"box 1" in B.lib().xfdtd_last_error()
+    assert B.lib().xfdtd_batch_create(grids, bad, cc, 3, B.XFDTD_F32, 1, ctypes.byref(h)) == 0
+    # calls before binding are state errors; bad configurations are rejected
+    assert B.lib().xfdtd_batch_run(h, 2) == -5
+    assert B.lib().xfdtd_batch_tune(h, 0, None) == -5
+    assert B.lib().xfdtd_batch_set_config(h, 5, 1, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 4, 0, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 4, 2, 0) == 0
+    B.lib().xfdtd_batch_destroy(h)
+    g0 = (B.Grid * 1)(B.make_grid((0, 5, 6)))
+    assert B.lib().xfdtd_batch_create(g0, dts, cc, 1, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
+    assert B.lib().xfdtd_batch_create(grids, dts, cc, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
+
+
+def test_batch_bind_rejects_overlap_before_device_work():
+    c = O.yee_coeffs()
+    grids = (B.Grid * 2)(B.make_grid((4, 4, 4)), B.make_grid((4, 4, 4)))
+    dts = (ctypes.c_double * 2)(0.3, 0.3)
+    cc = (ctypes.c_double * 24)(*(list(c) * 2))
+    h = ctypes.c_void_p()
+    assert B.lib().xfdtd_batch_create(grids, dts, cc, 2, B.XFDTD_F64, 0, ctypes.byref(h)) == 0
+    base, nb = 1 << 40, 64 * 8
+    f = (ctypes.c_void_p * 12)(*[base + i * nb for i in range(12)])
+    s = (ctypes.c_void_p * 12)(*[base + (12 + i) * nb for i in range(12)])
+    s_bad = (ctypes.c_void_p * 12)(*[base + (11 + i) * nb for i in range(12)])
+    assert B.lib().xfdtd_batch_bind(h, f, s_bad, None) == -1
+    f_mis = (ctypes.c_void_p * 12)(*[base + 4 + i * nb for i in range(12)])
+    assert B.lib().xfdtd_batch_bind(h, f_mis, s, None) == -1
+    B.lib().xfdtd_batch_destroy(h)

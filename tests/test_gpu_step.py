@@ -203,3 +203,26 @@ def test_dispersion_flags_unstable_wave_vectors():
     w, _, _ = pkg.dispersion(k, dt, c, allow_unstable=True)
     w = w.cpu().numpy()
     assert np.isfinite(w[0]) and np.isnan(w[1])
+
+
+@pytest.mark.parametrize("shape", [(37, 45, 150), (16, 33, 64), (3, 17, 5)])
+def test_fp32_tilings_agree_bitwise_and_match_oracle(env, shape):
+    """Every FP32 tiling (4, 8 and 16 rows, the 16-row one with two rows per
+    lane) and z-chunking evaluates the same arithmetic per cell: results are
+    bitwise equal and match the oracle under the FP32 convention."""
+    c = _coeffs(491)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 492)
+    outs = []
+    for ty in (4, 8, 16):
+        for zc in (2, 7, 64):
+            env(XFDTD_TILE_Y=ty, XFDTD_ZCHUNK=zc)
+            t = to_dev(f0, torch.float32)
+            pkg.Solver(t, dt, c, spacing=sp).run(6)
+            outs.append(to_host(t))
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+    ce, spe = _fp32.effective(c, dt, sp)
+    exp = oracle.c_run(_fp32.round_fields(f0), 6, ce, dt, spe)
+    assert rel_l2(outs[0], exp) < 1e-6
