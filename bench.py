@@ -148,9 +148,117 @@ def fwd_adj_ratio(steps=200):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     t_fa = min(times)
+    # every E kept (one segment of n steps: no recompute), for comparison
+    ws2 = torch.empty(sg.grad_workspace_bytes(steps, steps), dtype=torch.uint8, device=dev)
+    for a in range(6):
+        work[a].copy_(f32[a])
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    sg.grad_forward(steps, ws2, steps)
+    for a in range(6):
+        lam[a].zero_()
+    for a in range(3):
+        lam[a][:, :, xp] = work[a][:, :, xp]
+    sg.grad_backward(steps, ws2, lam, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_all = e0.elapsed_time(e1)
     return {"ratio": round(t_fa / t_fwd, 3), "fwd_ms": round(t_fwd, 3), "fwd_adj_ms": round(t_fa, 3),
-            "steps": steps, "segment": seg, "workload": "128^3 FP32 Gaussian pulse (wavelength 12), "
+            "steps": steps, "segment": seg,
+            "ratio_all_E_kept": round(t_all / t_fwd, 3),
+            "workload": "128^3 FP32 Gaussian pulse (wavelength 12), "
             "probe-plane misfit loss, gradients w.r.t. 12 coefficients and initial fields"}
+
+
+def sustained_large(steps=5000):
+    """1024x256x256 FP32 box, 5000 steps of a Gaussian pulse (wavelength 20,
+    waist 40, duration 50 cells; extended set seed 601): sustained rate."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    import paper_1710_06829_amd as pkg
+
+    shape = (256, 256, 1024)
+    beta, delta = S.extended_beta_delta(601)
+    raw = [0.0] * 12
+    for a in range(3):
+        raw[4 * a + 1], raw[4 * a + 2], raw[4 * a + 3] = beta[a, 0], beta[a, 1], delta[a]
+    coeffs = pkg.consistent_alpha(raw)
+    dt = 0.95 * pkg.cfl_limit(shape, coeffs)[0]
+    f = S.gaussian_pulse(shape, dt, 20.0, 40.0, 50.0)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(x)).to(device=dev, dtype=torch.float32) for x in f]
+    del f
+    s = pkg.Solver(t, dt, coeffs)
+    s.run(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = shape[0] * shape[1] * shape[2]
+    _, _, bad = s.divergence_max(raise_nonfinite=False)
+    return {"workload": "1024x256x256 FP32 Gaussian pulse (wavelength 20), 5000 steps",
+            "steps": steps, "seconds": round(ms / 1e3, 3),
+            "Gcell_updates_per_s": round(cells * steps / (ms * 1e-3) / 1e9, 2),
+            "launch": s.launch_config(), "nonfinite": bad}
+
+
+def batched_boxes(steps=500):
+    """64 periodic boxes (edges iid in {32, 48, 64, 96, 128}, own coefficient
+    sets and random FP32 fields): one graph-captured batched run vs 64
+    sequential single-box runs."""
+    import numpy as np
+    import torch
+
+    import synthetic as S
+    import paper_1710_06829_amd as pkg
+
+    dev = torch.device("cuda:0")
+    boxes, seq = [], []
+    cells = 0
+    for b, (nx, ny, nz) in enumerate(S.box_edges(64, 301)):
+        beta, delta = S.extended_beta_delta(302 + b)
+        raw = [0.0] * 12
+        for a in range(3):
+            raw[4 * a + 1], raw[4 * a + 2], raw[4 * a + 3] = beta[a, 0], beta[a, 1], delta[a]
+        c = pkg.consistent_alpha(raw)
+        shape = (nz, ny, nx)
+        dt = 0.95 * pkg.cfl_limit(shape, c)[0]
+        f = [torch.from_numpy(x).to(device=dev, dtype=torch.float32) for x in S.uniform_fields(shape, 400 + b)]
+        boxes.append(([x.clone() for x in f], dt, c))
+        seq.append((f, dt, c))
+        cells += nx * ny * nz
+    bt = pkg.Batch(boxes, tune=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    bt.run(steps)  # captures the graph (first call)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    bt.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1)
+    solvers = [pkg.Solver(f, dt, c) for (f, dt, c) in seq]
+    for s in solvers:
+        s.run(2)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for s in solvers:
+        s.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_s = e0.elapsed_time(e1)
+    return {"workload": "64 boxes, edges in {32,48,64,96,128}, FP32, 500 steps", "cells": cells,
+            "batched_ms": round(t_b, 3), "sequential_ms": round(t_s, 3),
+            "batched_Gcell_updates_per_s": round(cells * steps / (t_b * 1e-3) / 1e9, 2),
+            "sequential_Gcell_updates_per_s": round(cells * steps / (t_s * 1e-3) / 1e9, 2),
+            "speedup": round(t_s / t_b, 3), "config": bt.config()}
 
 
 def calib_copy(gib=1.0, reps=5):
@@ -182,6 +290,8 @@ def main():
     ap.add_argument("--no-adj", action="store_true")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 1024x256x256 sustained run and the 64-box batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -257,6 +367,11 @@ def main():
     }
     if not args.no_adj:
         line["fwd_adj"] = fwd_adj_ratio()
+    if not args.no_extra:
+        line["sustained_1024x256x256"] = sustained_large()
+        torch.cuda.empty_cache()
+        line["batched_64_boxes"] = batched_boxes()
+        torch.cuda.empty_cache()
     if args.calib:
         line["calib_copy"] = calib_copy()
     if not args.no_cpu:

@@ -646,15 +646,24 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
     for (int c = 0; c < 6; ++c)
         HIP_TRY(hipMemcpyAsync(ck0.c[c], fields.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
     Fields<T> A = state_at<T>(ws, fb, 6 * nck), B = state_at<T>(ws, fb, 6 * nck + 6);
+    // The last segment's E fields go straight to the snapshot slots that the
+    // backward pass would otherwise recompute (B ping-pongs in state A).
+    const int64_t s0_last = (nck - 1) * seg;
     Fields<T> cur = ck0;
     for (int64_t s = 0; s < n; ++s) {
         Fields<T> dst;
-        if (s + 1 == n)
+        if (s + 1 == n) {
             dst = fields;
-        else if ((s + 1) % seg == 0)
+        } else if ((s + 1) % seg == 0) {
             dst = state_at<T>(ws, fb, 6 * ((s + 1) / seg));
-        else
+        } else if (s >= s0_last) {
+            for (int c = 0; c < 3; ++c) {
+                dst.c[c] = (T *)(ws + (size_t)(6 * nck + 12 + 3 * (s - s0_last) + c) * fb);
+                dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
+            }
+        } else {
             dst = (cur.c[0] == A.c[0]) ? B : A;
+        }
         HIP_TRY(launch_fused<T>(cur, dst, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
         cur = dst;
     }
@@ -687,9 +696,10 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
     for (int64_t m = nck - 1; m >= 0 && n > 0; --m) {
         const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
         Fields<T> ck = state_at<T>(ws, fb, 6 * m);
-        // recompute the segment, keeping E of every step
+        // recompute the segment, keeping E of every step (the forward pass
+        // already stored those of the last segment)
         Fields<T> in = ck;
-        for (int64_t s = s0; s + 1 < s1; ++s) {
+        for (int64_t s = s0; s + 1 < s1 && m != nck - 1; ++s) {
             Fields<T> out;
             Fields<T> e = segE(s + 1 - s0);
             for (int c = 0; c < 3; ++c) out.c[c] = e.c[c];
