@@ -261,6 +261,83 @@ def batched_boxes(steps=500):
             "speedup": round(t_s / t_b, 3), "config": bt.config()}
 
 
+def batched_grads(steps=300, count=16, edge=96):
+    """16 extended coefficient sets on 96^3 FP32 pulse boxes, 300 steps:
+    batched checkpointed forward + adjoint vs the batched forward alone and
+    vs 16 sequential single-box gradient runs."""
+    import torch
+
+    import synthetic as S
+    import paper_1710_06829_amd as pkg
+
+    dev = torch.device("cuda:0")
+    shape = (edge, edge, edge)
+    boxes = []
+    for b in range(count):
+        beta, delta = S.extended_beta_delta(520 + 10 * b)
+        raw = [0.0] * 12
+        for a in range(3):
+            raw[4 * a + 1], raw[4 * a + 2], raw[4 * a + 3] = beta[a, 0], beta[a, 1], delta[a]
+        c = pkg.consistent_alpha(raw)
+        dt = 0.95 * pkg.cfl_limit(shape, c)[0]
+        f = S.add_noise(S.gaussian_pulse(shape, dt, wavelength=12.0, waist=16.0, duration=16.0,
+                                         x0=0.5 * edge), 1e-3, 521)
+        boxes.append(([torch.from_numpy(x).to(device=dev, dtype=torch.float32) for x in f], dt, c))
+    lam0 = [torch.from_numpy(x).to(device=dev, dtype=torch.float32) for x in S.uniform_fields(shape, 540)]
+    init = [[x.clone() for x in f] for (f, _, _) in boxes]
+    bt = pkg.Batch(boxes, tune=True)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def reset():
+        for (f, _, _), f0 in zip(boxes, init):
+            for a, b in zip(f, f0):
+                a.copy_(b)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    bt.run(steps)  # graph capture
+    reset()
+    t_fwd = timed(lambda: bt.run(steps))
+    ws = bt.grad_workspaces(steps)
+    lams = [[x.clone() for x in lam0] for _ in range(count)]
+    reset()
+    bt.grad_forward(steps, ws)
+    bt.grad_backward(steps, ws, lams)  # warm-up (descriptor uploads, buffers)
+    reset()
+    lams = [[x.clone() for x in lam0] for _ in range(count)]
+    t_f = timed(lambda: bt.grad_forward(steps, ws))
+    t_b = timed(lambda: bt.grad_backward(steps, ws, lams))
+    del ws
+    torch.cuda.empty_cache()
+    reset()
+    solvers = [pkg.Solver(f, dt, c, scratch=False) for (f, dt, c) in boxes]
+    w1 = torch.empty(solvers[0].grad_workspace_bytes(steps), dtype=torch.uint8, device=dev)
+    lam1 = [x.clone() for x in lam0]
+
+    def seq():
+        for s in solvers:
+            s.grad_forward(steps, w1)
+            s.grad_backward(steps, w1, lam1)
+
+    seq()
+    reset()
+    t_s = timed(seq)
+    cells = count * edge ** 3
+    return {"workload": f"{count} extended sets x {edge}^3 FP32 pulse boxes, {steps} steps, forward+adjoint",
+            "forward_ms": round(t_fwd, 3), "grad_forward_ms": round(t_f, 3), "grad_backward_ms": round(t_b, 3),
+            "fwd_adj_ms": round(t_f + t_b, 3), "ratio_to_forward": round((t_f + t_b) / t_fwd, 3),
+            "sequential_fwd_adj_ms": round(t_s, 3), "speedup_vs_sequential": round(t_s / (t_f + t_b), 3),
+            "Gcell_updates_per_s_fwd_adj": round(cells * steps / ((t_f + t_b) * 1e-3) / 1e9, 2),
+            "config": bt.config()}
+
+
 def calib_copy(gib=1.0, reps=5):
     """A plain device copy of known size (for scaling rocprofv3 byte counters);
     returns its size and achieved bandwidth (read + write bytes per second)."""
@@ -290,12 +367,12 @@ def main():
     ap.add_argument("--no-adj", action="store_true")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
+    ap.add_argument("--grad-batch-only", action="store_true", help="only the batched gradient measurement")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 1024x256x256 sustained run and the 64-box batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -304,6 +381,9 @@ def main():
 
     if args.adj_only:
         print(json.dumps({"fwd_adj": fwd_adj_ratio()}), flush=True)
+        return
+    if args.grad_batch_only:
+        print(json.dumps({"batched_grads_16x96cube": batched_grads()}), flush=True)
         return
     steps = args.steps + (args.steps & 1)  # the fused kernel runs in pairs
     fields, coeffs, dt, f64 = make_inputs(SHAPE, torch.float32)
@@ -371,6 +451,8 @@ def main():
         line["sustained_1024x256x256"] = sustained_large()
         torch.cuda.empty_cache()
         line["batched_64_boxes"] = batched_boxes()
+        torch.cuda.empty_cache()
+        line["batched_grads_16x96cube"] = batched_grads()
         torch.cuda.empty_cache()
     if args.calib:
         line["calib_copy"] = calib_copy()

@@ -272,6 +272,24 @@ int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_y, int *zsplit, int *grid,
 int xfdtd_batch_run(xfdtd_batch_t b, int64_t n);
 int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
 
+/*
+ * Batched checkpointed gradients: the single-box schedule of
+ * xfdtd_grad_forward / xfdtd_grad_backward for every box of the batch at once
+ * (same n and seg for all boxes), one batched launch per step.
+ *   bytes[m] / ws[m] / ws_bytes[m] : one workspace per box (device,
+ *       256-byte aligned, caller-owned), sized by xfdtd_batch_grad_workspace.
+ *   lam[m*6] : device, dL/d(final state) of each box in, dL/d(initial state)
+ *       out (box-major, Ex..Bz).
+ *   grad : host, m*12 doubles, dL/dcoeffs of each box.
+ * The forward leaves the final states in the bound fields.  Both synchronise
+ * the stream and allocate small internal buffers (launch descriptors).
+ */
+int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t *bytes);
+int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws,
+                             const uint64_t *ws_bytes);
+int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws,
+                              const uint64_t *ws_bytes, void *const *lam, double *grad);
+
 #ifdef __cplusplus
 }
 #endif

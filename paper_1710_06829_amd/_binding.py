@@ -65,6 +65,10 @@ SIGNATURES = {
                                 ctypes.POINTER(_int)], _int),
     "xfdtd_batch_run": ([_vp, _i64], _int),
     "xfdtd_batch_run_eager": ([_vp, _i64], _int),
+    "xfdtd_batch_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),
+    "xfdtd_batch_grad_forward": ([_vp, _i64, _i64, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)], _int),
+    "xfdtd_batch_grad_backward": ([_vp, _i64, _i64, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(_vp), _dp], _int),
 }
 
 

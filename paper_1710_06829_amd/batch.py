@@ -80,6 +80,44 @@ class Batch:
         fn = B.lib().xfdtd_batch_run if graph else B.lib().xfdtd_batch_run_eager
         B.check(fn(self._h, int(n)))
 
+    def grad_workspaces(self, n, seg=0):
+        """Allocate one gradient workspace per box (uint8 CUDA tensors)."""
+        b = (ctypes.c_uint64 * self.m)()
+        B.check(B.lib().xfdtd_batch_grad_workspace(self._h, int(n), int(seg), b))
+        return [torch.empty(max(256, b[i]), dtype=torch.uint8, device=self.device) for i in range(self.m)]
+
+    def _ws_args(self, ws):
+        ws = list(ws)
+        if len(ws) != self.m:
+            raise ValueError(f"need {self.m} workspaces, got {len(ws)}")
+        for w in ws:
+            if w.dtype != torch.uint8 or w.device != self.device or not w.is_contiguous():
+                raise ValueError("workspaces must be contiguous uint8 tensors on the batch device")
+        ptrs = (ctypes.c_void_p * self.m)(*[w.data_ptr() for w in ws])
+        sizes = (ctypes.c_uint64 * self.m)(*[w.numel() for w in ws])
+        return ptrs, sizes
+
+    def grad_forward(self, n, ws, seg=0):
+        """n steps of every box, storing checkpoints in ``ws``."""
+        p, sz = self._ws_args(ws)
+        B.check(B.lib().xfdtd_batch_grad_forward(self._h, int(n), int(seg), p, sz))
+
+    def grad_backward(self, n, ws, lams, seg=0):
+        """lams: per box six tensors dL/d(final state) in, dL/d(initial state)
+        out.  Returns the per-box coefficient gradients (m lists of 12)."""
+        p, sz = self._ws_args(ws)
+        lams = [list(l) for l in lams]
+        if len(lams) != self.m or any(len(l) != 6 for l in lams):
+            raise ValueError("need six adjoint tensors per box")
+        for f, l in zip(self.fields, lams):
+            for a, t in zip(f, l):
+                if t.shape != a.shape or t.dtype != a.dtype or t.device != a.device or not t.is_contiguous():
+                    raise ValueError("adjoint tensors must match their box's fields")
+        la = (ctypes.c_void_p * (6 * self.m))(*[t.data_ptr() for l in lams for t in l])
+        g = (ctypes.c_double * (12 * self.m))()
+        B.check(B.lib().xfdtd_batch_grad_backward(self._h, int(n), int(seg), p, sz, la, g))
+        return [[g[12 * i + j] for j in range(12)] for i in range(self.m)]
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             B.lib().xfdtd_batch_destroy(self._h)

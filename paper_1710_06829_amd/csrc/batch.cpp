@@ -59,6 +59,13 @@ struct xfdtd_batch_s {
     hipGraphExec_t gexec = nullptr;
     int64_t graph_n = -1;
     std::string key;
+    // batched gradient: adjoint work list, per-item gradient sums, per-box
+    // item ranges, scales and accumulators
+    int2 *d_aitems = nullptr;
+    int naitems = 0;
+    double *d_apart = nullptr;
+    int *d_afirst = nullptr;
+    double *d_scale = nullptr, *d_grad = nullptr;
 };
 
 namespace {
@@ -229,6 +236,9 @@ void xfdtd_batch_destroy(xfdtd_batch_t b)
     drop_graph(b);
     if (b->d_boxes) hipFree(b->d_boxes);
     if (b->d_items) hipFree(b->d_items);
+    for (void *p : {(void *)b->d_aitems, (void *)b->d_apart, (void *)b->d_afirst, (void *)b->d_scale,
+                    (void *)b->d_grad})
+        if (p) hipFree(p);
     if (b->capture) hipStreamDestroy(b->capture);
     delete b;
 }
@@ -400,6 +410,341 @@ int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n)
     }
     for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->stream);
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched checkpointed gradient (the single-box schedule of host.cpp, run for
+// all boxes at once: one batched launch per step)
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t box_field_bytes(const xfdtd_batch_s *b, int64_t i)
+{
+    const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
+    const size_t by = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
+    return (by + 255) / 256 * 256;
+}
+
+int64_t bseg(int64_t n, int64_t seg)
+{
+    if (seg > 0) return seg;
+    int64_t s = (int64_t)ceil(sqrt((double)(n > 0 ? n : 1)));
+    return s < 1 ? 1 : s;
+}
+
+uint64_t bws_arrays(int64_t n, int64_t seg)
+{
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    return (uint64_t)(6 * nck + 12 + 3 * (seg - 1));
+}
+
+template <typename T>
+struct BoxWs {  // the workspace of one box, addressed like host.cpp's layout
+    char *ws;
+    size_t fb;
+    int64_t nck;
+    Fields<T> state(int64_t first) const
+    {
+        Fields<T> f;
+        for (int c = 0; c < 6; ++c) f.c[c] = (T *)(ws + (size_t)(first + c) * fb);
+        return f;
+    }
+    Fields<T> ck(int64_t m) const { return state(6 * m); }
+    Fields<T> A() const { return state(6 * nck); }
+    Fields<T> B() const { return state(6 * nck + 6); }
+    T *segE(int64_t i, int c) const { return (T *)(ws + (size_t)(6 * nck + 12 + 3 * (i - 1) + c) * fb); }
+};
+
+template <typename T>
+BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, const Fields<T> &out)
+{
+    const xfdtd_grid &g = b->g[i];
+    BoxDesc<T> d;
+    d.f = in;
+    d.s = out;
+    d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
+    const double sp[3] = {g.dx, g.dy, g.dz};
+    d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
+    int zc = (int)((g.nz + b->cfg.zsplit - 1) / b->cfg.zsplit);
+    if (zc < 4) zc = (int)std::min<int64_t>(4, g.nz);
+    d.zchunk = zc;
+    d.ntx = (int)((g.nx + 63) / 64);
+    d.nty = (int)((g.ny + b->cfg.tile_y - 1) / b->cfg.tile_y);
+    d.pad = 0;
+    return d;
+}
+
+int adj_tile(const xfdtd_batch_s *b) { return b->dtype == XFDTD_F64 ? 4 : (b->cfg.tile_y > 8 ? 8 : b->cfg.tile_y); }
+
+template <typename T>
+AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, const Fields<T> &lout,
+                    T *const en[3])
+{
+    const BoxDesc<T> f = fwd_desc<T>(b, i, lin, lout);
+    AdjDesc<T> a;
+    a.lin = lin;
+    a.lout = lout;
+    for (int c = 0; c < 3; ++c) a.en[c] = en[c];
+    a.d = f.d;
+    a.w = f.w;
+    a.zchunk = f.zchunk;
+    a.ntx = f.ntx;
+    a.nty = (int)((b->g[i].ny + adj_tile(b) - 1) / adj_tile(b));
+    a.pad = 0;
+    return a;
+}
+
+// adjoint work list (tile height adj_tile), item ranges per box, scales
+template <typename T>
+int build_adjoint(xfdtd_batch_t b)
+{
+    std::vector<int2> items;
+    std::vector<int> first;
+    std::vector<double> scale;
+    Fields<T> z;
+    for (int c = 0; c < 6; ++c) z.c[c] = nullptr;
+    T *en0[3] = {nullptr, nullptr, nullptr};
+    for (int64_t i = 0; i < b->m; ++i) {
+        const AdjDesc<T> a = adj_desc<T>(b, i, z, z, en0);
+        first.push_back((int)items.size());
+        const int nzc = (a.d.nz + a.zchunk - 1) / a.zchunk;
+        const int64_t nt = (int64_t)a.ntx * a.nty * nzc;
+        for (int64_t t = 0; t < nt; ++t) items.push_back(make_int2((int)i, (int)t));
+        const double sp[3] = {b->g[i].dx, b->g[i].dy, b->g[i].dz};
+        for (int j = 0; j < 12; ++j) scale.push_back(b->dt[i] / sp[j / 4]);
+    }
+    first.push_back((int)items.size());
+    for (void *p : {(void *)b->d_aitems, (void *)b->d_apart, (void *)b->d_afirst, (void *)b->d_scale,
+                    (void *)b->d_grad})
+        if (p) hipFree(p);
+    b->d_aitems = nullptr;
+    b->d_apart = nullptr;
+    b->d_afirst = nullptr;
+    b->d_scale = nullptr;
+    b->d_grad = nullptr;
+    BTRY(hipMalloc((void **)&b->d_aitems, sizeof(int2) * items.size()), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_apart, sizeof(double) * 12 * items.size()), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_afirst, sizeof(int) * first.size()), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_scale, sizeof(double) * scale.size()), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_grad, sizeof(double) * scale.size()), "hipMalloc");
+    BTRY(hipMemcpy(b->d_aitems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    BTRY(hipMemcpy(b->d_afirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    BTRY(hipMemcpy(b->d_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    b->naitems = (int)items.size();
+    return XFDTD_OK;
+}
+
+template <typename T>
+int upload(std::vector<T> &host, T **dev)
+{
+    *dev = nullptr;
+    if (host.empty()) return XFDTD_OK;
+    BTRY(hipMalloc((void **)dev, sizeof(T) * host.size()), "hipMalloc");
+    BTRY(hipMemcpy(*dev, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    return XFDTD_OK;
+}
+
+template <typename T>
+int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
+{
+    const int64_t m = b->m;
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    const int64_t s0_last = (nck - 1) * seg;
+    std::vector<BoxWs<T>> W(m);
+    std::vector<Fields<T>> cur(m), fields(m);
+    for (int64_t i = 0; i < m; ++i) {
+        W[i] = BoxWs<T>{(char *)ws[i], box_field_bytes(b, i), nck};
+        for (int c = 0; c < 6; ++c) fields[i].c[c] = (T *)b->f[6 * i + c];
+        const Fields<T> ck0 = W[i].ck(0);
+        const size_t raw = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * sizeof(T);
+        for (int c = 0; c < 6; ++c)
+            BTRY(hipMemcpyAsync(ck0.c[c], fields[i].c[c], raw, hipMemcpyDeviceToDevice, b->stream), "hipMemcpyAsync");
+        cur[i] = ck0;
+    }
+    std::vector<BoxDesc<T>> descs;
+    descs.reserve((size_t)(n * m));
+    for (int64_t s = 0; s < n; ++s)
+        for (int64_t i = 0; i < m; ++i) {
+            Fields<T> dst;
+            const Fields<T> A = W[i].A(), Bs = W[i].B();
+            if (s + 1 == n) {
+                dst = fields[i];
+            } else if ((s + 1) % seg == 0) {
+                dst = W[i].ck((s + 1) / seg);
+            } else if (s >= s0_last) {
+                for (int c = 0; c < 3; ++c) {
+                    dst.c[c] = W[i].segE(s + 1 - s0_last, c);
+                    dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
+                }
+            } else {
+                dst = (cur[i].c[0] == A.c[0]) ? Bs : A;
+            }
+            descs.push_back(fwd_desc<T>(b, i, cur[i], dst));
+            cur[i] = dst;
+        }
+    BoxDesc<T> *d_descs = nullptr;
+    BTRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    int rc = upload(descs, &d_descs);
+    if (rc) return rc;
+    for (int64_t s = 0; s < n && !rc; ++s) {
+        hipError_t e = launch_batched<T>(d_descs + s * m, b->d_items, b->nitems, 0, b->cfg.tile_y, grid_of(b),
+                                         b->stream);
+        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched launch: %s", hipGetErrorString(e));
+    }
+    hipStreamSynchronize(b->stream);
+    if (d_descs) hipFree(d_descs);
+    return rc;
+}
+
+template <typename T>
+int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, void *const *lam, double *grad)
+{
+    const int64_t m = b->m;
+    int rc = build_adjoint<T>(b);
+    if (rc) return rc;
+    const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
+    std::vector<BoxWs<T>> W(m);
+    std::vector<Fields<T>> lamU(m), lamS(m), lcur(m), lnext(m);
+    for (int64_t i = 0; i < m; ++i) {
+        W[i] = BoxWs<T>{(char *)ws[i], box_field_bytes(b, i), nck};
+        for (int c = 0; c < 6; ++c) lamU[i].c[c] = (T *)lam[6 * i + c];
+        lamS[i] = W[i].B();
+        lcur[i] = lamU[i];
+        lnext[i] = lamS[i];
+    }
+    // descriptors of every launch, in launch order
+    std::vector<BoxDesc<T>> rdesc;
+    std::vector<AdjDesc<T>> adesc;
+    struct Launch {
+        int kind;  // 0 recompute, 1 adjoint
+        int64_t off;
+    };
+    std::vector<Launch> order;
+    for (int64_t mseg = nck - 1; mseg >= 0 && n > 0; --mseg) {
+        const int64_t s0 = mseg * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        if (mseg != nck - 1) {
+            std::vector<Fields<T>> in(m);
+            for (int64_t i = 0; i < m; ++i) in[i] = W[i].ck(mseg);
+            for (int64_t s = s0; s + 1 < s1; ++s) {
+                order.push_back({0, (int64_t)rdesc.size()});
+                for (int64_t i = 0; i < m; ++i) {
+                    Fields<T> out;
+                    const Fields<T> A = W[i].A();
+                    for (int c = 0; c < 3; ++c) {
+                        out.c[c] = W[i].segE(s + 1 - s0, c);
+                        out.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
+                    }
+                    rdesc.push_back(fwd_desc<T>(b, i, in[i], out));
+                    in[i] = out;
+                }
+            }
+        }
+        for (int64_t s = s1 - 1; s >= s0; --s) {
+            order.push_back({1, (int64_t)adesc.size()});
+            for (int64_t i = 0; i < m; ++i) {
+                T *en[3];
+                for (int c = 0; c < 3; ++c) en[c] = (s == s0) ? W[i].ck(mseg).c[c] : W[i].segE(s - s0, c);
+                adesc.push_back(adj_desc<T>(b, i, lcur[i], lnext[i], en));
+                std::swap(lcur[i], lnext[i]);
+            }
+        }
+    }
+    BoxDesc<T> *d_r = nullptr;
+    AdjDesc<T> *d_a = nullptr;
+    BTRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    rc = upload(rdesc, &d_r);
+    if (!rc) rc = upload(adesc, &d_a);
+    if (!rc) {
+        hipError_t e = hipMemsetAsync(b->d_grad, 0, sizeof(double) * 12 * m, b->stream);
+        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    }
+    // adjoint grid: the tuned persistent size if one is set, else one
+    // workgroup per item
+    const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems) ? b->cfg.grid : b->naitems;
+    bool first = true;
+    for (size_t k = 0; k < order.size() && !rc; ++k) {
+        hipError_t e;
+        if (order[k].kind == 0) {
+            e = launch_batched<T>(d_r + order[k].off, b->d_items, b->nitems, 0, b->cfg.tile_y, grid_of(b),
+                                  b->stream);
+        } else {
+            e = launch_batched_adjoint<T>(d_a + order[k].off, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
+                                          adj_tile(b), ga, b->stream);
+            first = false;
+        }
+        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
+    }
+    if (!rc && !first) {
+        hipError_t e = launch_reduce_boxes(b->d_apart, b->d_afirst, (int)m, b->d_scale, b->d_grad, b->stream);
+        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "reduce launch: %s", hipGetErrorString(e));
+    }
+    for (int64_t i = 0; i < m && !rc; ++i)
+        if (lcur[i].c[0] != lamU[i].c[0]) {
+            const size_t raw = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * sizeof(T);
+            for (int c = 0; c < 6 && !rc; ++c) {
+                hipError_t e = hipMemcpyAsync(lamU[i].c[c], lcur[i].c[c], raw, hipMemcpyDeviceToDevice, b->stream);
+                if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+            }
+        }
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(grad, b->d_grad, sizeof(double) * 12 * m, hipMemcpyDeviceToHost, b->stream);
+        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (!rc && e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    if (d_r) hipFree(d_r);
+    if (d_a) hipFree(d_a);
+    return rc;
+}
+
+int check_bws(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)
+{
+    if (!b) return set_error(XFDTD_EINVAL, "null handle");
+    if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
+    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
+    if (!ws || !ws_bytes) return set_error(XFDTD_EINVAL, "null workspace list");
+    for (int64_t i = 0; i < b->m; ++i) {
+        if (!ws[i] || (uintptr_t)ws[i] % 256) return set_error(XFDTD_EINVAL, "box %lld: workspace null or not 256-byte aligned", (long long)i);
+        const uint64_t need = bws_arrays(n, seg) * box_field_bytes(b, i);
+        if (ws_bytes[i] < need) return set_error(XFDTD_EINVAL, "box %lld: workspace too small", (long long)i);
+    }
+    return XFDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t *bytes)
+{
+    if (!b || !bytes) return set_error(XFDTD_EINVAL, "null argument");
+    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
+    seg = bseg(n, seg);
+    for (int64_t i = 0; i < b->m; ++i) bytes[i] = bws_arrays(n, seg) * box_field_bytes(b, i);
+    return XFDTD_OK;
+}
+
+int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)
+{
+    seg = bseg(n, seg);
+    int rc = check_bws(b, n, seg, ws, ws_bytes);
+    if (rc) return rc;
+    return b->dtype == XFDTD_F32 ? bgrad_forward_t<float>(b, n, seg, ws) : bgrad_forward_t<double>(b, n, seg, ws);
+}
+
+int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes,
+                              void *const *lam, double *grad)
+{
+    seg = bseg(n, seg);
+    int rc = check_bws(b, n, seg, ws, ws_bytes);
+    if (rc) return rc;
+    if (!lam || !grad) return set_error(XFDTD_EINVAL, "null argument");
+    for (int64_t i = 0; i < 6 * b->m; ++i)
+        if (!lam[i]) return set_error(XFDTD_EINVAL, "lam[%lld] is null", (long long)i);
+    return b->dtype == XFDTD_F32 ? bgrad_backward_t<float>(b, n, seg, ws, lam, grad)
+                                 : bgrad_backward_t<double>(b, n, seg, ws, lam, grad);
 }
 
 }  // extern "C"

@@ -48,22 +48,32 @@ constexpr int ATILE_X = 64;
 // iteration k-1).  accumulate != 0 adds this step's sums to `partials`
 // (each workgroup owns its 12 slots), else overwrites them.
 template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
-    Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
-    const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
-    double *__restrict__ partials, int accumulate)
-{
-    constexpr int PX = ATILE_X + 4;
-    constexpr int PY = TY + 4;
-    constexpr int P = PX * PY;
-    __shared__ T LEbuf[2][3][P];  // lE'(k+1), lE'(k+2)
-    __shared__ T Mbuf[2][3][P];   // mu(k), mu(k+1)
-    __shared__ T Sbuf[2][6][P];   // stars of mu at planes k-1, k
-    __shared__ double red[12][TY + 5];
+struct AdjSmem {
+    static constexpr int PX = ATILE_X + 4;
+    static constexpr int PY = TY + 4;
+    static constexpr int P = PX * PY;
+    T LEbuf[2][3][P];  // lE'(k+1), lE'(k+2)
+    T Mbuf[2][3][P];   // mu(k), mu(k+1)
+    T Sbuf[2][6][P];   // stars of mu at planes k-1, k
+    double red[12][TY + 5];
+};
 
-    const int nb = gridDim.x, bid = blockIdx.x;
-    const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
-    const int logical = xcd * q + min(xcd, r) + (bid >> 3);
+// One tile (number `logical`) of the adjoint step.  slot: this tile's 12
+// gradient sums (written, or added to when accumulate != 0).
+template <typename T, int TY>
+__device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<T> &lout,
+                                             const T *__restrict__ en_x, const T *__restrict__ en_y,
+                                             const T *__restrict__ en_z, const Dims &d, const Weights<T> &w,
+                                             int zchunk, int ntx, int nty, int logical, AdjSmem<T, TY> &sm,
+                                             double *__restrict__ slot, int accumulate)
+{
+    constexpr int PX = AdjSmem<T, TY>::PX;
+    constexpr int PY = AdjSmem<T, TY>::PY;
+    constexpr int P = AdjSmem<T, TY>::P;
+    auto &LEbuf = sm.LEbuf;
+    auto &Mbuf = sm.Mbuf;
+    auto &Sbuf = sm.Sbuf;
+    auto &red = sm.red;
     const int tx = logical % ntx;
     const int rest = logical / ntx;
     const int ty = rest % nty;
@@ -278,9 +288,70 @@ __global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
     if (threadIdx.x < 12) {
         double v = 0.0;
         for (int wv = 0; wv < TY + 5; ++wv) v += red[threadIdx.x][wv];
-        double *slot = partials + (int64_t)blockIdx.x * 12 + threadIdx.x;
-        *slot = accumulate ? *slot + v : v;
+        slot[threadIdx.x] = accumulate ? slot[threadIdx.x] + v : v;
     }
+}
+
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
+    Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
+    const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
+    double *__restrict__ partials, int accumulate)
+{
+    __shared__ AdjSmem<T, TY> sm;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
+    const int logical = xcd * q + min(xcd, r) + (bid >> 3);
+    adjoint_tile<T, TY>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, logical, sm,
+                        partials + (int64_t)blockIdx.x * 12, accumulate);
+}
+
+// Batched adjoint step: work item i is tile items[i].y of box items[i].x;
+// its 12 gradient sums live at partials[12 i] (the item list is fixed for a
+// batch, so the sums accumulate per item across steps).
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * (TY + 5)) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
+                                                                        const int2 *__restrict__ items,
+                                                                        int nitems, double *__restrict__ partials,
+                                                                        int accumulate)
+{
+    __shared__ AdjSmem<T, TY> sm;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
+    const int slot = xcd * q + min(xcd, r) + (bid >> 3);
+    for (int base = 0; base < nitems; base += gridDim.x) {
+        const int i = base + slot;
+        if (i >= nitems) break;
+        const int2 it = items[i];
+        const AdjDesc<T> &b = boxes[it.x];
+        adjoint_tile<T, TY>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
+                            partials + (int64_t)i * 12, accumulate);
+        __syncthreads();
+    }
+}
+
+// grad[12 b + j] += scale[12 b + j] * sum of partials over box b's items
+// [first[b], first[b+1]); one block per box, fixed order.
+__global__ __launch_bounds__(256) void reduce_boxes_kernel(const double *__restrict__ partials,
+                                                           const int *__restrict__ first,
+                                                           const double *__restrict__ scale,
+                                                           double *__restrict__ grad)
+{
+    __shared__ double sm[12][256];
+    const int b = blockIdx.x;
+    const int i0 = first[b], i1 = first[b + 1];
+    for (int j = 0; j < 12; ++j) {
+        double v = 0.0;
+        for (int i = i0 + threadIdx.x; i < i1; i += 256) v += partials[(int64_t)i * 12 + j];
+        sm[j][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int j = 0; j < 12; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) grad[12 * b + threadIdx.x] += scale[12 * b + threadIdx.x] * sm[threadIdx.x][0];
 }
 
 // grad[j] += scale[j] * sum_b partials[b][j], one block, fixed order.
@@ -343,6 +414,38 @@ hipError_t launch_reduce_partials(const double *partials, int nblocks, const Sca
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, int nitems, double *partials,
+                                 int accumulate, int tile_y, int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (grid <= 0 || grid > nitems) grid = nitems;
+    switch (tile_y) {
+    case 4:
+        hipLaunchKernelGGL((batched_adjoint_kernel<T, 4>), dim3(grid), dim3(64 * 9), 0, s, boxes, items, nitems,
+                           partials, accumulate);
+        break;
+    case 8:
+        hipLaunchKernelGGL((batched_adjoint_kernel<T, 8>), dim3(grid), dim3(64 * 13), 0, s, boxes, items, nitems,
+                           partials, accumulate);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
+                               double *grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_boxes_kernel, dim3(nboxes), dim3(256), 0, s, partials, first, scale, grad);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batched_adjoint<float>(const AdjDesc<float> *, const int2 *, int, double *, int, int,
+                                                  int, hipStream_t);
+template hipError_t launch_batched_adjoint<double>(const AdjDesc<double> *, const int2 *, int, double *, int, int,
+                                                   int, hipStream_t);
 template hipError_t launch_adjoint<float>(const Fields<float> &, const Fields<float> &, const float *const[3],
                                           Dims, const Weights<float> &, int, int, double *, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const Fields<double> &, const Fields<double> &,

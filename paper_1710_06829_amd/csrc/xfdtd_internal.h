@@ -71,6 +71,21 @@ template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
                           const Weights<T> &w, int tile_y, int zchunk, double *partials, int accumulate,
                           hipStream_t s);
+// One box of a batched adjoint step: lambda in/out, the step's primal E.
+template <typename T>
+struct AdjDesc {
+    Fields<T> lin, lout;
+    const T *en[3];
+    Dims d;
+    Weights<T> w;
+    int zchunk, ntx, nty, pad;
+};
+template <typename T>
+hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, int nitems, double *partials,
+                                 int accumulate, int tile_y, int grid, hipStream_t s);
+// grad[12b + j] += scale[12b + j] * sum_{i in [first[b], first[b+1])} partials[12i + j]
+hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
+                               double *grad, hipStream_t s);
 // grad[j] += sc.s[j] * sum over blocks of partials[b*12 + j]
 hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
                                   hipStream_t s);

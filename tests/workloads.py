@@ -78,3 +78,26 @@ def c3_boxes(count=64):
         shape = (nz, ny, nx)
         out.append((shape, S.uniform_fields(shape, 400 + b), c, dt))
     return out
+
+
+def c5_boxes(count=16, shape=(96, 96, 96), steps=300):
+    """Batched coefficient tuning: ``count`` boxes of 96^3 holding the same
+    pulse (wavelength 12, waist 16, duration 16 cells, centred at x0 = nx/2,
+    plus 1e-3 noise, seed 521), box b with its own extended set (seed
+    520 + 10 b) and dt = 0.95 x its stability bound; the loss of box b is the
+    probe misfit against its own translated target.  Returns
+    [(fields, coeffs, dt, sp, xp, tgt)]."""
+    nz, ny, nx = shape
+    lam, w0, dur, x0 = 12.0, 16.0, 16.0, 0.5 * nx
+    sp = (1.0, 1.0, 1.0)
+    out = []
+    for b in range(count):
+        beta, delta = S.extended_beta_delta(520 + 10 * b)
+        c = O.coeffs_from(beta, delta)
+        dt = 0.95 * O.cfl_dt(c, sp)
+        f = S.gaussian_pulse(shape, dt, wavelength=lam, waist=w0, duration=dur, x0=x0)
+        f = S.add_noise(f, 1e-3, 521)
+        xp, tgt = pulse_target_loss_setup(shape, steps, lam, w0, dur, x0, dt)
+        out.append((f, c, dt, sp, xp, tgt))
+    return out
+
