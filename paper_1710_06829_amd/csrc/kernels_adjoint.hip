@@ -22,6 +22,8 @@
 // per cell: read lE', lB', E (9 values), write lE, lB (6 values).
 // Per-workgroup gradient sums (unscaled, FP64) go to `partials`.
 
+#include <type_traits>
+
 #include "xfdtd_internal.h"
 
 namespace xfdtd {
@@ -55,6 +57,7 @@ struct AdjSmem {
     T LEbuf[2][3][P];  // lE'(k+1), lE'(k+2)
     T Mbuf[2][3][P];   // mu(k), mu(k+1)
     T Sbuf[2][6][P];   // stars of mu at planes k-1, k
+    T Ebuf[2][3][P];   // primal E(k), E(k+1)
     double red[12][TY + 5];
 };
 
@@ -73,6 +76,7 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     auto &LEbuf = sm.LEbuf;
     auto &Mbuf = sm.Mbuf;
     auto &Sbuf = sm.Sbuf;
+    auto &Ebuf = sm.Ebuf;
     auto &red = sm.red;
     const int tx = logical % ntx;
     const int rest = logical / ntx;
@@ -104,45 +108,45 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     const int64_t nxy = (int64_t)d.nx * d.ny;
     const int gyc = valid ? wrapa(y0 + ry, d.ny) : 0, gxc = valid ? wrapa(x0 + rx, d.nx) : 0;
     const int col = gyc * d.nx + gxc;
-    // the primal E neighbours the gradient needs (x+1 and y+1 columns)
-    const int colx1 = isO ? gyc * d.nx + wrapa(x0 + rx + 1, d.nx) : 0;
-    const int coly1 = isO ? wrapa(y0 + ry + 1, d.ny) * d.nx + gxc : 0;
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
     const T *en[3] = {en_x, en_y, en_z};
 
     // own-column queues: la = lE'(k-1), l0 = lE'(k), l1 = lE'(k+1);
     // mm, mc = mu(k-1), mu(k); sp0/sp3 and sq0/sq3 = stars 0 and 3 at k-1 and
-    // k-2; n0 = E(k), nn = E(k) neighbours (x+1: Ez, Ey; y+1: Ez, Ex)
-    T la[3], l0[3], l1[3], epf[3], bpf[3], npf[3], nnpf[4], n0[3], nn[4];
+    // k-2; n0 = E(k), staged in LDS for the x+1 and y+1 neighbours that the
+    // gradient needs.  Prefetched values (lE'(k+2), lB'(k+1), E(k+1))
+    // alternate between two register sets, so a load issued in one iteration
+    // is first waited for in the next (a single rotating set would make the
+    // compiler wait for it at the loop back-edge, with the iteration's stores).
+    T la[3], l0[3], l1[3], n0[3];
+    T pe[2][3], pb[2][3], pn[2][3];
     T mm[3], mc[3], sp0 = T(0), sp3 = T(0), sq0 = T(0), sq3 = T(0);
     double acc[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) acc[j] = 0.0;
-    int eb = 0, mb = 0, sb = 0;
 
     // plane trackers (k starts at k0 - 3): w3 = k+3 (lE' prefetch),
-    // wb = k+1 -> k+2 (lB' prefetch), wn = k+1 -> k+2 (primal E prefetch:
-    // neighbours of plane k+1, own value of plane k+2), wm = k-1 (outputs)
+    // wb = k+1 -> k+2 (lB' prefetch), wn = k+1 -> k+2 (primal E prefetch),
+    // wm = k-1 (outputs)
     int w3 = wrapa(k0, nz), wb = wrapa(k0 - 2, nz), wn = wrapa(k0 - 2, nz), wm = wrapa(k0 - 4, nz);
     {
-        const int64_t pa = (int64_t)wrapa(k0 - 2, nz) * nxy, pb = (int64_t)wrapa(k0 - 1, nz) * nxy;
-        const int64_t pn = (int64_t)wrapa(k0 - 3, nz) * nxy;
+        const int64_t pa = (int64_t)wrapa(k0 - 2, nz) * nxy, pq = (int64_t)wrapa(k0 - 1, nz) * nxy;
+        const int64_t pm = (int64_t)wrapa(k0 - 3, nz) * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             l1[c] = lin.c[c][pa + col];
-            epf[c] = lin.c[c][pb + col];
-            bpf[c] = lin.c[3 + c][pa + col];
-            npf[c] = en[c][pa + col];
-            n0[c] = en[c][pn + col];
+            pe[0][c] = lin.c[c][pq + col];
+            pb[0][c] = lin.c[3 + c][pa + col];
+            pn[0][c] = en[c][pa + col];
+            n0[c] = en[c][pm + col];
         }
-        nnpf[0] = en_z[pn + colx1];
-        nnpf[1] = en_y[pn + colx1];
-        nnpf[2] = en_z[pn + coly1];
-        nnpf[3] = en_x[pn + coly1];
         if (isE) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) LEbuf[0][c][li] = l1[c];
+            for (int c = 0; c < 3; ++c) {
+                LEbuf[0][c][li] = l1[c];
+                Ebuf[0][c][li] = n0[c];
+            }
         }
     }
 #pragma unroll
@@ -150,36 +154,36 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     __syncthreads();
 
     const int klast = k0 + KZe - 1;
-    for (int k = k0 - 3; k <= klast + 1; ++k) {
+    // One plane iteration.  B = k & 1 relative to k0 - 3: LDS buffer parity
+    // and prefetch register set (set B is consumed, set B^1 refilled).
+    auto plane = [&](auto parity, int k) {
+        constexpr int B = decltype(parity)::value;
+        constexpr int eb = B, mb = B, sb = B;
         T l2[3], bo[3], n1[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l2[c] = epf[c];  // lE'(k+2)
-            bo[c] = bpf[c];  // lB'(k+1)
-            n1[c] = npf[c];  // E(k+1)
+            l2[c] = pe[B][c];  // lE'(k+2)
+            bo[c] = pb[B][c];  // lB'(k+1)
+            n1[c] = pn[B][c];  // E(k+1)
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) nn[m] = nnpf[m];  // E(k) neighbours
         {
             const int64_t p3 = (int64_t)w3 * nxy;
-            const int64_t pn1 = (int64_t)wn * nxy;  // wn = k+1: neighbours of E(k+1)
             wb = inc(wb);
             wn = inc(wn);
-            const int64_t pb = (int64_t)wb * nxy, pn2 = (int64_t)wn * nxy;  // k+2: own E
+            const int64_t pq = (int64_t)wb * nxy, pn2 = (int64_t)wn * nxy;  // k+2: own E
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                epf[c] = lin.c[c][p3 + col];
-                bpf[c] = lin.c[3 + c][pb + col];
-                npf[c] = en[c][pn2 + col];
+                pe[B ^ 1][c] = lin.c[c][p3 + col];
+                pb[B ^ 1][c] = lin.c[3 + c][pq + col];
+                pn[B ^ 1][c] = en[c][pn2 + col];
             }
-            nnpf[0] = en_z[pn1 + colx1];
-            nnpf[1] = en_y[pn1 + colx1];
-            nnpf[2] = en_z[pn1 + coly1];
-            nnpf[3] = en_x[pn1 + coly1];
         }
         if (isE) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) LEbuf[eb ^ 1][c][li] = l2[c];
+            for (int c = 0; c < 3; ++c) {
+                LEbuf[eb ^ 1][c][li] = l2[c];
+                Ebuf[eb ^ 1][c][li] = n1[c];
+            }
         }
 
         // mu(k+1) = lB'(k+1) + L^T lE' (lanes outside the mu region read the
@@ -222,8 +226,8 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             if (isO && k >= k0) {
                 // coefficient gradient at plane k: forward differences of E(k)
                 const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
-                const T gxEz = nn[0] - n0[2], gxEy = nn[1] - n0[1];
-                const T gyEz = nn[2] - n0[2], gyEx = nn[3] - n0[0];
+                const T gxEz = Ebuf[eb][2][li + 1] - n0[2], gxEy = Ebuf[eb][1][li + 1] - n0[1];
+                const T gyEz = Ebuf[eb][2][li + PX] - n0[2], gyEx = Ebuf[eb][0][li + PX] - n0[0];
                 // axis x (slots 0..3): +g_x[Ez] with mu_y, -g_x[Ey] with mu_z
                 acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
                 acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
@@ -270,11 +274,15 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         sq3 = sp3;
         sp0 = s[0];
         sp3 = s[3];
-        eb ^= 1;
-        mb ^= 1;
-        sb ^= 1;
         w3 = inc(w3);
         wm = inc(wm);
+    };
+    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), two per loop trip
+    for (int k = k0 - 3;; k += 2) {
+        plane(std::integral_constant<int, 0>{}, k);
+        if (k + 1 > klast + 1) break;
+        plane(std::integral_constant<int, 1>{}, k + 1);
+        if (k + 2 > klast + 1) break;
     }
 
     // workgroup reduction of the 12 gradient sums (FP64)
@@ -397,10 +405,14 @@ hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *
         hipLaunchKernelGGL((adjoint_step_kernel<T, 4>), dim3(nb), dim3(64 * 9), 0, s, lin, lout, en[0],
                            en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
         break;
-    case 8:
-        hipLaunchKernelGGL((adjoint_step_kernel<T, 8>), dim3(nb), dim3(64 * 13), 0, s, lin, lout, en[0],
-                           en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
-        break;
+    case 8:  // FP32 only: the FP64 tile would exceed the 160 KiB of LDS
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((adjoint_step_kernel<T, 8>), dim3(nb), dim3(64 * 13), 0, s, lin, lout, en[0],
+                               en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
     default:
         return hipErrorInvalidValue;
     }
@@ -425,10 +437,14 @@ hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, in
         hipLaunchKernelGGL((batched_adjoint_kernel<T, 4>), dim3(grid), dim3(64 * 9), 0, s, boxes, items, nitems,
                            partials, accumulate);
         break;
-    case 8:
-        hipLaunchKernelGGL((batched_adjoint_kernel<T, 8>), dim3(grid), dim3(64 * 13), 0, s, boxes, items, nitems,
-                           partials, accumulate);
-        break;
+    case 8:  // FP32 only, as above
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((batched_adjoint_kernel<T, 8>), dim3(grid), dim3(64 * 13), 0, s, boxes, items,
+                               nitems, partials, accumulate);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
     default:
         return hipErrorInvalidValue;
     }
