@@ -9,7 +9,7 @@ Dispersion in Maxwell Solvers" (arXiv:1710.06829), written plainly with numpy in
 float64: gather-form stencils with periodic ``np.roll`` indexing, no tiling, no
 fusion, no reordering beyond the equations.
 
-Conventions (readings of the paper, each one listed in the design doc):
+Conventions (the readings taken where the paper is silent or ambiguous):
   * periodic boundaries on all three axes; c = 1; vacuum (J = 0);
   * arrays have shape (nz, ny, nx), x fastest; component (i, j, k) sits at the
     staggered site given by the index subscripts of the update equations

@@ -36,8 +36,14 @@ __device__ __forceinline__ int wrapa(int v, int n)
     return m < 0 ? m + n : m;
 }
 
+// Global-address-space pointers: the batched kernel reads its pointers from a
+// descriptor in memory, where the compiler would otherwise emit flat accesses
+// (which also hold up every LDS wait until outstanding loads return).
 template <typename T>
-__device__ __forceinline__ void nt_store_a(T *p, T v)
+using gptr_a = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ void nt_store_a(gptr_a<T> p, T v)
 {
     __builtin_nontemporal_store(v, p);
 }
@@ -110,7 +116,14 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     const int col = gyc * d.nx + gxc;
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
-    const T *en[3] = {en_x, en_y, en_z};
+    gptr_a<const T> en[3] = {(gptr_a<const T>)en_x, (gptr_a<const T>)en_y, (gptr_a<const T>)en_z};
+    gptr_a<const T> src[6];
+    gptr_a<T> dst[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        src[c] = (gptr_a<const T>)lin.c[c];
+        dst[c] = (gptr_a<T>)lout.c[c];
+    }
 
     // own-column queues: la = lE'(k-1), l0 = lE'(k), l1 = lE'(k+1);
     // mm, mc = mu(k-1), mu(k); sp0/sp3 and sq0/sq3 = stars 0 and 3 at k-1 and
@@ -135,9 +148,9 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         const int64_t pm = (int64_t)wrapa(k0 - 3, nz) * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l1[c] = lin.c[c][pa + col];
-            pe[0][c] = lin.c[c][pq + col];
-            pb[0][c] = lin.c[3 + c][pa + col];
+            l1[c] = src[c][pa + col];
+            pe[0][c] = src[c][pq + col];
+            pb[0][c] = src[3 + c][pa + col];
             pn[0][c] = en[c][pa + col];
             n0[c] = en[c][pm + col];
         }
@@ -173,8 +186,8 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             const int64_t pq = (int64_t)wb * nxy, pn2 = (int64_t)wn * nxy;  // k+2: own E
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                pe[B ^ 1][c] = lin.c[c][p3 + col];
-                pb[B ^ 1][c] = lin.c[3 + c][pq + col];
+                pe[B ^ 1][c] = src[c][p3 + col];
+                pb[B ^ 1][c] = src[3 + c][pq + col];
                 pn[B ^ 1][c] = en[c][pn2 + col];
             }
         }
@@ -253,11 +266,11 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             const T lx = la[0] + ((sp3 - sq3) - (Sp[4][li] - Sp[4][li - PX]));
             const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (sp0 - sq0));
             const T lz = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
-            nt_store_a(lout.c[0] + po, lx);
-            nt_store_a(lout.c[1] + po, ly);
-            nt_store_a(lout.c[2] + po, lz);
+            nt_store_a(dst[0] + po, lx);
+            nt_store_a(dst[1] + po, ly);
+            nt_store_a(dst[2] + po, lz);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) nt_store_a(lout.c[3 + c] + po, mm[c]);
+            for (int c = 0; c < 3; ++c) nt_store_a(dst[3 + c] + po, mm[c]);
         }
         __syncthreads();
 

@@ -25,6 +25,8 @@
 
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "xfdtd_internal.h"
 
 namespace xfdtd {
@@ -54,6 +56,19 @@ __device__ __forceinline__ T ampere_eval(T e, T wa1, T b1, T b1m, T wa2, T b2, T
 
 template <typename T>
 __device__ __forceinline__ void nt_store(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// Field pointers in the global address space.  The batched kernels read
+// their pointers from a descriptor in memory, so the compiler cannot infer the
+// address space and would emit flat accesses, which also count against the
+// LDS wait counter and so stall every LDS wait on outstanding field loads.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ void nt_store(gptr<T> p, T v)
 {
     __builtin_nontemporal_store(v, p);
 }
@@ -176,6 +191,13 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     auto &Ebuf = sm.Ebuf;
     auto &Gbuf = sm.Gbuf;
     auto &Bbuf = sm.Bbuf;
+    gptr<const T> src[6];
+    gptr<T> dst[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        src[c] = (gptr<const T>)in.c[c];
+        dst[c] = (gptr<T>)out.c[c];
+    }
     const int tx = logical % ntx;
     const int rest = logical / ntx;
     const int ty = rest % nty;
@@ -217,20 +239,22 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
 
     // per position: ea = E(k-1), e0 = E(k), e1 = E(k+1); g at k-1, k;
-    // b1 = B^{n+1/2}(k-1), b2 = B^{n+1/2}(k-2) (x, y components)
-    T ea[R][3], e0[R][3], e1[R][3], epf[R][3], bpf[R][3], gm[R][6], gc[R][6], b1[R][3], b2[R][2];
-    int eb = 0, gb = 0, bb = 0;
+    // b1 = B^{n+1/2}(k-1), b2 = B^{n+1/2}(k-2) (x, y components).  The
+    // prefetched E(k+2) and B^{n-1/2}(k) alternate between two register sets
+    // (pe, pb): a load issued in one iteration is first waited for in the
+    // next, instead of at the loop back-edge together with the stores.
+    T ea[R][3], e0[R][3], e1[R][3], pe[2][R][3], pb[2][R][3], gm[R][6], gc[R][6], b1[R][3], b2[R][2];
     int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), w0 = wrap(k0 - 3, nz), wm = wrap(k0 - 4, nz);
     {
-        const int64_t pa = (int64_t)wrap(k0 - 2, nz) * nxy, pb = (int64_t)wrap(k0 - 1, nz) * nxy;
-        const int64_t pc = (int64_t)w1 * nxy;
+        const int64_t qa = (int64_t)wrap(k0 - 2, nz) * nxy, qb = (int64_t)wrap(k0 - 1, nz) * nxy;
+        const int64_t qc = (int64_t)w1 * nxy;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                e1[r][c] = in.c[c][pa + col[r]];
-                epf[r][c] = in.c[c][pb + col[r]];
-                bpf[r][c] = in.c[3 + c][pc + col[r]];
+                e1[r][c] = src[c][qa + col[r]];
+                pe[0][r][c] = src[c][qb + col[r]];
+                pb[0][r][c] = src[3 + c][qc + col[r]];
             }
             if (isE[r]) {
 #pragma unroll
@@ -246,14 +270,18 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     __syncthreads();
 
     const int klast = k0 + KZe - 1;
-    for (int k = k0 - 3; k <= klast + 1; ++k) {
+    // One plane iteration; Q = (k - k0 + 3) & 1 is the LDS buffer parity and
+    // the prefetch set consumed (set Q^1 is refilled).
+    auto plane = [&](auto parity, int k) {
+        constexpr int Q = decltype(parity)::value;
+        constexpr int eb = Q, gb = Q, bb = Q;
         T e2[R][3], bo[R][3];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                e2[r][c] = epf[r][c];
-                bo[r][c] = bpf[r][c];
+                e2[r][c] = pe[Q][r][c];
+                bo[r][c] = pb[Q][r][c];
             }
         {
             const int64_t p3 = (int64_t)w3 * nxy;
@@ -263,8 +291,8 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    epf[r][c] = in.c[c][p3 + col[r]];
-                    bpf[r][c] = in.c[3 + c][p1 + col[r]];
+                    pe[Q ^ 1][r][c] = src[c][p3 + col[r]];
+                    pb[Q ^ 1][r][c] = src[3 + c][p1 + col[r]];
                 }
         }
 #pragma unroll
@@ -323,7 +351,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 if (isO[r] && k >= k0) {
                     const int64_t po = (int64_t)w0 * nxy + col[r];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) nt_store(out.c[3 + c] + po, bn[r][c]);
+                    for (int c = 0; c < 3; ++c) nt_store(dst[3 + c] + po, bn[r][c]);
                 }
             }
         }
@@ -339,9 +367,9 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 const T ey = ampere_eval(ea[r][1], w.wa[2], b1[r][0], b2[r][0], w.wa[0], b1[r][2], Bp[2][l - 1]);
                 const T ez = ampere_eval(ea[r][2], w.wa[0], b1[r][1], Bp[1][l - 1], w.wa[1], b1[r][0], Bp[0][l - PX]);
                 const int64_t po = (int64_t)wm * nxy + col[r];
-                nt_store(out.c[0] + po, ex);
-                nt_store(out.c[1] + po, ey);
-                nt_store(out.c[2] + po, ez);
+                nt_store(dst[0] + po, ex);
+                nt_store(dst[1] + po, ey);
+                nt_store(dst[2] + po, ez);
             }
         }
         __syncthreads();
@@ -364,12 +392,16 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
 #pragma unroll
             for (int c = 0; c < 3; ++c) b1[r][c] = bn[r][c];
         }
-        eb ^= 1;
-        gb ^= 1;
-        bb ^= 1;
         w3 = inc(w3);
         wm = w0;
         w0 = inc(w0);
+    };
+    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), two per loop trip
+    for (int k = k0 - 3;; k += 2) {
+        plane(std::integral_constant<int, 0>{}, k);
+        if (k + 1 > klast + 1) break;
+        plane(std::integral_constant<int, 1>{}, k + 1);
+        if (k + 2 > klast + 1) break;
     }
 }
 
