@@ -114,6 +114,10 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     const int64_t nxy = (int64_t)d.nx * d.ny;
     const int gyc = valid ? wrapa(y0 + ry, d.ny) : 0, gxc = valid ? wrapa(x0 + rx, d.nx) : 0;
     const int col = gyc * d.nx + gxc;
+    // lB' is needed only where mu is formed, the primal E only at the output
+    // cells and their x+1 / y+1 neighbours; other lanes load column 0
+    const int colb = isG ? col : 0;
+    const int coln = (valid && rx >= 0 && rx <= TXe && ry >= 0 && ry <= TYe) ? col : 0;
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
     gptr_a<const T> en[3] = {(gptr_a<const T>)en_x, (gptr_a<const T>)en_y, (gptr_a<const T>)en_z};
@@ -150,9 +154,9 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         for (int c = 0; c < 3; ++c) {
             l1[c] = src[c][pa + col];
             pe[0][c] = src[c][pq + col];
-            pb[0][c] = src[3 + c][pa + col];
-            pn[0][c] = en[c][pa + col];
-            n0[c] = en[c][pm + col];
+            pb[0][c] = src[3 + c][pa + colb];
+            pn[0][c] = en[c][pa + coln];
+            n0[c] = en[c][pm + coln];
         }
         if (isE) {
 #pragma unroll
@@ -187,8 +191,8 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 pe[B ^ 1][c] = src[c][p3 + col];
-                pb[B ^ 1][c] = src[3 + c][pq + col];
-                pn[B ^ 1][c] = en[c][pn2 + col];
+                pb[B ^ 1][c] = src[3 + c][pq + colb];
+                pn[B ^ 1][c] = en[c][pn2 + coln];
             }
         }
         if (isE) {

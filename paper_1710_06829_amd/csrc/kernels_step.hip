@@ -220,7 +220,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
         lane_ok = sel < 4;
     }
     bool isE[R], isG[R], isB[R], isO[R];
-    int li[R], col[R];
+    int li[R], col[R], colb[R];
     const int64_t nxy = (int64_t)d.nx * d.ny;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -234,6 +234,8 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
         // idle positions use column 0 so that every lane can load
         // unconditionally (in bounds, value unused)
         col[r] = valid ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+        // B^{n-1/2} is needed only where B^{n+1/2} is formed
+        colb[r] = isB[r] ? col[r] : 0;
     }
     const int nz = d.nz;
     auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
@@ -254,7 +256,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
             for (int c = 0; c < 3; ++c) {
                 e1[r][c] = src[c][qa + col[r]];
                 pe[0][r][c] = src[c][qb + col[r]];
-                pb[0][r][c] = src[3 + c][qc + col[r]];
+                pb[0][r][c] = src[3 + c][qc + colb[r]];
             }
             if (isE[r]) {
 #pragma unroll
@@ -292,7 +294,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     pe[Q ^ 1][r][c] = src[c][p3 + col[r]];
-                    pb[Q ^ 1][r][c] = src[3 + c][p1 + col[r]];
+                    pb[Q ^ 1][r][c] = src[3 + c][p1 + colb[r]];
                 }
         }
 #pragma unroll
