@@ -246,7 +246,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     // (pe, pb): a load issued in one iteration is first waited for in the
     // next, instead of at the loop back-edge together with the stores.
     T ea[R][3], e0[R][3], e1[R][3], pe[2][R][3], pb[2][R][3], gm[R][6], gc[R][6], b1[R][3], b2[R][2];
-    int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), w0 = wrap(k0 - 3, nz), wm = wrap(k0 - 4, nz);
+    int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), wm = wrap(k0 - 4, nz);
     {
         const int64_t qa = (int64_t)wrap(k0 - 2, nz) * nxy, qb = (int64_t)wrap(k0 - 1, nz) * nxy;
         const int64_t qc = (int64_t)w1 * nxy;
@@ -282,8 +282,8 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                e2[r][c] = pe[Q][r][c];
-                bo[r][c] = pb[Q][r][c];
+                e2[r][c] = take(pe[Q][r][c]);
+                bo[r][c] = take(pb[Q][r][c]);
             }
         {
             const int64_t p3 = (int64_t)w3 * nxy;
@@ -350,16 +350,12 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 bn[r][2] = bo[r][2] + (sy4 - sx5);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Bbuf[bb][c][l] = bn[r][c];
-                if (isO[r] && k >= k0) {
-                    const int64_t po = (int64_t)w0 * nxy + col[r];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) nt_store(dst[3 + c] + po, bn[r][c]);
-                }
             }
         }
 
-        // E^{n+1}(k-1) from B^{n+1/2}(k-1) (LDS, written last iteration)
-        if (k - 1 >= k0) {
+        // outputs of plane k-1: E^{n+1}(k-1) from B^{n+1/2}(k-1) (LDS and
+        // registers, formed last iteration) and B^{n+1/2}(k-1) itself
+        if (k - 1 >= k0 && k - 1 <= klast) {
             const T(*Bp)[P] = Bbuf[bb ^ 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -372,8 +368,11 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 nt_store(dst[0] + po, ex);
                 nt_store(dst[1] + po, ey);
                 nt_store(dst[2] + po, ez);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nt_store(dst[3 + c] + po, b1[r][c]);
             }
         }
+
         __syncthreads();
 
 #pragma unroll
@@ -395,15 +394,15 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
             for (int c = 0; c < 3; ++c) b1[r][c] = bn[r][c];
         }
         w3 = inc(w3);
-        wm = w0;
-        w0 = inc(w0);
+        wm = inc(wm);
     };
-    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), two per loop trip
-    for (int k = k0 - 3;; k += 2) {
+    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), two per loop trip; an odd
+    // count runs one more iteration (k = klast + 2) whose results are unused,
+    // so that the loop has a single exit and the prefetch register sets need
+    // no copies at the back-edge
+    for (int k = k0 - 3; k <= klast + 1; k += 2) {
         plane(std::integral_constant<int, 0>{}, k);
-        if (k + 1 > klast + 1) break;
         plane(std::integral_constant<int, 1>{}, k + 1);
-        if (k + 2 > klast + 1) break;
     }
 }
 

@@ -32,6 +32,26 @@ struct Dims {
     int nx, ny, nz;
 };
 
+// Copies a prefetched value into a fresh register at the point where it is
+// consumed.  The z-marching kernels keep two alternating sets of prefetch
+// registers; without an explicit copy the register allocator may keep a
+// consumed value in its prefetch register for the rest of the iteration and
+// then move the next load's result at the loop back-edge, which makes the
+// wave wait for that load (and the iteration's stores) there.
+__device__ __forceinline__ float take(float v)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+__device__ __forceinline__ double take(double v)
+{
+    double r;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 // Launchers (kernels_step.hip).  All return hipSuccess or the launch error.
 template <typename T>
 hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s);
