@@ -53,7 +53,9 @@ extern "C" {
 
 typedef struct xfdtd_s *xfdtd_t;
 
-/* Grid: cell counts (each >= 1) and spacings (each > 0). */
+/* Grid: cell counts (each >= 1, each <= 2^30, nx*ny*nz <= 4e9, and
+ * nx*ny <= 2^28 because z-planes are addressed with 32-bit offsets) and
+ * spacings (each > 0, finite). */
 typedef struct {
     int64_t nx, ny, nz;
     double dx, dy, dz;

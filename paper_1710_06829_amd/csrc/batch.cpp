@@ -200,7 +200,8 @@ int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double 
     for (int64_t i = 0; i < m; ++i) {
         const xfdtd_grid &g = grids[i];
         if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > (1 << 30) || g.ny > (1 << 30) || g.nz > (1 << 30) ||
-            (double)g.nx * g.ny * g.nz > 4.0e9 || !(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) ||
+            (double)g.nx * g.ny * g.nz > 4.0e9 || (double)g.nx * g.ny > (double)(1 << 28) || !(g.dx > 0) ||
+            !(g.dy > 0) || !(g.dz > 0) ||
             !isfinite(g.dx) || !isfinite(g.dy) || !isfinite(g.dz))
             return set_error(XFDTD_EINVAL, "box %lld: invalid grid", (long long)i);
         if (!(dts[i] > 0) || !isfinite(dts[i])) return set_error(XFDTD_EINVAL, "box %lld: bad dt", (long long)i);

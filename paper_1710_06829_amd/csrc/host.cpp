@@ -64,6 +64,8 @@ bool grid_ok(const xfdtd_grid *g)
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
     if (g->nx > (1 << 30) || g->ny > (1 << 30) || g->nz > (1 << 30)) return false;
     if ((double)g->nx * (double)g->ny * (double)g->nz > 4.0e9) return false;
+    // z-planes are addressed with 32-bit byte offsets in the kernels
+    if ((double)g->nx * (double)g->ny > (double)(1 << 28)) return false;
     if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0)) return false;
     if (!isfinite(g->dx) || !isfinite(g->dy) || !isfinite(g->dz)) return false;
     return true;

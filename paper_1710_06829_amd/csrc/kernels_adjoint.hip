@@ -48,6 +48,20 @@ __device__ __forceinline__ void nt_store_a(gptr_a<T> p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// Plane accesses with a uniform base and a 32-bit lane offset (planes are
+// limited to 2^32 bytes on the host): scalar base + vector offset addressing.
+template <typename T>
+__device__ __forceinline__ T ld_plane_a(gptr_a<const T> plane, uint32_t off)
+{
+    return *(gptr_a<const T>)((gptr_a<const char>)plane + off * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_plane_a(gptr_a<T> plane, uint32_t off, T v)
+{
+    __builtin_nontemporal_store(v, (gptr_a<T>)((gptr_a<char>)plane + off * (uint32_t)sizeof(T)));
+}
+
 constexpr int ATILE_X = 64;
 
 // gradient slots: the 12-coefficient order (alpha, beta_t1, beta_t2, delta per axis)
@@ -111,7 +125,7 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     const bool isO = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;     // outputs
 
     const int li = valid ? (ry + 2) * PX + (rx + 2) : 0;
-    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const uint32_t nxy = (uint32_t)d.nx * (uint32_t)d.ny;  // <= 2^28 (host check)
     const int gyc = valid ? wrapa(y0 + ry, d.ny) : 0, gxc = valid ? wrapa(x0 + rx, d.nx) : 0;
     const int col = gyc * d.nx + gxc;
     // lB' is needed only where mu is formed, the primal E only at the output
@@ -148,8 +162,8 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     // wm = k-1 (outputs)
     int w3 = wrapa(k0, nz), wb = wrapa(k0 - 2, nz), wn = wrapa(k0 - 2, nz), wm = wrapa(k0 - 4, nz);
     {
-        const int64_t pa = (int64_t)wrapa(k0 - 2, nz) * nxy, pq = (int64_t)wrapa(k0 - 1, nz) * nxy;
-        const int64_t pm = (int64_t)wrapa(k0 - 3, nz) * nxy;
+        const uint64_t pa = (uint64_t)(uint32_t)wrapa(k0 - 2, nz) * nxy, pq = (uint64_t)(uint32_t)wrapa(k0 - 1, nz) * nxy;
+        const uint64_t pm = (uint64_t)(uint32_t)wrapa(k0 - 3, nz) * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             l1[c] = src[c][pa + col];
@@ -183,16 +197,21 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             bo[c] = pb[B][c];  // lB'(k+1)
             n1[c] = pn[B][c];  // E(k+1)
         }
+        // per-iteration copies of the lane offsets, opaque to the compiler, so
+        // that addresses stay scalar plane base + 32-bit lane offset (no
+        // per-lane 64-bit adds hoisted out of the loop)
+        uint32_t oc = col, ob = colb, on = coln;
+        asm("" : "+v"(oc), "+v"(ob), "+v"(on));
         {
-            const int64_t p3 = (int64_t)w3 * nxy;
+            const uint64_t p3 = (uint64_t)(uint32_t)w3 * nxy;
             wb = inc(wb);
             wn = inc(wn);
-            const int64_t pq = (int64_t)wb * nxy, pn2 = (int64_t)wn * nxy;  // k+2: own E
+            const uint64_t pq = (uint64_t)(uint32_t)wb * nxy, pn2 = (uint64_t)(uint32_t)wn * nxy;  // k+2: own E
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                pe[B ^ 1][c] = src[c][p3 + col];
-                pb[B ^ 1][c] = src[3 + c][pq + colb];
-                pn[B ^ 1][c] = en[c][pn2 + coln];
+                pe[B ^ 1][c] = ld_plane_a(src[c] + p3, oc);
+                pb[B ^ 1][c] = ld_plane_a(src[3 + c] + pq, ob);
+                pn[B ^ 1][c] = ld_plane_a(en[c] + pn2, on);
             }
         }
         if (isE) {
@@ -266,15 +285,15 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         // outputs of plane k-1: lE = lE' + backward differences of its stars
         if (isO && k - 1 >= k0) {
             const T(*Sp)[P] = Sbuf[sb ^ 1];
-            const int64_t po = (int64_t)wm * nxy + col;
+            const uint64_t po = (uint64_t)(uint32_t)wm * nxy;
             const T lx = la[0] + ((sp3 - sq3) - (Sp[4][li] - Sp[4][li - PX]));
             const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (sp0 - sq0));
             const T lz = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
-            nt_store_a(dst[0] + po, lx);
-            nt_store_a(dst[1] + po, ly);
-            nt_store_a(dst[2] + po, lz);
+            st_plane_a(dst[0] + po, oc, lx);
+            st_plane_a(dst[1] + po, oc, ly);
+            st_plane_a(dst[2] + po, oc, lz);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) nt_store_a(dst[3 + c] + po, mm[c]);
+            for (int c = 0; c < 3; ++c) st_plane_a(dst[3 + c] + po, oc, mm[c]);
         }
         __syncthreads();
 

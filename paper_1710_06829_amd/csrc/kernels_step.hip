@@ -73,6 +73,22 @@ __device__ __forceinline__ void nt_store(gptr<T> p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// Element `off` of a z-plane whose base pointer is uniform across the
+// workgroup: the byte offset is formed in 32 bits (planes are limited to
+// 2^32 bytes on the host), so the access takes a scalar base and a 32-bit
+// per-lane offset and needs no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T ld_plane(gptr<const T> plane, uint32_t off)
+{
+    return *(gptr<const T>)((gptr<const char>)plane + off * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void st_plane(gptr<T> plane, uint32_t off, T v)
+{
+    __builtin_nontemporal_store(v, (gptr<T>)((gptr<char>)plane + off * (uint32_t)sizeof(T)));
+}
+
 // ---------------------------------------------------------------------------
 // unfused Faraday: B += S(D* E) in place
 // ---------------------------------------------------------------------------
@@ -221,7 +237,7 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     }
     bool isE[R], isG[R], isB[R], isO[R];
     int li[R], col[R], colb[R];
-    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const uint32_t nxy = (uint32_t)d.nx * (uint32_t)d.ny;  // <= 2^28 (host check)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int ry = ry0 + r;
@@ -248,15 +264,15 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     T ea[R][3], e0[R][3], e1[R][3], pe[2][R][3], pb[2][R][3], gm[R][6], gc[R][6], b1[R][3], b2[R][2];
     int w3 = wrap(k0, nz), w1 = wrap(k0 - 3, nz), wm = wrap(k0 - 4, nz);
     {
-        const int64_t qa = (int64_t)wrap(k0 - 2, nz) * nxy, qb = (int64_t)wrap(k0 - 1, nz) * nxy;
-        const int64_t qc = (int64_t)w1 * nxy;
+        const uint64_t qa = (uint64_t)(uint32_t)wrap(k0 - 2, nz) * nxy, qb = (uint64_t)(uint32_t)wrap(k0 - 1, nz) * nxy;
+        const uint64_t qc = (uint64_t)(uint32_t)w1 * nxy;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                e1[r][c] = src[c][qa + col[r]];
-                pe[0][r][c] = src[c][qb + col[r]];
-                pb[0][r][c] = src[3 + c][qc + colb[r]];
+                e1[r][c] = ld_plane(src[c] + qa, col[r]);
+                pe[0][r][c] = ld_plane(src[c] + qb, col[r]);
+                pb[0][r][c] = ld_plane(src[3 + c] + qc, colb[r]);
             }
             if (isE[r]) {
 #pragma unroll
@@ -285,16 +301,27 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 e2[r][c] = take(pe[Q][r][c]);
                 bo[r][c] = take(pb[Q][r][c]);
             }
+        // per-iteration copies of the lane offsets, opaque to the compiler, so
+        // that it keeps the addresses in the form scalar plane base + 32-bit
+        // lane offset instead of hoisting base + offset out of the loop (which
+        // costs a 64-bit vector add per access)
+        uint32_t oc[R], ob[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            oc[r] = col[r];
+            ob[r] = colb[r];
+            asm("" : "+v"(oc[r]), "+v"(ob[r]));
+        }
         {
-            const int64_t p3 = (int64_t)w3 * nxy;
+            const uint64_t p3 = (uint64_t)(uint32_t)w3 * nxy;
             w1 = inc(w1);
-            const int64_t p1 = (int64_t)w1 * nxy;
+            const uint64_t p1 = (uint64_t)(uint32_t)w1 * nxy;
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    pe[Q ^ 1][r][c] = src[c][p3 + col[r]];
-                    pb[Q ^ 1][r][c] = src[3 + c][p1 + colb[r]];
+                    pe[Q ^ 1][r][c] = ld_plane(src[c] + p3, oc[r]);
+                    pb[Q ^ 1][r][c] = ld_plane(src[3 + c] + p1, ob[r]);
                 }
         }
 #pragma unroll
@@ -364,12 +391,12 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
                 const T ex = ampere_eval(ea[r][0], w.wa[1], b1[r][2], Bp[2][l - PX], w.wa[2], b1[r][1], b2[r][1]);
                 const T ey = ampere_eval(ea[r][1], w.wa[2], b1[r][0], b2[r][0], w.wa[0], b1[r][2], Bp[2][l - 1]);
                 const T ez = ampere_eval(ea[r][2], w.wa[0], b1[r][1], Bp[1][l - 1], w.wa[1], b1[r][0], Bp[0][l - PX]);
-                const int64_t po = (int64_t)wm * nxy + col[r];
-                nt_store(dst[0] + po, ex);
-                nt_store(dst[1] + po, ey);
-                nt_store(dst[2] + po, ez);
+                const uint64_t pm = (uint64_t)(uint32_t)wm * nxy;
+                st_plane(dst[0] + pm, oc[r], ex);
+                st_plane(dst[1] + pm, oc[r], ey);
+                st_plane(dst[2] + pm, oc[r], ez);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) nt_store(dst[3 + c] + po, b1[r][c]);
+                for (int c = 0; c < 3; ++c) st_plane(dst[3 + c] + pm, oc[r], b1[r][c]);
             }
         }
 
