@@ -93,7 +93,7 @@ def cpu_baseline(f64_fields, coeffs, dt, steps):
 def fwd_adj_ratio(steps=200):
     """Time of the checkpointed forward + adjoint over the plain forward, on the
     128^3 FP32 differentiation workload (Gaussian pulse, wavelength 12, probe
-    plane loss), sqrt(N) checkpoints."""
+    plane loss), sqrt(N) checkpoints (segments of ceil(sqrt(2N)) steps)."""
     import math
 
     import numpy as np
@@ -125,7 +125,7 @@ def fwd_adj_ratio(steps=200):
     torch.cuda.synchronize()
     t_fwd = e0.elapsed_time(e1)
 
-    seg = int(math.ceil(math.sqrt(steps)))
+    seg = int(math.ceil(math.sqrt(2 * steps)))  # the library's default segment
     work = [x.clone() for x in f32]
     sg = pkg.Solver(work, dt, coeffs, scratch=False)
     ws = torch.empty(sg.grad_workspace_bytes(steps, seg), dtype=torch.uint8, device=dev)

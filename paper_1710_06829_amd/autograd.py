@@ -4,7 +4,7 @@ library's hand-written adjoint kernels and its checkpoint schedule.
 ``propagate(fields, coeffs, n, dt)`` returns the six fields after n steps;
 gradients flow to the initial fields and to the 12 coefficients (a float64
 tensor).  The forward pass keeps the state every ``seg`` steps (default
-ceil(sqrt(n))); the backward pass recomputes each segment from its checkpoint
+ceil(sqrt(2 n)), which minimises the workspace); the backward pass recomputes each segment from its checkpoint
 and runs the adjoint steps in reverse (see include/xfdtd.h).
 """
 from __future__ import annotations

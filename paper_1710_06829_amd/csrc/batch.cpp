@@ -431,7 +431,7 @@ size_t box_field_bytes(const xfdtd_batch_s *b, int64_t i)
 int64_t bseg(int64_t n, int64_t seg)
 {
     if (seg > 0) return seg;
-    int64_t s = (int64_t)ceil(sqrt((double)(n > 0 ? n : 1)));
+    int64_t s = (int64_t)ceil(sqrt(2.0 * (double)(n > 0 ? n : 1)));  // as the single-box default
     return s < 1 ? 1 : s;
 }
 

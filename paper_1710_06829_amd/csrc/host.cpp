@@ -225,7 +225,8 @@ struct xfdtd_s {
     bool bound;
     bool have_scratch;
     hipStream_t stream;
-    int tile_y, zchunk;
+    int tile_y, zchunk;    // fused step
+    int atile_y, azchunk;  // adjoint step
     int device;
     double *partials;  // device, for reductions
     int npartials;
@@ -362,6 +363,14 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     const char *ty = getenv("XFDTD_TILE_Y");
     if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
     h->zchunk = pick_zchunk(*g, h->tile_y);
+    // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
+    // fit in LDS), its own z-chunk for that tile height
+    h->atile_y = dtype == XFDTD_F64 ? 4 : 8;
+    const char *aty = getenv("XFDTD_ADJ_TILE_Y");
+    if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && dtype == XFDTD_F32))) h->atile_y = atoi(aty);
+    h->azchunk = pick_zchunk(*g, h->atile_y);
+    const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
+    if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
     h->device = -1;
     h->partials = nullptr;
     h->npartials = 0;
@@ -558,11 +567,11 @@ int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double
 namespace {
 
 // the adjoint kernel exists for 4- and 8-row tiles
-int adjoint_tile_y(const xfdtd_s *h) { return h->dtype == XFDTD_F64 ? 4 : (h->tile_y > 8 ? 8 : h->tile_y); }
+int adjoint_tile_y(const xfdtd_s *h) { return h->atile_y; }
 
 int ensure_adjoint_buffers(xfdtd_t h)
 {
-    const int nb = adjoint_blocks(dims_of(h->g), adjoint_tile_y(h), h->zchunk);
+    const int nb = adjoint_blocks(dims_of(h->g), adjoint_tile_y(h), h->azchunk);
     if (h->napartials < nb) {
         if (h->apartials) {
             HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -593,10 +602,10 @@ int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T 
     const Dims d = dims_of(h->g);
     const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
     const int ty = adjoint_tile_y(h);
-    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->zchunk, h->apartials, accumulate, h->stream),
+    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->azchunk, h->apartials, accumulate, h->stream),
             "adjoint launch");
     if (reduce)
-        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->zchunk), grad_scale(h), grad,
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->azchunk), grad_scale(h), grad,
                                        h->stream),
                 "reduce launch");
     return XFDTD_OK;
@@ -609,10 +618,13 @@ size_t field_bytes(const xfdtd_s *h)
     return (b + 255) / 256 * 256;
 }
 
+// Default segment length: the workspace holds 6 ceil(n/seg) + 12 + 3 (seg - 1)
+// field arrays, smallest at seg = sqrt(2 n); the backward pass recomputes
+// n - seg steps.
 int64_t default_seg(int64_t n, int64_t seg)
 {
     if (seg > 0) return seg;
-    int64_t s = (int64_t)ceil(sqrt((double)(n > 0 ? n : 1)));
+    int64_t s = (int64_t)ceil(sqrt(2.0 * (double)(n > 0 ? n : 1)));
     return s < 1 ? 1 : s;
 }
 
@@ -728,7 +740,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
         }
     }
     if (!first)
-        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, adjoint_tile_y(h), h->zchunk), grad_scale(h),
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, adjoint_tile_y(h), h->azchunk), grad_scale(h),
                                        h->grad_acc, h->stream),
                 "reduce launch");
     if (lcur.c[0] != lamU.c[0])

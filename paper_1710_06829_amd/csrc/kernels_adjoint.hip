@@ -268,17 +268,17 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
                 acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
                 acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
                 acc[2] += (double)(gxEz * pz[1] - gxEy * pz[2]);
-                acc[3] += (double)(gxEz * (mc[1] + px[1]) - gxEy * (mc[2] + px[2]));
+                acc[3] += (double)(gxEz * px[1] - gxEy * px[2]);
                 // axis y (slots 4..7): -g_y[Ez] with mu_x, +g_y[Ex] with mu_z
                 acc[4] += (double)(gyEx * mc[2] - gyEz * mc[0]);
                 acc[5] += (double)(gyEx * px[2] - gyEz * px[0]);
                 acc[6] += (double)(gyEx * pz[2] - gyEz * pz[0]);
-                acc[7] += (double)(gyEx * (mc[2] + py[2]) - gyEz * (mc[0] + py[0]));
+                acc[7] += (double)(gyEx * py[2] - gyEz * py[0]);
                 // axis z (slots 8..11): +g_z[Ey] with mu_x, -g_z[Ex] with mu_y
                 acc[8] += (double)(gzEy * mc[0] - gzEx * mc[1]);
                 acc[9] += (double)(gzEy * px[0] - gzEx * px[1]);
                 acc[10] += (double)(gzEy * py[0] - gzEx * py[1]);
-                acc[11] += (double)(gzEy * (mc[0] + pz[0]) - gzEx * (mc[1] + pz[1]));
+                acc[11] += (double)(gzEy * pz[0] - gzEx * pz[1]);
             }
         }
 
@@ -320,6 +320,12 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         plane(std::integral_constant<int, 1>{}, k + 1);
         if (k + 2 > klast + 1) break;
     }
+
+    // delta_a: the centre term (that of alpha_a) plus the along-axis
+    // neighbours, which are all the delta slots accumulate per plane
+    acc[3] += acc[0];
+    acc[7] += acc[4];
+    acc[11] += acc[8];
 
     // workgroup reduction of the 12 gradient sums (FP64)
 #pragma unroll

@@ -88,6 +88,11 @@ def test_create_rejects_unstable_dt_and_bad_arguments():
     assert _create(dt=float("nan"))[0] == -1
     assert _create(dtype=3)[0] == -1
     assert _create(spacing=(1, 0, 1))[0] == -1
+    # z-planes are limited to 2^28 cells (32-bit plane offsets in the kernels)
+    assert _create(shape=(1, 1 << 14, 1 << 15))[0] == -1
+    rc, h = _create(shape=(1, 1 << 14, 1 << 14))
+    assert rc == 0
+    B.lib().xfdtd_destroy(h)
     bad = O.yee_coeffs()
     bad[5] = float("inf")
     assert _create(coeffs=bad)[0] == -1
