@@ -177,6 +177,62 @@ int xfdtd_dispersion(const xfdtd_grid *g, double dt, const double coeffs[12],
                      void *stream);
 
 /*
+ * Dispersion norm f_w of Sec. 4 (eq. norm), c = 1:
+ *   f_w = prod_a d_a  integral over [0, pi/d_a]^dims of w(k) (omega(k) - |k|)^2,
+ * by the midpoint rule with n points per axis, on the GPU (FP64).
+ *   dims  : 3, or 2 for the k_z = 0 plane (the paper's 2D tables; the
+ *           product then runs over d_x d_y).
+ *   weight: XFDTD_WEIGHT_UNIT (w = 1) or XFDTD_WEIGHT_AXIS,
+ *           w = exp(-sum_{t = y, z} (k_t d_t / width)^2) (Sec. 5.2,
+ *           eq. norm_x_axis with width 0.1: propagation close to the x axis).
+ *   f     : host, the norm.  grad: host, 13 doubles or NULL: d f_w / d coeffs
+ *           (12, coefficient order) then d f_w / d dt, from the closed-form
+ *           derivative of omega.
+ * Only the spacings of g are used.  If any sample has dt^2 F outside (0, 1)
+ * (omega undefined or on the stability boundary) f is NaN and the call
+ * returns XFDTD_EUNSTABLE.  Synchronises `stream`; allocates two small device
+ * buffers per call.
+ */
+enum { XFDTD_WEIGHT_UNIT = 0, XFDTD_WEIGHT_AXIS = 1 };
+int xfdtd_dispersion_norm(const xfdtd_grid *g, double dt, const double coeffs[12], int dims, int64_t n,
+                          int weight, double width, double *f, double grad[13], void *stream);
+
+/*
+ * Minimisation of f_w over a family of stencils (Sec. 4: bounded, from a grid
+ * of starting points, under the stability constraints of eq. constraints,
+ * 0 <= F and dt^2 F <= 1 over the zone, dims-dimensional).
+ * The stencil is affine in the free parameters x[0..nparam):
+ *   q = base + map x  (q: the 12 coefficients, then dt; map row-major 13 x 8),
+ * then, if alpha_rule != 0, alpha_a = 1 - 2 beta_at1 - 2 beta_at2 - 3 delta_a
+ * (eq. alpha).  dt_mode 0 takes dt = q[12]; dt_mode 1 takes
+ * dt = x[dt_param] * (stability bound of the stencil), x[dt_param] in (0, 1].
+ * The box lo <= x <= hi is the search space; the search starts from the
+ * centres of a grid of starts^nparam cells of the box and runs a projected
+ * quasi-Newton iteration (at most max_iter steps each) that rejects unstable
+ * stencils.  Outputs (host): x_out[nparam], the 12 coefficients, dt, f_w and
+ * (if non-NULL) the number of norm evaluations.  Returns XFDTD_EUNSTABLE if
+ * no starting point is stable.  Synchronises `stream`.
+ */
+typedef struct {
+    int32_t nparam;      /* 1..8 */
+    int32_t alpha_rule;  /* nonzero: alpha from eq. alpha after the map */
+    int32_t dt_mode;     /* 0 or 1, see above */
+    int32_t dt_param;    /* dt_mode 1: the parameter that scales the bound */
+    double base[13];
+    double map[13 * 8];
+    double lo[8], hi[8];
+    int32_t dims;        /* norm: 2 or 3 */
+    int32_t weight;      /* norm: XFDTD_WEIGHT_* */
+    double width;        /* norm: XFDTD_WEIGHT_AXIS width */
+    int64_t n;           /* norm: midpoints per axis */
+    int32_t starts;      /* starting points per parameter, 1..64, starts^nparam <= 4096 */
+    int32_t max_iter;    /* per start, 1..1e5 */
+} xfdtd_stencil_problem;
+int xfdtd_optimize_stencil(const xfdtd_grid *g, const xfdtd_stencil_problem *p, double x_out[8],
+                           double coeffs_out[12], double *dt_out, double *f_out, int *evals_out,
+                           void *stream);
+
+/*
  * Divergence diagnostics of the bound fields (eq. divstarb, eq. divE).
  *   div_star_b : device, nz*ny*nx of the handle dtype, or NULL: D*.B at the
  *                cell centres, element (i,j,k) at (i+1/2, j+1/2, k+1/2).

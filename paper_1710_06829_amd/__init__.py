@@ -9,5 +9,7 @@ from ._binding import XfdtdError, lib  # noqa: F401
 from .solver import Solver, cfl_limit, consistent_alpha, dispersion  # noqa: F401
 from .autograd import propagate  # noqa: F401
 from .batch import Batch  # noqa: F401
+from .norm import Family, dispersion_norm, optimize_stencil  # noqa: F401
 
-__all__ = ["Batch", "Solver", "cfl_limit", "consistent_alpha", "dispersion", "propagate", "XfdtdError", "lib"]
+__all__ = ["Batch", "Family", "Solver", "cfl_limit", "consistent_alpha", "dispersion", "dispersion_norm",
+           "optimize_stencil", "propagate", "XfdtdError", "lib"]

@@ -30,6 +30,18 @@ class Grid(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
 
 
+class StencilProblem(ctypes.Structure):
+    """xfdtd_stencil_problem."""
+    _fields_ = [("nparam", ctypes.c_int32), ("alpha_rule", ctypes.c_int32), ("dt_mode", ctypes.c_int32),
+                ("dt_param", ctypes.c_int32), ("base", ctypes.c_double * 13), ("map", ctypes.c_double * (13 * 8)),
+                ("lo", ctypes.c_double * 8), ("hi", ctypes.c_double * 8), ("dims", ctypes.c_int32),
+                ("weight", ctypes.c_int32), ("width", ctypes.c_double), ("n", ctypes.c_int64),
+                ("starts", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
+XFDTD_WEIGHT_UNIT = 0
+XFDTD_WEIGHT_AXIS = 1
+
 _lib = None
 
 # name -> (argtypes, restype); every symbol include/xfdtd.h declares
@@ -50,6 +62,10 @@ SIGNATURES = {
     "xfdtd_get_weights": ([_vp, _dp, ctypes.POINTER(_int)], _int),
     "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "xfdtd_dispersion": ([_GP, ctypes.c_double, _dp, _vp, _i64, _vp, _vp, _vp, _vp], _int),
+    "xfdtd_dispersion_norm": ([_GP, ctypes.c_double, _dp, _int, _i64, _int, ctypes.c_double, _dp, _dp, _vp],
+                              _int),
+    "xfdtd_optimize_stencil": ([_GP, ctypes.POINTER(StencilProblem), _dp, _dp, _dp, _dp, ctypes.POINTER(_int),
+                                _vp], _int),
     "xfdtd_divergence": ([_vp, _vp, _vp], _int),
     "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),
     "xfdtd_adjoint_step": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libxfdtd.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["host.cpp", "batch.cpp", "kernels_step.hip", "kernels_diag.hip", "kernels_adjoint.hip"]
+SOURCES = ["host.cpp", "batch.cpp", "norm.cpp", "kernels_step.hip", "kernels_diag.hip", "kernels_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

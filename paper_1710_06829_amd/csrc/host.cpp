@@ -92,7 +92,8 @@ inline int t2_of(int a) { return a == 2 ? 1 : 2; }
 // is singular reaches its extremes on its own boundary, so it is skipped.
 }  // namespace
 
-void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double *out_hi)
+void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double *out_hi, int dims,
+                    double umax[3])
 {
     double lin[3] = {0, 0, 0}, Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int a = 0; a < 3; ++a) {
@@ -119,6 +120,7 @@ void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double 
     double lo = INFINITY, hi = -INFINITY;
     for (int pat = 0; pat < 27; ++pat) {
         int st[3] = {pat % 3, (pat / 3) % 3, pat / 9};  // 0: u=0, 1: u=1, 2: free
+        if (dims == 2 && st[2] != 0) continue;           // k_z = 0 plane
         double u[3];
         int fr[3], nf = 0;
         for (int a = 0; a < 3; ++a) {
@@ -172,7 +174,11 @@ void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double 
         }
         const double v = F(u);
         lo = fmin(lo, v);
-        hi = fmax(hi, v);
+        if (v > hi) {
+            hi = v;
+            if (umax)
+                for (int q = 0; q < 3; ++q) umax[q] = u[q];
+        }
     }
     *out_lo = lo;
     *out_hi = hi;

@@ -183,7 +183,122 @@ __global__ __launch_bounds__(256) void dispersion_kernel(const double *kv, int64
     }
 }
 
+// Dispersion norm of Sec. 4 (eq. norm): f_w = prod_a d_a * integral over
+// [0, pi/d_a]^dims of w(k) (omega(k) - |k|)^2 (c = 1), by the midpoint rule
+// with n points per axis (k_z = 0 when dims = 2), together with its
+// derivatives with respect to the 12 coefficients and dt:
+//   d omega/dF  = 1 / (sqrt(F) sqrt(1 - dt^2 F))
+//   d omega/ddt = -omega/dt + 2 sqrt(F) / (dt sqrt(1 - dt^2 F))
+//   dF/d alpha_a = s_a^2, dF/d delta_a = s_a^2 (1 + 2 cos th_a),
+//   dF/d beta_at = 2 s_a^2 cos th_t.
+// Each thread accumulates its points in FP64; every block writes its 14 sums
+// (f, 12 coefficients, dt) to `partials`; norm_reduce_kernel adds them in a
+// fixed order.  Samples with dt^2 F outside [0, 1) are counted in `bad`.
+constexpr int NORM_THREADS = 256;
+
+__global__ __launch_bounds__(NORM_THREADS) void norm_kernel(NormArgs a, double *partials, unsigned int *bad)
+{
+    __shared__ double red[14][NORM_THREADS];
+    double acc[14];
+    for (int j = 0; j < 14; ++j) acc[j] = 0.0;
+    const int64_t n = a.n;
+    const int64_t total = a.dims == 2 ? n * n : n * n * n;
+    const int64_t stride = (int64_t)gridDim.x * NORM_THREADS;
+    unsigned int nbad = 0;
+    for (int64_t q = blockIdx.x * (int64_t)NORM_THREADS + threadIdx.x; q < total; q += stride) {
+        const int64_t idx[3] = {q % n, (q / n) % n, a.dims == 2 ? 0 : q / (n * n)};
+        double s2[3], cs[3], kk = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (ax < a.dims) {
+                const double th = ((double)idx[ax] + 0.5) * (M_PI / (double)n);  // k_a d_a
+                const double k = th / a.sp[ax];
+                kk += k * k;
+                const double sh = sin(0.5 * th) / a.sp[ax];
+                s2[ax] = sh * sh;
+                cs[ax] = cos(th);
+            } else {
+                s2[ax] = 0.0;
+                cs[ax] = 1.0;
+            }
+        }
+        double F = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+            const double A = a.c[4 * ax] + 2.0 * a.c[4 * ax + 1] * cs[t1] + 2.0 * a.c[4 * ax + 2] * cs[t2] +
+                             a.c[4 * ax + 3] * (1.0 + 2.0 * cs[ax]);
+            F += s2[ax] * A;
+        }
+        const double x = a.dt * a.dt * F;
+        if (!(x > 0.0 && x < 1.0)) {
+            ++nbad;
+            continue;
+        }
+        const double sf = sqrt(F), rt = sqrt(1.0 - x);
+        const double om = (2.0 / a.dt) * asin(a.dt * sf);
+        const double dev = om - sqrt(kk);
+        double w = 1.0;
+        if (a.weight == 1) {
+            double e = 0.0;
+            for (int ax = 1; ax < a.dims; ++ax) {
+                const double r = ((double)idx[ax] + 0.5) * (M_PI / (double)n) / a.width;
+                e += r * r;
+            }
+            w = exp(-e);
+        }
+        const double wd = w * dev;
+        acc[0] += wd * dev;
+        const double g = 2.0 * wd / (sf * rt);  // 2 w dev d omega/dF
+        for (int ax = 0; ax < 3; ++ax) {
+            const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+            acc[1 + 4 * ax] += g * s2[ax];
+            acc[2 + 4 * ax] += g * 2.0 * s2[ax] * cs[t1];
+            acc[3 + 4 * ax] += g * 2.0 * s2[ax] * cs[t2];
+            acc[4 + 4 * ax] += g * s2[ax] * (1.0 + 2.0 * cs[ax]);
+        }
+        acc[13] += 2.0 * wd * (-om / a.dt + 2.0 * sf / (a.dt * rt));
+    }
+    if (nbad) atomicAdd(bad, nbad);
+    for (int j = 0; j < 14; ++j) red[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int st = NORM_THREADS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int j = 0; j < 14; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 14) partials[(int64_t)blockIdx.x * 14 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[j] = scale * sum over blocks of partials[b*14 + j], fixed order.
+__global__ __launch_bounds__(NORM_THREADS) void norm_reduce_kernel(const double *partials, int nblocks,
+                                                                   double scale, double *out)
+{
+    __shared__ double red[14][NORM_THREADS];
+    for (int j = 0; j < 14; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += NORM_THREADS) v += partials[(int64_t)b * 14 + j];
+        red[j][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int st = NORM_THREADS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int j = 0; j < 14; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 14) out[threadIdx.x] = scale * red[threadIdx.x][0];
+}
+
 }  // namespace
+
+hipError_t launch_norm(const NormArgs &args, double *partials, int nblocks, unsigned int *bad, double *out,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(norm_kernel, dim3(nblocks), dim3(NORM_THREADS), 0, s, args, partials, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double scale = pow(M_PI / (double)args.n, (double)args.dims);  // prod d_a * cell volume
+    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partials, nblocks, scale, out);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_divergence(const Fields<T> &f, Dims d, const double coeffs[12], const double sp[3],

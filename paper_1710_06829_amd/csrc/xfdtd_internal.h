@@ -122,9 +122,26 @@ hipError_t launch_dispersion(const double *k, int64_t n, double dt, const double
                              const double sp[3], double *omega, double *vph, double *vg,
                              unsigned int *bad, hipStream_t s);
 
+// Dispersion norm (kernels_diag.hip): f_w and its derivatives with respect to
+// the 12 coefficients and dt, out[14] on the device (f, d/dc[12], d/ddt).
+struct NormArgs {
+    double c[12];
+    double sp[3];
+    double dt;
+    double width;  // weight 1: w = exp(-sum_{t = y, z} (k_t d_t / width)^2)
+    int64_t n;     // midpoints per axis
+    int dims;      // 2 (k_z = 0) or 3
+    int weight;    // 0: w = 1
+};
+hipError_t launch_norm(const NormArgs &args, double *partials, int nblocks, unsigned int *bad, double *out,
+                       hipStream_t s);
+
 // Host helpers shared by the single-box and batched front ends (host.cpp).
-// F_min, F_max of the dispersion right-hand side over the whole zone.
-void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi);
+// F_min, F_max of the dispersion right-hand side over the whole zone
+// (dims = 2: the k_z = 0 plane).  umax (optional) receives
+// u_a = sin^2(k_a d_a / 2) at the maximum.
+void f_range(const double sp[3], const double *c, double *out_lo, double *out_hi, int dims = 3,
+             double umax[3] = nullptr);
 // Fold dt*coef/d_a into the star weights, computed in double and rounded
 // once to T; out15 receives the T values as doubles (xfdtd_get_weights order).
 template <typename T>

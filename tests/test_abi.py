@@ -212,3 +212,22 @@ def test_batch_bind_rejects_overlap_before_device_work():
     f_mis = (ctypes.c_void_p * 12)(*[base + 4 + i * nb for i in range(12)])
     assert B.lib().xfdtd_batch_bind(h, f_mis, s, None) == -1
     B.lib().xfdtd_batch_destroy(h)
+
+
+def test_stencil_family_builds_the_affine_problem():
+    """Host-side marshalling of the minimiser's problem (no GPU call)."""
+    from paper_1710_06829_amd.norm import NAMES
+    fam = (pkg.Family({"dt": 0.5}).param(-0.1, 0.2, beta_xy=1, beta_yx=1)
+           .param(-0.125, 0.125, delta_x=1, delta_y=0.5))
+    p = fam.problem(dims=2, n=100, weight="axis", width=0.1, starts=3, max_iter=50)
+    assert p.nparam == 2 and p.alpha_rule == 1 and p.dt_mode == 0
+    assert p.base[NAMES.index("dt")] == 0.5
+    assert p.map[NAMES.index("beta_yx") * 8 + 0] == 1.0 and p.map[NAMES.index("delta_y") * 8 + 1] == 0.5
+    assert p.map[NAMES.index("delta_x") * 8 + 0] == 0.0
+    assert (p.lo[0], p.hi[0], p.lo[1], p.hi[1]) == (-0.1, 0.2, -0.125, 0.125)
+    assert p.weight == B.XFDTD_WEIGHT_AXIS and p.width == 0.1 and p.n == 100 and p.dims == 2
+    fam2 = pkg.Family().param(0, 0.1, beta_xy=1).dt_fraction(0.2, 1.0)
+    p2 = fam2.problem(dims=3, n=10, weight="unit", width=0.1, starts=2, max_iter=5)
+    assert p2.dt_mode == 1 and p2.dt_param == 1
+    with pytest.raises(ValueError):
+        fam2.dt_fraction(0.1, 1.0)
