@@ -338,6 +338,41 @@ def batched_grads(steps=300, count=16, edge=96):
             "config": bt.config()}
 
 
+def norm_bench():
+    """Dispersion norm f_w with its gradient (3D n = 256 and 2D n = 1000
+    midpoint grids) and the minimisation of Table 1's min.1 family."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import paper_1710_06829_amd as pkg
+
+    beta, delta = 0.110, -0.125
+    c = [1 - 2 * beta - 3 * delta, beta, 0.0, delta, 1 - 2 * beta - 3 * delta, beta, 0.0, delta,
+         1.0, 0.0, 0.0, 0.0]
+    out = {}
+    for dims, n, dt in ((3, 256, 0.5), (2, 1000, 0.686)):
+        pkg.dispersion_norm(dt, c, dims=dims, n=n)
+        ts = []
+        for _ in range(10):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f, _ = pkg.dispersion_norm(dt, c, dims=dims, n=n)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        out[f"{dims}d_n{n}"] = {"samples": n ** dims, "ms": round(t * 1e3, 3),
+                                "Gsamples_per_s": round(n ** dims / t / 1e9, 3), "f": f}
+    fam = (pkg.Family().param(-0.125, 0.25, beta_xy=1, beta_yx=1)
+           .param(-0.125, 0.125, delta_x=1, delta_y=1).dt_fraction(0.1, 1.0))
+    t0 = time.perf_counter()
+    r = pkg.optimize_stencil(fam, dims=2, n=1000, starts=3)
+    out["minimise_table1_min1"] = {"seconds": round(time.perf_counter() - t0, 3), "evaluations": r["evals"],
+                                   "beta": round(r["x"][0], 5), "delta": round(r["x"][1], 5),
+                                   "dt": round(r["dt"], 5), "f": r["f"]}
+    return out
+
+
 def calib_copy(gib=1.0, reps=5):
     """A plain device copy of known size (for scaling rocprofv3 byte counters);
     returns its size and achieved bandwidth (read + write bytes per second)."""
@@ -368,6 +403,7 @@ def main():
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
     ap.add_argument("--grad-batch-only", action="store_true", help="only the batched gradient measurement")
+    ap.add_argument("--norm-only", action="store_true", help="only the dispersion-norm measurement")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 1024x256x256 sustained run and the 64-box batch")
     args = ap.parse_args()
@@ -381,6 +417,9 @@ def main():
 
     if args.adj_only:
         print(json.dumps({"fwd_adj": fwd_adj_ratio()}), flush=True)
+        return
+    if args.norm_only:
+        print(json.dumps({"dispersion_norm": norm_bench()}), flush=True)
         return
     if args.grad_batch_only:
         print(json.dumps({"batched_grads_16x96cube": batched_grads()}), flush=True)
@@ -454,6 +493,7 @@ def main():
         torch.cuda.empty_cache()
         line["batched_grads_16x96cube"] = batched_grads()
         torch.cuda.empty_cache()
+        line["dispersion_norm"] = norm_bench()
     if args.calib:
         line["calib_copy"] = calib_copy()
     if not args.no_cpu:

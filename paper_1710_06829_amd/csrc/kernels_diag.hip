@@ -192,8 +192,9 @@ __global__ __launch_bounds__(256) void dispersion_kernel(const double *kv, int64
 //   dF/d alpha_a = s_a^2, dF/d delta_a = s_a^2 (1 + 2 cos th_a),
 //   dF/d beta_at = 2 s_a^2 cos th_t.
 // Each thread accumulates its points in FP64; every block writes its 14 sums
-// (f, 12 coefficients, dt) to `partials`; norm_reduce_kernel adds them in a
-// fixed order.  Samples with dt^2 F outside [0, 1) are counted in `bad`.
+// (f, 12 coefficients, dt) to `partials` (j-major: partials[j * nblocks + b]);
+// norm_reduce_kernel adds them in a fixed order.  Samples with dt^2 F outside
+// (0, 1) are counted in `bad`.
 constexpr int NORM_THREADS = 256;
 
 __global__ __launch_bounds__(NORM_THREADS) void norm_kernel(NormArgs a, double *partials, unsigned int *bad)
@@ -265,17 +266,20 @@ __global__ __launch_bounds__(NORM_THREADS) void norm_kernel(NormArgs a, double *
             for (int j = 0; j < 14; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x < 14) partials[(int64_t)blockIdx.x * 14 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < 14) partials[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
 }
 
-// out[j] = scale * sum over blocks of partials[b*14 + j], fixed order.
+// out[j] = scale * sum over blocks of partials[j * nblocks + b] (fixed order)
+// for j < 14; out[14] = the count of rejected samples, which is reset to 0
+// for the next evaluation.
 __global__ __launch_bounds__(NORM_THREADS) void norm_reduce_kernel(const double *partials, int nblocks,
-                                                                   double scale, double *out)
+                                                                   double scale, unsigned int *bad,
+                                                                   double *out)
 {
     __shared__ double red[14][NORM_THREADS];
     for (int j = 0; j < 14; ++j) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += NORM_THREADS) v += partials[(int64_t)b * 14 + j];
+        for (int b = threadIdx.x; b < nblocks; b += NORM_THREADS) v += partials[(int64_t)j * nblocks + b];
         red[j][threadIdx.x] = v;
     }
     __syncthreads();
@@ -285,6 +289,10 @@ __global__ __launch_bounds__(NORM_THREADS) void norm_reduce_kernel(const double 
         __syncthreads();
     }
     if (threadIdx.x < 14) out[threadIdx.x] = scale * red[threadIdx.x][0];
+    if (threadIdx.x == 14) {
+        out[14] = (double)*bad;
+        *bad = 0u;
+    }
 }
 
 }  // namespace
@@ -296,7 +304,8 @@ hipError_t launch_norm(const NormArgs &args, double *partials, int nblocks, unsi
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = pow(M_PI / (double)args.n, (double)args.dims);  // prod d_a * cell volume
-    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partials, nblocks, scale, out);
+    hipLaunchKernelGGL(norm_reduce_kernel, dim3(1), dim3(NORM_THREADS), 0, s, partials, nblocks, scale, bad,
+                       out);
     return hipGetLastError();
 }
 

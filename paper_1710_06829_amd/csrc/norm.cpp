@@ -52,9 +52,9 @@ int check_norm_args(int dims, int64_t n, int weight, double width)
 
 // Device buffers of one norm evaluation (reused by the minimiser).
 struct NormDev {
-    double *partials = nullptr;  // nblocks x 14
-    double *out = nullptr;       // 14
-    unsigned int *bad = nullptr;
+    double *partials = nullptr;  // 14 x nblocks
+    double *out = nullptr;       // 15
+    unsigned int *bad = nullptr;  // zero between evaluations
     int nblocks = 0;
     hipStream_t s = nullptr;
     ~NormDev()
@@ -66,21 +66,24 @@ struct NormDev {
     int init(int64_t total, hipStream_t stream)
     {
         s = stream;
-        const int64_t nb = (total + 255) / 256;
-        nblocks = (int)(nb < 2048 ? nb : 2048);
+        // about 8 samples per thread, 64..1024 workgroups
+        const int64_t nb = (total + 2047) / 2048;
+        nblocks = (int)(nb < 64 ? 64 : nb > 1024 ? 1024 : nb);
         NTRY(hipMalloc((void **)&partials, sizeof(double) * 14 * (size_t)nblocks), "hipMalloc");
-        NTRY(hipMalloc((void **)&out, sizeof(double) * 14), "hipMalloc");
+        NTRY(hipMalloc((void **)&out, sizeof(double) * 15), "hipMalloc");
         NTRY(hipMalloc((void **)&bad, sizeof(unsigned int)), "hipMalloc");
+        NTRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s), "hipMemsetAsync");
         return XFDTD_OK;
     }
     // out14: f, df/dc[12], df/ddt.  *nbad: samples with dt^2 F outside (0, 1).
     int eval(const NormArgs &a, double out14[14], unsigned int *nbad)
     {
-        NTRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s), "hipMemsetAsync");
+        double o[15];
         NTRY(launch_norm(a, partials, nblocks, bad, out, s), "norm launch");
-        NTRY(hipMemcpyAsync(out14, out, sizeof(double) * 14, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-        NTRY(hipMemcpyAsync(nbad, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        NTRY(hipMemcpyAsync(o, out, sizeof(double) * 15, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
         NTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        for (int j = 0; j < 14; ++j) out14[j] = o[j];
+        *nbad = (unsigned int)o[14];
         return XFDTD_OK;
     }
 };

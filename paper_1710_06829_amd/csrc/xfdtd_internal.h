@@ -123,7 +123,9 @@ hipError_t launch_dispersion(const double *k, int64_t n, double dt, const double
                              unsigned int *bad, hipStream_t s);
 
 // Dispersion norm (kernels_diag.hip): f_w and its derivatives with respect to
-// the 12 coefficients and dt, out[14] on the device (f, d/dc[12], d/ddt).
+// the 12 coefficients and dt, out[15] on the device (f, d/dc[12], d/ddt, then
+// the number of samples with dt^2 F outside (0, 1)).  `bad` must be 0 on
+// entry and is left 0.
 struct NormArgs {
     double c[12];
     double sp[3];
