@@ -226,3 +226,23 @@ def test_fp32_tilings_agree_bitwise_and_match_oracle(env, shape):
     ce, spe = _fp32.effective(c, dt, sp)
     exp = oracle.c_run(_fp32.round_fields(f0), 6, ce, dt, spe)
     assert rel_l2(outs[0], exp) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_2d_box_anisotropic_spacing(dtype):
+    """The 2D variant (nz = 1: k_z = 0 only) on a grid with d_y = 10 d_x
+    (Sec. 5.3), against the oracle; FP32 under the documented convention."""
+    shape = (1, 48, 200)
+    sp = (1.0, 10.0, 1.0)
+    c = _coeffs(431)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 432)
+    n = 40
+    t = to_dev(f0, dtype)
+    pkg.Solver(t, dt, c, spacing=sp).run(n)
+    got = to_host(t)
+    if dtype == torch.float64:
+        assert rel_l2(got, oracle.c_run(f0, n, c, dt, sp)) < 1e-13
+    else:
+        ce, spe = _fp32.effective(c, dt, sp)
+        assert rel_l2(got, oracle.c_run(_fp32.round_fields(f0), n, ce, dt, spe)) < 2e-6
