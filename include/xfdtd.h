@@ -136,6 +136,18 @@ int xfdtd_step_faraday(xfdtd_t h);
  * E^{n+1} = E^n + dt (D x B^{n+1/2}). */
 int xfdtd_step_ampere(xfdtd_t h);
 
+/*
+ * The Ampere update with a current source (App. A eq. update4-6 with the
+ * mu_0 J term, in the library's units c = mu_0 = 1):
+ *   E^{n+1} = E^n + dt (D x B^{n+1/2}) - dt J^{n+1/2},
+ * in place on the bound fields.  J: three device arrays (Jx, Jy, Jz) of the
+ * handle's dtype and grid shape, at the staggered sites of Ex, Ey, Ez;
+ * caller-owned, read only.  dt is rounded once to the dtype.  A hook for
+ * particle codes: the discrete continuity D.E^{n+1} - D.E^n = -dt D.J holds
+ * exactly (up to rounding).  Asynchronous on the bound stream.
+ */
+int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3]);
+
 /* n >= 0 full steps (Faraday then Ampere each); the result is in the bound
  * fields when the queued work completes. */
 int xfdtd_run(xfdtd_t h, int64_t n);

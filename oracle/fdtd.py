@@ -147,6 +147,18 @@ def ampere(E, B, dt, d):
     return [Ex_n, Ey_n, Ez_n]
 
 
+def ampere_current(E, B, J, dt, d):
+    """E^{n+1} with the current term of update4-6, E += c^2 dt (D x B - mu_0 J),
+    in units c = mu_0 = 1; J = (Jx, Jy, Jz) at the sites of Ex, Ey, Ez."""
+    Ex, Ey, Ez = E
+    Bx, By, Bz = B
+    Jx, Jy, Jz = J
+    Ex_n = Ex + dt * (back_diff(Bz, 1, d) - back_diff(By, 2, d) - Jx)
+    Ey_n = Ey + dt * (back_diff(Bx, 2, d) - back_diff(Bz, 0, d) - Jy)
+    Ez_n = Ez + dt * (back_diff(By, 0, d) - back_diff(Bx, 1, d) - Jz)
+    return [Ex_n, Ey_n, Ez_n]
+
+
 def step(fields, coeffs, dt, d):
     """One leapfrog step: (E^n, B^{n-1/2}) -> (E^{n+1}, B^{n+1/2})."""
     E, B = list(fields[:3]), list(fields[3:])

@@ -58,6 +58,7 @@ SIGNATURES = {
     "xfdtd_bind": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
     "xfdtd_step_faraday": ([_vp], _int),
     "xfdtd_step_ampere": ([_vp], _int),
+    "xfdtd_step_ampere_current": ([_vp, ctypes.POINTER(_vp)], _int),
     "xfdtd_run": ([_vp, _i64], _int),
     "xfdtd_get_weights": ([_vp, _dp, ctypes.POINTER(_int)], _int),
     "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),

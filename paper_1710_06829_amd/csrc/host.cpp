@@ -461,6 +461,27 @@ int xfdtd_step_ampere(xfdtd_t h)
     return XFDTD_OK;
 }
 
+int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3])
+{
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!J || !J[0] || !J[1] || !J[2]) return fail(XFDTD_EINVAL, "J must be three device arrays");
+    const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
+    for (int c = 0; c < 3; ++c)
+        if ((uintptr_t)J[c] % esz) return fail(XFDTD_EINVAL, "J[%d] is misaligned", c);
+    const Dims d = dims_of(h->g);
+    if (h->dtype == XFDTD_F32) {
+        const float *j[3] = {(const float *)J[0], (const float *)J[1], (const float *)J[2]};
+        HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream, j, (float)h->dt),
+                "ampere launch");
+    } else {
+        const double *j[3] = {(const double *)J[0], (const double *)J[1], (const double *)J[2]};
+        HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream, j, h->dt),
+                "ampere launch");
+    }
+    return XFDTD_OK;
+}
+
 int xfdtd_run(xfdtd_t h, int64_t n)
 {
     int rc = check_bound(h);

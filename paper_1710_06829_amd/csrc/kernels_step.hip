@@ -140,7 +140,10 @@ __global__ __launch_bounds__(256) void faraday_kernel(Fields<T> f, Dims d, Weigh
 // unfused Ampere: E += dt (D x B) in place
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weights<T> w)
+// With a current source (jx non-null; App. A eq. update4-6 in c = mu_0 = 1
+// units): E += dt (D x B) - dt J, wj = dt rounded to T.
+__global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weights<T> w, const T *__restrict__ jx,
+                                                     const T *__restrict__ jy, const T *__restrict__ jz, T wj)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -153,6 +156,12 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
     const int64_t pzm = (int64_t)wrap(k - 1, d.nz) * nxy + (int64_t)j * d.nx + i;
     const T *Bx = f.c[3], *By = f.c[4], *Bz = f.c[5];
     const T bx = Bx[p], by = By[p], bz = Bz[p];
+    if (jx) {
+        f.c[0][p] = f.c[0][p] + ((w.wa[1] * (bz - Bz[pym]) - w.wa[2] * (by - By[pzm])) - wj * jx[p]);
+        f.c[1][p] = f.c[1][p] + ((w.wa[2] * (bx - Bx[pzm]) - w.wa[0] * (bz - Bz[pxm])) - wj * jy[p]);
+        f.c[2][p] = f.c[2][p] + ((w.wa[0] * (by - By[pxm]) - w.wa[1] * (bx - Bx[pym])) - wj * jz[p]);
+        return;
+    }
     f.c[0][p] = ampere_eval(f.c[0][p], w.wa[1], bz, Bz[pym], w.wa[2], by, By[pzm]);
     f.c[1][p] = ampere_eval(f.c[1][p], w.wa[2], bx, Bx[pzm], w.wa[0], bz, Bz[pxm]);
     f.c[2][p] = ampere_eval(f.c[2][p], w.wa[0], by, By[pxm], w.wa[1], bx, Bx[pym]);
@@ -488,10 +497,12 @@ hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipSt
 }
 
 template <typename T>
-hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s)
+hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s, const T *const *j,
+                         T wj)
 {
     dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
-    hipLaunchKernelGGL(ampere_kernel<T>, grd, blk, 0, s, f, d, w);
+    hipLaunchKernelGGL(ampere_kernel<T>, grd, blk, 0, s, f, d, w, j ? j[0] : nullptr, j ? j[1] : nullptr,
+                       j ? j[2] : nullptr, wj);
     return hipGetLastError();
 }
 
@@ -558,8 +569,10 @@ template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, 
 template hipError_t launch_batched<double>(const BoxDesc<double> *, const int2 *, int, int, int, int, hipStream_t);
 template hipError_t launch_faraday<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
 template hipError_t launch_faraday<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
-template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
-template hipError_t launch_ampere<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
+template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t,
+                                         const float *const *, float);
+template hipError_t launch_ampere<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t,
+                                          const double *const *, double);
 template hipError_t launch_fused<float>(const Fields<float> &, const Fields<float> &, Dims,
                                         const Weights<float> &, int, int, hipStream_t);
 template hipError_t launch_fused<double>(const Fields<double> &, const Fields<double> &, Dims,

@@ -55,8 +55,10 @@ __device__ __forceinline__ double take(double v)
 // Launchers (kernels_step.hip).  All return hipSuccess or the launch error.
 template <typename T>
 hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s);
+// j (nullable): three device arrays of the current J^{n+1/2}; E -= wj J.
 template <typename T>
-hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s);
+hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s,
+                         const T *const *j = nullptr, T wj = T(0));
 // One fused step from `in` to `out` (distinct buffers).  tile_y: rows per
 // tile (4 or 8), zchunk: planes per workgroup (>= 1).
 template <typename T>

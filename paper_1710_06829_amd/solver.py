@@ -119,9 +119,19 @@ class Solver:
         self._bind()
         B.check(B.lib().xfdtd_step_faraday(self._h))
 
-    def step_ampere(self):
+    def step_ampere(self, J=None):
+        """E^{n+1} = E^n + dt (D x B^{n+1/2}) [- dt J]: J is None or three
+        tensors (Jx, Jy, Jz) of the field dtype and shape."""
         self._bind()
-        B.check(B.lib().xfdtd_step_ampere(self._h))
+        if J is None:
+            B.check(B.lib().xfdtd_step_ampere(self._h))
+            return
+        J = list(J)
+        if len(J) != 3 or any(t.shape != self.fields[0].shape or t.dtype != self.dtype or not t.is_contiguous()
+                               or t.device != self.device for t in J):
+            raise ValueError("J must be three contiguous tensors of the field dtype, shape and device")
+        arr = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in J])
+        B.check(B.lib().xfdtd_step_ampere_current(self._h, arr))
 
     def run(self, n: int):
         self._bind()

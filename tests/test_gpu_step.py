@@ -246,3 +246,39 @@ def test_2d_box_anisotropic_spacing(dtype):
     else:
         ce, spe = _fp32.effective(c, dt, sp)
         assert rel_l2(got, oracle.c_run(_fp32.round_fields(f0), n, ce, dt, spe)) < 2e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ampere_with_current_matches_oracle(dtype):
+    """The current-source hook (App. A eq. update4-6 with mu_0 J): a Faraday
+    step then the Ampere step with J, against the oracle; the GPU divergence
+    diagnostic sees the discrete continuity D.E^{n+1} - D.E^n = -dt D.J."""
+    shape = (9, 20, 70)
+    c = _coeffs(441)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.9 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 442)
+    J = S.uniform_fields(shape, 443)[:3]
+    t = to_dev(f0, dtype)
+    s = pkg.Solver(t, dt, c, spacing=sp, scratch=False)
+    _, de0 = s.divergence()
+    s.step_faraday()
+    s.step_ampere(J=to_dev(J, dtype))
+    got = to_host(t)
+    if dtype == torch.float64:
+        Bn = O.faraday(f0[:3], f0[3:], c, dt, sp)
+        exp = O.ampere_current(f0[:3], Bn, J, dt, sp) + Bn
+        assert rel_l2(got, exp) < 1e-14
+        tol = 1e-11
+    else:
+        ce, spe = _fp32.effective(c, dt, sp)
+        f32 = _fp32.round_fields(f0)
+        dt32 = float(np.float32(dt))
+        Bn = O.faraday(f32[:3], f32[3:], ce, dt, spe)
+        exp = O.ampere_current(f32[:3], Bn, _fp32.round_fields(J), dt32, spe) + Bn
+        assert rel_l2(got, exp) < 1e-6
+        tol = 1e-4
+    _, de1 = s.divergence()
+    ddj = O.div_E(J, sp)
+    err = (de1 - de0).cpu().double().numpy() + dt * ddj
+    assert np.abs(err).max() <= tol * np.abs(dt * ddj).max()

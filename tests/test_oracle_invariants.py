@@ -58,3 +58,24 @@ def test_plain_div_b_conserved_with_eq_beta():
     g = O.run(f, 40, c, dt, D)
     drift = np.abs(O.div_B(g[3:], D) - O.div_B(f[3:], D)).max()
     assert drift < 1e-12
+
+
+def test_current_term_continuity_and_sign():
+    """App. A eq. update4-6 with the mu_0 J term (c = mu_0 = 1): D.D x B = 0
+    makes D.E^{n+1} - D.E^n = -dt D.J exactly; with B = 0 a uniform current
+    changes E by exactly -dt J; J = 0 is the vacuum update."""
+    f = S.uniform_fields((8, 9, 10), 108)
+    J = S.uniform_fields((8, 9, 10), 109)[:3]
+    dt = 0.37
+    E1 = O.ampere_current(f[:3], f[3:], J, dt, D)
+    lhs = O.div_E(E1, D) - O.div_E(f[:3], D)
+    rhs = -dt * O.div_E(J, D)
+    assert np.abs(lhs - rhs).max() < 1e-13
+    zero = [np.zeros_like(x) for x in J]
+    assert all(np.array_equal(a, b) for a, b in zip(O.ampere_current(f[:3], f[3:], zero, dt, D),
+                                                    O.ampere(f[:3], f[3:], dt, D)))
+    Bz = [np.zeros_like(x) for x in J]
+    Ju = [np.full_like(x, v) for x, v in zip(J, (0.5, -1.25, 2.0))]
+    E2 = O.ampere_current(f[:3], Bz, Ju, dt, D)
+    for a in range(3):
+        assert np.abs(E2[a] - (f[a] - dt * Ju[a])).max() < 1e-15
