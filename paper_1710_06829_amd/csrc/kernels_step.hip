@@ -2,7 +2,8 @@
 //
 // One step advances (E^n, B^{n-1/2}) to (E^{n+1}, B^{n+1/2}): the Faraday
 // update with the extended difference D* (App. A, eq. update1-3; D* from
-// Sec. 2) followed by the Yee Ampere update (eq. update4-6, J = 0).
+// Sec. 2) followed by the Yee Ampere update (eq. update4-6; J = 0 except in
+// the unfused Ampere kernel, which optionally subtracts dt J).
 //
 // The extended difference is evaluated as a 7-point "star" of the plain
 // forward difference g(q) = X[q+e_a] - X[q] (see Weights in
@@ -20,8 +21,9 @@
 //       along z (g at k-1, k, k+1; E at k, k+1, k+2; B^{n+1/2} at k-1) are kept
 //       in registers, so z-neighbours never touch LDS.  One barrier per plane
 //       (the Ampere update lags one plane).  Each of the 12 field
-//       values per cell is read and written once from HBM (halo re-reads hit
-//       L2): 48 B (FP32) / 96 B (FP64) per cell-update.
+//       values per cell is read and written once (48 B FP32 / 96 B FP64 per
+//       cell-update); halo re-reads of neighbouring tiles add about a fifth
+//       to the reads where they miss the XCD's L2.
 
 #include <stdlib.h>
 
