@@ -167,12 +167,26 @@ int xfdtd_run(xfdtd_t h, int64_t n);
  */
 int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw);
 
-/* Launch configuration of the fused step chosen for this handle: tile height
- * (rows of the 64-wide (x, y) tile), z-planes per workgroup, and workgroups
- * per launch.  Any pointer may be NULL.  The choice depends on grid and
- * dtype only (overridable with the XFDTD_TILE_Y / XFDTD_ZCHUNK environment
- * variables read at xfdtd_create). */
-int xfdtd_launch_config(xfdtd_t h, int *tile_y, int *zchunk, int *workgroups);
+/* Launch configuration of the fused step for this handle: tile width (64 or
+ * 32 columns), tile height (rows of the (x, y) tile), z-planes per workgroup,
+ * and workgroups per launch.  Any pointer may be NULL.  Until xfdtd_tune is
+ * called the choice depends on grid and dtype only: 32-column tiles for
+ * boxes at most 96 wide that they cover with fewer loaded columns (e.g.
+ * nx = 96), overridable with the XFDTD_TILE_X / XFDTD_TILE_Y / XFDTD_ZCHUNK
+ * environment variables read at xfdtd_create.  Results are bitwise the same
+ * for every configuration. */
+int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *workgroups);
+
+/* Autotunes the fused step's launch configuration for this handle: times
+ * tile widths 64 and 32, tile heights 8 and 16 (FP32; 4 and 8 for FP64) and a
+ * few z-chunk lengths with steps that read the bound fields and write only the
+ * scratch arrays (the state is unchanged), keeps the fastest and caches it
+ * per (grid size, dtype, device); force = 1 re-times, otherwise a cached
+ * choice is taken.  best_ms (nullable) receives the best time per step (-1
+ * when taken from the cache).  Requires bound fields and scratch arrays
+ * (XFDTD_ESTATE otherwise); synchronises the stream.  Results are bitwise
+ * the same for every configuration. */
+int xfdtd_tune(xfdtd_t h, int force, double *best_ms);
 
 /*
  * Dispersion of the scheme at n wave vectors (Sec. 3 and Sec. 5), on the GPU.
@@ -320,13 +334,17 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
  *     per box, handle dtype, 16-byte aligned, no overlaps); stream as in
  *     xfdtd_bind.  Builds the work list (small internal device buffers).
  * xfdtd_batch_tune: times a candidate set of launch configurations (tile
- *     height 4/8, z-split 1/2/4, persistent grid of 1x/2x the CU count or one
- *     workgroup per item) with steps that read the state and write only the
+ *     height 4/8/16 (16: FP32), 32-column tiles as well when a box's nx
+ *     leaves a 64-column tile at most half used, z-split 1/2/4, persistent
+ *     grid of 1x/2x the CU count or one workgroup per item) with steps that read the state and write only the
  *     scratch arrays, keeps the fastest, and caches it per set of box shapes
  *     (force = 1 re-times).  best_ms (nullable) receives the best time per
  *     step (-1 when taken from the cache).  Synchronises the stream.
- * xfdtd_batch_set_config / get_config: choose / report the configuration
- *     (grid 0 = one workgroup per work item); nitems = work-list length.
+ * xfdtd_batch_set_config / get_config: choose / report the configuration:
+ *     tile_x 64 or 32 (default 32 only when every box has nx <= 32),
+ *     tile_y 4, 8 or 16 (16: FP32 only), zsplit 1..1024, grid >= 0
+ *     (0 = one workgroup per work item); nitems = work-list length.
+ *     XFDTD_EINVAL for any other value.
  * xfdtd_batch_run: n >= 0 steps of every box through the cached graph (the
  *     graph is re-captured when n or the configuration changes); the result
  *     is in the bound fields when the queued work completes.
@@ -338,8 +356,8 @@ int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double 
 void xfdtd_batch_destroy(xfdtd_batch_t b);
 int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch, void *stream);
 int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms);
-int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_y, int zsplit, int grid);
-int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_y, int *zsplit, int *grid, int *nitems);
+int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_x, int tile_y, int zsplit, int grid);
+int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems);
 int xfdtd_batch_run(xfdtd_batch_t b, int64_t n);
 int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
 

@@ -61,7 +61,9 @@ SIGNATURES = {
     "xfdtd_step_ampere_current": ([_vp, ctypes.POINTER(_vp)], _int),
     "xfdtd_run": ([_vp, _i64], _int),
     "xfdtd_get_weights": ([_vp, _dp, ctypes.POINTER(_int)], _int),
-    "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
+    "xfdtd_tune": ([_vp, _int, _dp], _int),
+    "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                             ctypes.POINTER(_int)], _int),
     "xfdtd_dispersion": ([_GP, ctypes.c_double, _dp, _vp, _i64, _vp, _vp, _vp, _vp], _int),
     "xfdtd_dispersion_norm": ([_GP, ctypes.c_double, _dp, _int, _i64, _int, ctypes.c_double, _dp, _dp, _vp],
                               _int),
@@ -77,9 +79,9 @@ SIGNATURES = {
     "xfdtd_batch_destroy": ([_vp], None),
     "xfdtd_batch_bind": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
     "xfdtd_batch_tune": ([_vp, _int, _dp], _int),
-    "xfdtd_batch_set_config": ([_vp, _int, _int, _int], _int),
+    "xfdtd_batch_set_config": ([_vp, _int, _int, _int, _int], _int),
     "xfdtd_batch_get_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
-                                ctypes.POINTER(_int)], _int),
+                                ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "xfdtd_batch_run": ([_vp, _i64], _int),
     "xfdtd_batch_run_eager": ([_vp, _i64], _int),
     "xfdtd_batch_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),

@@ -68,13 +68,14 @@ class Batch:
         self.tuned_ms = ms.value
         return self.config()
 
-    def set_config(self, tile_y, zsplit, grid):
-        B.check(B.lib().xfdtd_batch_set_config(self._h, int(tile_y), int(zsplit), int(grid)))
+    def set_config(self, tile_y, zsplit, grid, tile_x=64):
+        B.check(B.lib().xfdtd_batch_set_config(self._h, int(tile_x), int(tile_y), int(zsplit), int(grid)))
 
     def config(self):
-        v = [ctypes.c_int() for _ in range(4)]
+        v = [ctypes.c_int() for _ in range(5)]
         B.check(B.lib().xfdtd_batch_get_config(self._h, *[ctypes.byref(x) for x in v]))
-        return {"tile_y": v[0].value, "zsplit": v[1].value, "grid": v[2].value, "items": v[3].value}
+        return {"tile_x": v[0].value, "tile_y": v[1].value, "zsplit": v[2].value, "grid": v[3].value,
+                "items": v[4].value}
 
     def run(self, n, graph=True):
         fn = B.lib().xfdtd_batch_run if graph else B.lib().xfdtd_batch_run_eager

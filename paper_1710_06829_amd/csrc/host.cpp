@@ -10,7 +10,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/xfdtd.h"
 #include "xfdtd_internal.h"
@@ -186,11 +191,9 @@ void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double 
 
 namespace {
 
-int pick_zchunk(const xfdtd_grid &g, int tile_y)
+int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
 {
-    const char *env = getenv("XFDTD_ZCHUNK");
-    if (env && atoi(env) > 0) return atoi(env);
-    const int64_t ntx = (g.nx + 63) / 64, nty = (g.ny + tile_y - 1) / tile_y;
+    const int64_t ntx = (g.nx + tile_x - 1) / tile_x, nty = (g.ny + tile_y - 1) / tile_y;
     const int64_t tiles = ntx * nty;
     // Long z-marches amortise the 3-plane warm-up of each chunk; split z only
     // when the (x, y) tiles alone would leave CUs idle (fewer than 256
@@ -204,15 +207,34 @@ int pick_zchunk(const xfdtd_grid &g, int tile_y)
     return (int)z;
 }
 
+int pick_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
+{
+    const char *env = getenv("XFDTD_ZCHUNK");
+    if (env && atoi(env) > 0) return atoi(env);
+    return auto_zchunk(g, tile_x, tile_y);
+}
+
 // FP64: 4-row tiles (LDS).  FP32: the 16-row tile (two rows per lane, fewer
 // redundant halo cells per output) whenever its z-chunks stay long (>= 64
 // planes, so the 3-plane warm-up is amortised); 8-row tiles otherwise.
 // Measured on 512x256x256: 16 rows 96 Gcell/s vs 8 rows 88; on 128^3 the
 // 8-row tile with 16-plane chunks is best.
-int pick_tile_y(const xfdtd_grid &g, int dtype)
+int pick_tile_y(const xfdtd_grid &g, int tile_x, int dtype)
 {
     if (dtype == XFDTD_F64) return 4;
-    return pick_zchunk(g, 16) >= 64 ? 16 : 8;
+    return pick_zchunk(g, tile_x, 16) >= 64 ? 16 : 8;
+}
+
+// 32-column tiles for narrow boxes (nx <= 96) that they cover with fewer
+// loaded columns (tile plus its 4 halo columns) than 64-column tiles: nx = 96
+// loads 3 x 36 columns instead of 2 x 68, half of the second 64-wide tile
+// being idle.  Measured: 96^3 20 us per step with 32-wide tiles vs 28 us;
+// for wider boxes the better width depends on the z-chunking (xfdtd_tune
+// times both).
+int pick_tile_x(const xfdtd_grid &g)
+{
+    const int64_t c64 = (g.nx + 63) / 64 * 68, c32 = (g.nx + 31) / 32 * 36;
+    return c32 < c64 && g.nx <= 96 ? 32 : 64;
 }
 
 }  // namespace
@@ -231,7 +253,7 @@ struct xfdtd_s {
     bool bound;
     bool have_scratch;
     hipStream_t stream;
-    int tile_y, zchunk;    // fused step
+    int tile_x, tile_y, zchunk;  // fused step
     int atile_y, azchunk;  // adjoint step
     int device;
     double *partials;  // device, for reductions
@@ -267,12 +289,18 @@ int check_bound(xfdtd_t h)
     return XFDTD_OK;
 }
 
+// the folded weights of the handle's dtype
+template <typename T>
+const Weights<T> &weights_of(const xfdtd_s *h)
+{
+    return *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+}
+
 template <typename T>
 int run_t(xfdtd_t h, int64_t n)
 {
     const Dims d = dims_of(h->g);
-    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf
-                                                                      : (const void *)&h->wd);
+    const Weights<T> &w = weights_of<T>(h);
     Fields<T> f = as_fields<T>(h->fields);
     if (!h->have_scratch) {
         for (int64_t s = 0; s < n; ++s) {
@@ -289,9 +317,101 @@ int run_t(xfdtd_t h, int64_t n)
         --left;
     }
     for (; left > 0; left -= 2) {
-        HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
-        HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+        HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
+        HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
     }
+    return XFDTD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Fused-step tilings chosen by xfdtd_tune, per (nx, ny, nz, dtype, device).
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 5>, std::array<int, 3>> g_tune;
+
+std::array<int64_t, 5> tune_key(const xfdtd_s *h)
+{
+    return {h->g.nx, h->g.ny, h->g.nz, (int64_t)h->dtype, (int64_t)h->device};
+}
+
+// Times each candidate tiling with fused steps fields -> scratch (the bound
+// state is only read) and keeps the fastest.
+template <typename T>
+int tune_t(xfdtd_t h, double *best_ms)
+{
+    const Dims d = dims_of(h->g);
+    const Weights<T> &w = weights_of<T>(h);
+    const Fields<T> f = as_fields<T>(h->fields), s = as_fields<T>(h->scratch);
+    std::vector<std::array<int, 3>> cands;
+    const int tys[2] = {sizeof(T) == 4 ? 8 : 4, sizeof(T) == 4 ? 16 : 8};
+    for (int tx : {64, 32})
+        for (int ty : tys) {
+            const int64_t nz = h->g.nz;
+            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty), nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
+            std::vector<int> seen;
+            for (int64_t z : zs) {
+                if (z > nz) z = nz;
+                if (z < 1 || (z < 8 && z < nz)) continue;
+                bool dup = false;
+                for (int q : seen) dup = dup || q == (int)z;
+                if (dup) continue;
+                seen.push_back((int)z);
+                const int64_t nb = ((d.nx + tx - 1) / tx) * (int64_t)((d.ny + ty - 1) / ty) * ((nz + z - 1) / z);
+                if (nb <= 0x7fffffff) cands.push_back({tx, ty, (int)z});
+            }
+        }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    // Two interleaved passes over the candidates (slow drifts of the clock
+    // hit all of them alike); each timing covers about 2 ms of launches and
+    // a candidate keeps its faster pass.
+    std::vector<double> per(cands.size(), INFINITY);
+    std::vector<int> reps(cands.size(), 0);
+    for (int pass = 0; pass < 2 && he == hipSuccess; ++pass)
+        for (size_t i = 0; i < cands.size() && he == hipSuccess; ++i) {
+            const auto &c = cands[i];
+            auto timed = [&](int r, float *ms) {
+                hipError_t e = hipEventRecord(e0, h->stream);
+                for (int q = 0; q < r && e == hipSuccess; ++q)
+                    e = launch_fused<T>(f, s, d, w, c[0], c[1], c[2], h->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+                return e;
+            };
+            float ms = 0.f;
+            if (reps[i] == 0) {  // warm-up launch, whose time sizes the repetitions
+                he = timed(1, &ms);
+                reps[i] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
+            }
+            if (he == hipSuccess) he = timed(reps[i], &ms);
+            if (he == hipSuccess) per[i] = std::min(per[i], (double)ms / reps[i]);
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    double best = INFINITY;
+    std::array<int, 3> bestc = {h->tile_x, h->tile_y, h->zchunk};
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (per[i] < best) {
+            best = per[i];
+            bestc = cands[i];
+        }
+    if (he != hipSuccess) return hip_fail(he, "tuning launch");
+    h->tile_x = bestc[0];
+    h->tile_y = bestc[1];
+    h->zchunk = bestc[2];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(h)] = bestc;
+    }
+    if (best_ms) *best_ms = best;
     return XFDTD_OK;
 }
 
@@ -299,7 +419,7 @@ int run_t(xfdtd_t h, int64_t n)
 
 extern "C" {
 
-int xfdtd_abi_version(void) { return 1; }
+int xfdtd_abi_version(void) { return 2; }
 
 const char *xfdtd_last_error(void) { return g_err.c_str(); }
 
@@ -365,16 +485,19 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->bound = false;
     h->have_scratch = false;
     h->stream = nullptr;
-    h->tile_y = pick_tile_y(*g, dtype);
+    h->tile_x = pick_tile_x(*g);
+    const char *tx = getenv("XFDTD_TILE_X");
+    if (tx && (atoi(tx) == 32 || atoi(tx) == 64)) h->tile_x = atoi(tx);
+    h->tile_y = pick_tile_y(*g, h->tile_x, dtype);
     const char *ty = getenv("XFDTD_TILE_Y");
     if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
-    h->zchunk = pick_zchunk(*g, h->tile_y);
+    h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y);
     // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
     // fit in LDS), its own z-chunk for that tile height
     h->atile_y = dtype == XFDTD_F64 ? 4 : 8;
     const char *aty = getenv("XFDTD_ADJ_TILE_Y");
     if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && dtype == XFDTD_F32))) h->atile_y = atoi(aty);
-    h->azchunk = pick_zchunk(*g, h->atile_y);
+    h->azchunk = pick_zchunk(*g, 64, h->atile_y);
     const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
     if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
     h->device = -1;
@@ -490,13 +613,33 @@ int xfdtd_run(xfdtd_t h, int64_t n)
     return h->dtype == XFDTD_F32 ? run_t<float>(h, n) : run_t<double>(h, n);
 }
 
-int xfdtd_launch_config(xfdtd_t h, int *tile_y, int *zchunk, int *workgroups)
+int xfdtd_tune(xfdtd_t h, int force, double *best_ms)
+{
+    const int rc = check_bound(h);
+    if (rc) return rc;
+    if (!h->have_scratch) return fail(XFDTD_ESTATE, "tuning times the fused step: bind scratch arrays");
+    if (!force) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(h));
+        if (it != g_tune.end()) {
+            h->tile_x = it->second[0];
+            h->tile_y = it->second[1];
+            h->zchunk = it->second[2];
+            if (best_ms) *best_ms = -1.0;
+            return XFDTD_OK;
+        }
+    }
+    return h->dtype == XFDTD_F32 ? tune_t<float>(h, best_ms) : tune_t<double>(h, best_ms);
+}
+
+int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *workgroups)
 {
     if (!h) return fail(XFDTD_EINVAL, "null handle");
+    if (tile_x) *tile_x = h->tile_x;
     if (tile_y) *tile_y = h->tile_y;
     if (zchunk) *zchunk = h->zchunk;
     if (workgroups) {
-        const int64_t ntx = (h->g.nx + 63) / 64, nty = (h->g.ny + h->tile_y - 1) / h->tile_y;
+        const int64_t ntx = (h->g.nx + h->tile_x - 1) / h->tile_x, nty = (h->g.ny + h->tile_y - 1) / h->tile_y;
         const int64_t nzc = (h->g.nz + h->zchunk - 1) / h->zchunk;
         *workgroups = (int)(ntx * nty * nzc);
     }
@@ -627,7 +770,7 @@ int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T 
                 int accumulate, int reduce)
 {
     const Dims d = dims_of(h->g);
-    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const Weights<T> &w = weights_of<T>(h);
     const int ty = adjoint_tile_y(h);
     HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->azchunk, h->apartials, accumulate, h->stream),
             "adjoint launch");
@@ -679,7 +822,7 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
 {
     const size_t fb = field_bytes(h);
     const Dims d = dims_of(h->g);
-    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const Weights<T> &w = weights_of<T>(h);
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
     const size_t raw = (size_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
     Fields<T> fields = as_fields<T>(h->fields);
@@ -705,7 +848,7 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
         } else {
             dst = (cur.c[0] == A.c[0]) ? B : A;
         }
-        HIP_TRY(launch_fused<T>(cur, dst, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+        HIP_TRY(launch_fused<T>(cur, dst, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
         cur = dst;
     }
     return XFDTD_OK;
@@ -718,7 +861,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
     if (rc) return rc;
     const size_t fb = field_bytes(h);
     const Dims d = dims_of(h->g);
-    const Weights<T> &w = *(const Weights<T> *)(h->dtype == XFDTD_F32 ? (const void *)&h->wf : (const void *)&h->wd);
+    const Weights<T> &w = weights_of<T>(h);
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
     const size_t raw = (size_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
     HIP_TRY(hipMemsetAsync(h->grad_acc, 0, sizeof(double) * 12, h->stream), "hipMemsetAsync");
@@ -745,7 +888,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
             Fields<T> e = segE(s + 1 - s0);
             for (int c = 0; c < 3; ++c) out.c[c] = e.c[c];
             for (int c = 0; c < 3; ++c) out.c[3 + c] = segB.c[3 * ((s - s0) & 1) + c];
-            HIP_TRY(launch_fused<T>(in, out, d, w, h->tile_y, h->zchunk, h->stream), "fused launch");
+            HIP_TRY(launch_fused<T>(in, out, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
             in = out;
         }
         // reverse through the segment

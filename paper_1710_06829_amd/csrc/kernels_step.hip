@@ -172,30 +172,32 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
 // ---------------------------------------------------------------------------
 // fused step, z-march (see the file header)
 // ---------------------------------------------------------------------------
-constexpr int TILE_X = 64;
-
 // Tiling of the fused step: a workgroup of NW row waves plus one halo wave
-// owns a 64 x TY tile with TY = R*NW - 4.  Row wave w owns the rows
-// y = R*w - 2 .. R*w - 2 + R - 1 (lane = x, R positions per lane); the halo
-// wave owns the four halo columns x = -2, -1, TXe, TXe+1 over the same rows,
-// R rows per lane.
-template <int R_, int NW_>
+// owns a TX x TY tile (TX = 64 or 32 columns).  A row wave holds 64 / TX row
+// groups (lane = slot * TX + x); the G = NW * 64 / TX row groups own R rows
+// each, y = R*g - 2 .. R*g - 2 + R - 1, so TY = R*G - 4.  The halo wave owns
+// the four halo columns x = -2, -1, TXe, TXe+1 over the same row groups.
+template <int R_, int NW_, int TX_ = 64>
 struct TileCfg {
     static constexpr int R = R_;
     static constexpr int NW = NW_;
-    static constexpr int TY = R_ * NW_ - 4;
+    static constexpr int TX = TX_;
+    static constexpr int SLOTS = 64 / TX_;
+    static constexpr int G = NW_ * SLOTS;
+    static constexpr int TY = R_ * G - 4;
     static constexpr int THREADS = 64 * (NW_ + 1);
+    static_assert(TX_ == 64 || TX_ == 32, "tile width");
     static_assert(TY > 0, "tile height");
-    static_assert(4 * NW_ <= 64, "halo wave must cover 4 columns x NW row groups");
+    static_assert(4 * G <= 64, "halo wave must cover 4 columns x G row groups");
 };
 
 // LDS of one workgroup of the fused step.  B^{n+1/2} is double-buffered so
 // that the Ampere update can lag one plane behind and read the previous
 // plane's B after the single barrier per plane.
-template <typename T, int TY>
+template <typename T, int TX, int TY>
 struct FusedSmem {
-    static constexpr int PX = TILE_X + 4;  // row pitch: x in [-2, 66)
-    static constexpr int PY = TY + 4;      // rows y in [-2, TY + 2)
+    static constexpr int PX = TX + 4;  // row pitch: x in [-2, TX + 2)
+    static constexpr int PY = TY + 4;  // rows y in [-2, TY + 2)
     static constexpr int P = PX * PY;
     T Ebuf[2][3][P];  // E(k+1), E(k+2)
     T Gbuf[2][6][P];  // g(k), g(k+1)
@@ -210,11 +212,11 @@ struct FusedSmem {
 template <typename T, typename C>
 __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
                                            const Weights<T> &w, int zchunk, int ntx, int nty,
-                                           int logical, FusedSmem<T, C::TY> &sm)
+                                           int logical, FusedSmem<T, C::TX, C::TY> &sm)
 {
-    constexpr int R = C::R, NW = C::NW, TY = C::TY;
-    constexpr int PX = FusedSmem<T, TY>::PX;
-    constexpr int P = FusedSmem<T, TY>::P;
+    constexpr int R = C::R, NW = C::NW, TX = C::TX, TY = C::TY, G = C::G;
+    constexpr int PX = FusedSmem<T, TX, TY>::PX;
+    constexpr int P = FusedSmem<T, TX, TY>::P;
     auto &Ebuf = sm.Ebuf;
     auto &Gbuf = sm.Gbuf;
     auto &Bbuf = sm.Bbuf;
@@ -229,20 +231,20 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
     const int rest = logical / ntx;
     const int ty = rest % nty;
     const int zc = rest / nty;
-    const int x0 = tx * TILE_X, y0 = ty * TY, k0 = zc * zchunk;
-    const int TXe = min(TILE_X, d.nx - x0), TYe = min(TY, d.ny - y0);
+    const int x0 = tx * TX, y0 = ty * TY, k0 = zc * zchunk;
+    const int TXe = min(TX, d.nx - x0), TYe = min(TY, d.ny - y0);
     const int KZe = min(zchunk, d.nz - k0);
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int rx = 0, ry0 = 0;
     bool lane_ok;
     if (wave < NW) {
-        rx = lane;
-        ry0 = R * wave - 2;
+        rx = lane % TX;
+        ry0 = R * (wave * C::SLOTS + lane / TX) - 2;
         lane_ok = rx < TXe;
     } else {
-        const int sel = lane / NW;
-        ry0 = R * (lane % NW) - 2;
+        const int sel = lane / G;
+        ry0 = R * (lane % G) - 2;
         rx = sel == 0 ? -2 : sel == 1 ? -1 : sel == 2 ? TXe : TXe + 1;
         lane_ok = sel < 4;
     }
@@ -457,7 +459,7 @@ template <typename T, typename C>
 __global__ __launch_bounds__(C::THREADS) void fused_step_kernel(Fields<T> in, Fields<T> out, Dims d,
                                                                 Weights<T> w, int zchunk, int ntx, int nty)
 {
-    __shared__ FusedSmem<T, C::TY> sm;
+    __shared__ FusedSmem<T, C::TX, C::TY> sm;
     fused_tile<T, C>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
 }
 
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<
                                                                   const int2 *__restrict__ items,
                                                                   int nitems, int parity)
 {
-    __shared__ FusedSmem<T, C::TY> sm;
+    __shared__ FusedSmem<T, C::TX, C::TY> sm;
     const int slot = xcd_order(blockIdx.x, gridDim.x);
     for (int base = 0; base < nitems; base += gridDim.x) {
         const int i = base + slot;
@@ -483,10 +485,34 @@ __global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<
     }
 }
 
-// tile heights: 4 and 8 with one row per lane, 16 with two rows per lane
+// 64-wide tiles of height 4 and 8 (one row per lane) and 16 (two rows per
+// lane); 32-wide tiles (two row groups per wave) of the same heights, for
+// boxes whose x extent is 32 modulo 64 or too small to fill the CUs.
 using Tile4 = TileCfg<1, 8>;
 using Tile8 = TileCfg<1, 12>;
 using Tile16 = TileCfg<2, 10>;
+using Tile32x4 = TileCfg<1, 4, 32>;
+using Tile32x8 = TileCfg<1, 6, 32>;
+using Tile32x16 = TileCfg<2, 5, 32>;
+
+// Calls f(C{}) with the tile configuration of (tile_x, tile_y); the two-row
+// tiles are FP32 only (FP64 would exceed the LDS of a CU or the registers).
+template <typename T, typename F>
+hipError_t with_tile(int tile_x, int tile_y, F &&f)
+{
+    if (tile_x == 64) {
+        if (tile_y == 4) return f(Tile4{});
+        if (tile_y == 8) return f(Tile8{});
+        if constexpr (sizeof(T) == 4)
+            if (tile_y == 16) return f(Tile16{});
+    } else if (tile_x == 32) {
+        if (tile_y == 4) return f(Tile32x4{});
+        if (tile_y == 8) return f(Tile32x8{});
+        if constexpr (sizeof(T) == 4)
+            if (tile_y == 16) return f(Tile32x16{});
+    }
+    return hipErrorInvalidValue;
+}
 
 }  // namespace
 
@@ -509,66 +535,41 @@ hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStr
 }
 
 template <typename T>
-hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
+hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
                         int tile_y, int zchunk, hipStream_t s)
 {
-    const int ntx = (d.nx + TILE_X - 1) / TILE_X;
+    if (tile_x != 64 && tile_x != 32) return hipErrorInvalidValue;
+    const int ntx = (d.nx + tile_x - 1) / tile_x;
     const int nty = (d.ny + tile_y - 1) / tile_y;
     const int nzc = (d.nz + zchunk - 1) / zchunk;
     const int64_t nb = (int64_t)ntx * nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
-    switch (tile_y) {
-    case 4:
-        hipLaunchKernelGGL((fused_step_kernel<T, Tile4>), dim3((unsigned)nb), dim3(Tile4::THREADS), 0, s,
-                           in, out, d, w, zchunk, ntx, nty);
-        break;
-    case 8:
-        hipLaunchKernelGGL((fused_step_kernel<T, Tile8>), dim3((unsigned)nb), dim3(Tile8::THREADS), 0, s,
-                           in, out, d, w, zchunk, ntx, nty);
-        break;
-    case 16:  // two rows per lane; FP64 would exceed the LDS of a CU
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((fused_step_kernel<T, Tile16>), dim3((unsigned)nb), dim3(Tile16::THREADS), 0, s,
-                               in, out, d, w, zchunk, ntx, nty);
-        else
-            return hipErrorInvalidValue;
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((fused_step_kernel<T, C>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, in, out, d, w,
+                           zchunk, ntx, nty);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
-hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_y,
-                          int grid, hipStream_t s)
+hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_x,
+                          int tile_y, int grid, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     if (grid <= 0 || grid > nitems) grid = nitems;
-    switch (tile_y) {
-    case 4:
-        hipLaunchKernelGGL((batched_step_kernel<T, Tile4>), dim3(grid), dim3(Tile4::THREADS), 0, s, boxes, items,
-                           nitems, parity);
-        break;
-    case 8:
-        hipLaunchKernelGGL((batched_step_kernel<T, Tile8>), dim3(grid), dim3(Tile8::THREADS), 0, s, boxes, items,
-                           nitems, parity);
-        break;
-    case 16:
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((batched_step_kernel<T, Tile16>), dim3(grid), dim3(Tile16::THREADS), 0, s, boxes,
-                               items, nitems, parity);
-        else
-            return hipErrorInvalidValue;
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((batched_step_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items, nitems,
+                           parity);
+        return hipGetLastError();
+    });
 }
 
-template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, int, int, int, int, hipStream_t);
-template hipError_t launch_batched<double>(const BoxDesc<double> *, const int2 *, int, int, int, int, hipStream_t);
+template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, int, int, int, int, int,
+                                          hipStream_t);
+template hipError_t launch_batched<double>(const BoxDesc<double> *, const int2 *, int, int, int, int, int,
+                                           hipStream_t);
 template hipError_t launch_faraday<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
 template hipError_t launch_faraday<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
 template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t,
@@ -576,8 +577,8 @@ template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weig
 template hipError_t launch_ampere<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t,
                                           const double *const *, double);
 template hipError_t launch_fused<float>(const Fields<float> &, const Fields<float> &, Dims,
-                                        const Weights<float> &, int, int, hipStream_t);
+                                        const Weights<float> &, int, int, int, hipStream_t);
 template hipError_t launch_fused<double>(const Fields<double> &, const Fields<double> &, Dims,
-                                         const Weights<double> &, int, int, hipStream_t);
+                                         const Weights<double> &, int, int, int, hipStream_t);
 
 }  // namespace xfdtd

@@ -59,15 +59,16 @@ hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipSt
 template <typename T>
 hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s,
                          const T *const *j = nullptr, T wj = T(0));
-// One fused step from `in` to `out` (distinct buffers).  tile_y: rows per
-// tile (4 or 8), zchunk: planes per workgroup (>= 1).
+// One fused step from `in` to `out` (distinct buffers).  tile_x: columns per
+// tile (64 or 32), tile_y: rows per tile (4, 8, or 16 in FP32), zchunk:
+// planes per workgroup (>= 1).
 template <typename T>
-hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w,
+hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
                         int tile_y, int zchunk, hipStream_t s);
 
 // One box of a batch: state f and scratch s (the step alternates between
-// them), its grid, weights and tiling (64 x tile_y x zchunk, ntx x nty tiles
-// per z-chunk).
+// them), its grid, weights and tiling (tile_x x tile_y x zchunk, ntx x nty
+// tiles per z-chunk).
 template <typename T>
 struct BoxDesc {
     Fields<T> f, s;
@@ -78,8 +79,8 @@ struct BoxDesc {
 // Batched fused step over a work list of (box, tile) pairs (device arrays).
 // grid: persistent workgroup count (<= 0: one per item).
 template <typename T>
-hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_y,
-                          int grid, hipStream_t s);
+hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_x,
+                          int tile_y, int grid, hipStream_t s);
 
 // Adjoint step (kernels_adjoint.hip): lin -> lout (distinct buffers), primal
 // E of the step in en[3]; per-workgroup unscaled gradient sums in partials

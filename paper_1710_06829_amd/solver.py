@@ -137,11 +137,22 @@ class Solver:
         self._bind()
         B.check(B.lib().xfdtd_run(self._h, int(n)))
 
+    def tune(self, force=False):
+        """Autotune the fused step's tiling for this box (needs scratch); the
+        fields are left unchanged.  Returns the chosen launch_config()."""
+        if self.scratch is None:
+            raise ValueError("tuning needs scratch=True")
+        self._bind()
+        ms = ctypes.c_double()
+        B.check(B.lib().xfdtd_tune(self._h, int(bool(force)), ctypes.byref(ms)))
+        self.tuned_ms = ms.value
+        return self.launch_config()
+
     def launch_config(self):
-        """{'tile_y', 'zchunk', 'workgroups'} of the fused step for this box."""
-        v = [ctypes.c_int() for _ in range(3)]
+        """{'tile_x', 'tile_y', 'zchunk', 'workgroups'} of the fused step for this box."""
+        v = [ctypes.c_int() for _ in range(4)]
         B.check(B.lib().xfdtd_launch_config(self._h, *[ctypes.byref(x) for x in v]))
-        return {"tile_y": v[0].value, "zchunk": v[1].value, "workgroups": v[2].value}
+        return {"tile_x": v[0].value, "tile_y": v[1].value, "zchunk": v[2].value, "workgroups": v[3].value}
 
     def weights(self):
         w = (ctypes.c_double * 15)()

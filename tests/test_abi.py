@@ -132,11 +132,26 @@ def test_weight_folding(dtype, npdt):
             assert w[5 * a + m] == float(npdt(exp[m]))
 
 
+@pytest.mark.parametrize("nx,tx", [(96, 32), (32, 32), (80, 32), (5, 32), (48, 64), (128, 64), (160, 64),
+                                   (512, 64)])
+def test_default_tile_width(nx, tx):
+    """Untuned default: 32-column tiles for boxes at most 96 wide that they
+    cover with fewer loaded columns (tile plus four halo columns)."""
+    rc, h = _create(shape=(8, 8, nx))
+    assert rc == 0
+    v = [ctypes.c_int() for _ in range(4)]
+    assert B.lib().xfdtd_launch_config(h, *[ctypes.byref(x) for x in v]) == 0
+    assert v[0].value == tx
+    assert v[3].value == -(-nx // tx) * -(-8 // v[1].value) * -(-8 // v[2].value)
+    B.lib().xfdtd_destroy(h)
+
+
 def test_calls_without_bound_fields_are_state_errors():
     rc, h = _create()
     assert rc == 0
     assert B.lib().xfdtd_run(h, 3) == -5
     assert B.lib().xfdtd_step_faraday(h) == -5
+    assert B.lib().xfdtd_tune(h, 0, None) == -5
     out = (ctypes.c_double * 3)()
     assert B.lib().xfdtd_divergence_max(h, None, None, out) == -5
     B.lib().xfdtd_destroy(h)
@@ -188,9 +203,14 @@ def test_batch_create_validates_every_box():
     # calls before binding are state errors; bad configurations are rejected
     assert B.lib().xfdtd_batch_run(h, 2) == -5
     assert B.lib().xfdtd_batch_tune(h, 0, None) == -5
-    assert B.lib().xfdtd_batch_set_config(h, 5, 1, 0) == -1
-    assert B.lib().xfdtd_batch_set_config(h, 4, 0, 0) == -1
-    assert B.lib().xfdtd_batch_set_config(h, 4, 2, 0) == 0
+    assert B.lib().xfdtd_batch_set_config(h, 64, 5, 1, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 64, 4, 0, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 48, 4, 1, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 64, 4, 2, 0) == 0
+    assert B.lib().xfdtd_batch_set_config(h, 32, 16, 1, 0) == 0
+    tx, ty = ctypes.c_int(), ctypes.c_int()
+    assert B.lib().xfdtd_batch_get_config(h, ctypes.byref(tx), ctypes.byref(ty), None, None, None) == 0
+    assert (tx.value, ty.value) == (32, 16)
     B.lib().xfdtd_batch_destroy(h)
     g0 = (B.Grid * 1)(B.make_grid((0, 5, 6)))
     assert B.lib().xfdtd_batch_create(g0, dts, cc, 1, B.XFDTD_F32, 0, ctypes.byref(h)) == -1

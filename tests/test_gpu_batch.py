@@ -31,7 +31,8 @@ def _small_batch(dtype, seed=700):
     return boxes
 
 
-@pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 0), (8, 4, 3), (4, 1, 1), (8, 2, 512)])
+@pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 0), (8, 4, 3), (4, 1, 1), (8, 2, 512), (4, 1, 0, 32),
+                                 (8, 2, 3, 32)])
 @pytest.mark.parametrize("n", [6, 5])
 @pytest.mark.parametrize("graph", [True, False])
 def test_batch_matches_oracle_fp64(cfg, n, graph):
@@ -51,7 +52,7 @@ def test_batch_graph_replays_and_tuner_keeps_state_fp32():
     ref = [to_dev(f, torch.float32) for (_, f, _, _, _) in boxes]
     bt = pkg.Batch([(t[i], dt, c, sp) for i, (_, _, c, dt, sp) in enumerate(boxes)], tune=True)
     cfg = bt.config()
-    assert cfg["tile_y"] in (4, 8) and cfg["items"] > 0
+    assert cfg["tile_x"] in (32, 64) and cfg["tile_y"] in (4, 8, 16) and cfg["items"] > 0
     for i in range(len(boxes)):  # tuning leaves the state untouched
         assert all(torch.equal(a, b) for a, b in zip(t[i], ref[i]))
     # the same graph replayed three times with host synchronisations in between

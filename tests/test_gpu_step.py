@@ -67,10 +67,11 @@ def test_run_fused_fp64(shape, n):
     assert rel_l2(got, exp) < 1e-13
 
 
+@pytest.mark.parametrize("tile_x", [64, 32])
 @pytest.mark.parametrize("tile_y", [4, 8])
 @pytest.mark.parametrize("zchunk", [1, 3, 8, 64])
-def test_fused_launch_shapes_fp64(env, tile_y, zchunk):
-    env(XFDTD_TILE_Y=tile_y, XFDTD_ZCHUNK=zchunk)
+def test_fused_launch_shapes_fp64(env, tile_x, tile_y, zchunk):
+    env(XFDTD_TILE_X=tile_x, XFDTD_TILE_Y=tile_y, XFDTD_ZCHUNK=zchunk)
     shape = (19, 21, 131)
     c = _coeffs(421)
     dt = 0.95 * O.cfl_dt(c)
@@ -207,25 +208,53 @@ def test_dispersion_flags_unstable_wave_vectors():
 
 @pytest.mark.parametrize("shape", [(37, 45, 150), (16, 33, 64), (3, 17, 5)])
 def test_fp32_tilings_agree_bitwise_and_match_oracle(env, shape):
-    """Every FP32 tiling (4, 8 and 16 rows, the 16-row one with two rows per
-    lane) and z-chunking evaluates the same arithmetic per cell: results are
-    bitwise equal and match the oracle under the FP32 convention."""
+    """Every FP32 tiling (64 and 32 columns; 4, 8 and 16 rows, the 16-row one
+    with two rows per lane) and z-chunking evaluates the same arithmetic per
+    cell: results are bitwise equal and match the oracle under the FP32
+    convention."""
     c = _coeffs(491)
     sp = (1.0, 0.9, 1.1)
     dt = 0.95 * O.cfl_dt(c, sp)
     f0 = S.uniform_fields(shape, 492)
     outs = []
-    for ty in (4, 8, 16):
-        for zc in (2, 7, 64):
-            env(XFDTD_TILE_Y=ty, XFDTD_ZCHUNK=zc)
-            t = to_dev(f0, torch.float32)
-            pkg.Solver(t, dt, c, spacing=sp).run(6)
-            outs.append(to_host(t))
+    for tx in (64, 32):
+        for ty in (4, 8, 16):
+            for zc in (2, 7, 64):
+                env(XFDTD_TILE_X=tx, XFDTD_TILE_Y=ty, XFDTD_ZCHUNK=zc)
+                t = to_dev(f0, torch.float32)
+                s = pkg.Solver(t, dt, c, spacing=sp)
+                assert s.launch_config()["tile_x"] == tx
+                s.run(6)
+                outs.append(to_host(t))
     for o in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
     ce, spe = _fp32.effective(c, dt, sp)
     exp = oracle.c_run(_fp32.round_fields(f0), 6, ce, dt, spe)
     assert rel_l2(outs[0], exp) < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_tuner_keeps_state_and_result(dtype):
+    """Tuning reads the state and writes only scratch; the tuned tiling gives
+    bitwise the same steps as the default one, and a second handle of the same
+    shape takes the cached choice."""
+    shape = (40, 37, 96)
+    c = _coeffs(495)
+    dt = 0.95 * O.cfl_dt(c)
+    f0 = S.uniform_fields(shape, 496)
+    a, b = to_dev(f0, dtype), to_dev(f0, dtype)
+    sa = pkg.Solver(a, dt, c)
+    cfg = sa.tune(force=True)
+    assert sa.tuned_ms > 0
+    assert cfg["tile_x"] in (32, 64) and cfg["zchunk"] >= 1 and cfg["workgroups"] > 0
+    assert all(np.array_equal(x, y) for x, y in zip(to_host(a), to_host(b)))
+    sb = pkg.Solver(b, dt, c)
+    assert sb.tune() == cfg and sb.tuned_ms == -1.0
+    sa.run(6)
+    pkg.Solver(b, dt, c).run(6)
+    assert all(np.array_equal(x, y) for x, y in zip(to_host(a), to_host(b)))
+    with pytest.raises(ValueError):
+        pkg.Solver(b, dt, c, scratch=False).tune()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
