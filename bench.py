@@ -27,7 +27,7 @@ SHAPE = (256, 256, 512)  # (nz, ny, nx)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_06829_amd", "csrc", "kernels_step.hip")
 PROFILE = os.path.join(ROOT, "profiles", "fused_step_512x256x256_fp32.md")
-TILE_NAMES = {(64, 4): "TileCfg<1,8>", (64, 8): "TileCfg<1,12>", (64, 16): "TileCfg<2,10>",
+TILE_NAMES = {(64, 4): "TileCfg<1,8,64>", (64, 8): "TileCfg<1,12,64>", (64, 16): "TileCfg<2,10,64>",
               (32, 4): "TileCfg<1,4,32>", (32, 8): "TileCfg<1,6,32>", (32, 16): "TileCfg<2,5,32>"}
 
 
@@ -170,6 +170,31 @@ def fwd_adj_ratio(steps=200):
             "ratio_all_E_kept": round(t_all / t_fwd, 3),
             "workload": "128^3 FP32 Gaussian pulse (wavelength 12), "
             "probe-plane misfit loss, gradients w.r.t. 12 coefficients and initial fields"}
+
+
+def fp64_step(steps=200):
+    """The 512x256x256 pulse workload in FP64 (tuned launch): rate and the
+    fraction of 8 TB/s at 96 algorithmic bytes per cell-update."""
+    import torch
+
+    import paper_1710_06829_amd as pkg
+
+    fields, coeffs, dt, _ = make_inputs(SHAPE, torch.float64)
+    s = pkg.Solver(fields, dt, coeffs)
+    lc = s.tune()
+    s.run(10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    gc = cells * steps / (ms * 1e-3) / 1e9
+    return {"workload": "512x256x256 FP64 pulse workload, fused step", "steps": steps,
+            "ms_per_step": round(ms / steps, 4), "Gcell_updates_per_s": round(gc, 2),
+            "hbm_roofline_pct": round(100.0 * gc * 96.0 / HBM_PEAK_GBS, 2), "launch": lc}
 
 
 def sustained_large(steps=5000):
@@ -400,7 +425,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-adj", action="store_true")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
@@ -489,6 +514,8 @@ def main():
     if not args.no_adj:
         line["fwd_adj"] = fwd_adj_ratio()
     if not args.no_extra:
+        line["fp64_512x256x256"] = fp64_step()
+        torch.cuda.empty_cache()
         line["sustained_1024x256x256"] = sustained_large()
         torch.cuda.empty_cache()
         line["batched_64_boxes"] = batched_boxes()

@@ -237,7 +237,7 @@ int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double 
     b->dt.assign(dts, dts + m);
     b->coeffs.assign(coeffs, coeffs + 12 * m);
     b->cfg.tile_x = prefer_narrow(b) ? 32 : 64;
-    b->cfg.tile_y = dtype == XFDTD_F64 ? 4 : 8;
+    b->cfg.tile_y = 8;
     b->key = shape_key(b);
     *out = b;
     return XFDTD_OK;
@@ -335,7 +335,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
     for (int tx : {64, 32})
     for (int ty : tys) {
         if (tx == 32 && !narrow) continue;
-        if (b->dtype == XFDTD_F64 && ty != 4) continue;
+        if (b->dtype == XFDTD_F64 && ty == 16) continue;
         for (int zs : {1, 2, 4})
             for (int gm : {0, 1, 2}) {
                 Config c;

@@ -214,14 +214,16 @@ int pick_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
     return auto_zchunk(g, tile_x, tile_y);
 }
 
-// FP64: 4-row tiles (LDS).  FP32: the 16-row tile (two rows per lane, fewer
-// redundant halo cells per output) whenever its z-chunks stay long (>= 64
-// planes, so the 3-plane warm-up is amortised); 8-row tiles otherwise.
-// Measured on 512x256x256: 16 rows 96 Gcell/s vs 8 rows 88; on 128^3 the
-// 8-row tile with 16-plane chunks is best.
+// FP64: 8-row tiles (the largest whose LDS fits a CU; measured on
+// 512x256x256: 54.8 Gcell/s vs 48.1 with 4 rows, and better on 128^3 too).
+// FP32: the 16-row tile (two rows per lane, fewer redundant halo cells per
+// output) whenever its z-chunks stay long (>= 64 planes, so the 3-plane
+// warm-up is amortised); 8-row tiles otherwise.  Measured on 512x256x256:
+// 16 rows 96 Gcell/s vs 8 rows 88; on 128^3 the 8-row tile with 16-plane
+// chunks is best.
 int pick_tile_y(const xfdtd_grid &g, int tile_x, int dtype)
 {
-    if (dtype == XFDTD_F64) return 4;
+    if (dtype == XFDTD_F64) return 8;
     return pick_zchunk(g, tile_x, 16) >= 64 ? 16 : 8;
 }
 
