@@ -191,27 +191,69 @@ void xfdtd::f_range(const double sp[3], const double *c, double *out_lo, double 
 
 namespace {
 
-int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
+int device_cus()
 {
-    const int64_t ntx = (g.nx + tile_x - 1) / tile_x, nty = (g.ny + tile_y - 1) / tile_y;
-    const int64_t tiles = ntx * nty;
-    // Long z-marches amortise the 3-plane warm-up of each chunk; split z only
-    // when the (x, y) tiles alone would leave CUs idle (fewer than 256
-    // workgroups, one per CU).  Measured on the 512x256x256 box: full-depth
-    // chunks (256 workgroups) beat 2048 chunks of 32 planes by 7%.
-    if (tiles >= 256) return (int)g.nz;
-    int64_t nzc = (256 + tiles - 1) / tiles;
-    int64_t z = (g.nz + nzc - 1) / nzc;
-    if (z < 8) z = 8;
-    if (z > g.nz) z = g.nz;
-    return (int)z;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return n;
 }
 
-int pick_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
+// Workgroups that run at once: CUs x resident workgroups per CU (one where
+// the occupancy is unknown, e.g. without a device).
+int64_t fused_slots(int dtype, int tile_x, int tile_y)
+{
+    const int per = dtype == XFDTD_F32 ? fused_occupancy<float>(tile_x, tile_y)
+                                       : fused_occupancy<double>(tile_x, tile_y);
+    return (int64_t)device_cus() * (per > 0 ? per : 1);
+}
+
+int64_t adjoint_slots(int dtype, int tile_y)
+{
+    const int per = dtype == XFDTD_F32 ? adjoint_occupancy<float>(tile_y) : adjoint_occupancy<double>(tile_y);
+    return (int64_t)device_cus() * (per > 0 ? per : 1);
+}
+
+// z-chunk length of a z-march launch over (tile_x x tile_y) tiles.  The
+// workgroups run in rounds of `slots` (all CUs, each with its resident
+// workgroups), a round taking about z + 3 plane iterations (the chunk and its
+// 3-plane warm-up), so the chunk minimises rounds x (z + 3) over z >= 8 (or
+// the whole depth).  A chunk count just above a multiple of `slots` would
+// leave most CUs idle in its last round (the 96^3 adjoint: 264 workgroups of
+// 9 planes, 44.8 us per step, against 216 of 11 planes, 28.1 us).  Measured
+// on 512x256x256 with 64x16 tiles, one workgroup per CU: 128-plane chunks
+// (256 workgroups) beat 2048 chunks of 32 planes by 7 %.
+int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int64_t slots)
+{
+    const int64_t ntx = (g.nx + tile_x - 1) / tile_x, nty = (g.ny + tile_y - 1) / tile_y;
+    const int64_t tiles = ntx * nty, nz = g.nz;
+    if (slots < 1) slots = 1;
+    // beyond four full rounds of chunks, splitting further only adds warm-up
+    const int64_t max_chunks = std::max<int64_t>(1, 4 * slots / tiles + 1);
+    int64_t best_z = nz;
+    double best = INFINITY;
+    for (int64_t c = 1; c <= max_chunks && c <= nz; ++c) {
+        const int64_t z = (nz + c - 1) / c;
+        if (z < 8 && z < nz) break;
+        const int64_t chunks = (nz + z - 1) / z;
+        const int64_t rounds = (tiles * chunks + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(z + 3);
+        if (cost < best) {
+            best = cost;
+            best_z = z;
+        }
+    }
+    return (int)best_z;
+}
+
+int pick_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int dtype)
 {
     const char *env = getenv("XFDTD_ZCHUNK");
     if (env && atoi(env) > 0) return atoi(env);
-    return auto_zchunk(g, tile_x, tile_y);
+    return auto_zchunk(g, tile_x, tile_y, fused_slots(dtype, tile_x, tile_y));
 }
 
 // FP64: 8-row tiles (the largest whose LDS fits a CU; measured on
@@ -224,7 +266,7 @@ int pick_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
 int pick_tile_y(const xfdtd_grid &g, int tile_x, int dtype)
 {
     if (dtype == XFDTD_F64) return 8;
-    return pick_zchunk(g, tile_x, 16) >= 64 ? 16 : 8;
+    return pick_zchunk(g, tile_x, 16, dtype) >= 64 ? 16 : 8;
 }
 
 // 32-column tiles for narrow boxes (nx <= 96) that they cover with fewer
@@ -351,7 +393,7 @@ int tune_t(xfdtd_t h, double *best_ms)
     for (int tx : {64, 32})
         for (int ty : tys) {
             const int64_t nz = h->g.nz;
-            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty), nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
+            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty)), nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
             std::vector<int> seen;
             for (int64_t z : zs) {
                 if (z > nz) z = nz;
@@ -493,13 +535,14 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->tile_y = pick_tile_y(*g, h->tile_x, dtype);
     const char *ty = getenv("XFDTD_TILE_Y");
     if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
-    h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y);
+    h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
     // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
     // fit in LDS), its own z-chunk for that tile height
     h->atile_y = dtype == XFDTD_F64 ? 4 : 8;
     const char *aty = getenv("XFDTD_ADJ_TILE_Y");
     if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && dtype == XFDTD_F32))) h->atile_y = atoi(aty);
-    h->azchunk = pick_zchunk(*g, 64, h->atile_y);
+    h->azchunk = auto_zchunk(*g, 64, h->atile_y, adjoint_slots(dtype, h->atile_y));
+    if (getenv("XFDTD_ZCHUNK") && atoi(getenv("XFDTD_ZCHUNK")) > 0) h->azchunk = atoi(getenv("XFDTD_ZCHUNK"));
     const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
     if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
     h->device = -1;

@@ -461,6 +461,25 @@ hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *
     return hipGetLastError();
 }
 
+template <typename T>
+int adjoint_occupancy(int tile_y)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (tile_y == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_step_kernel<T, 4>, 64 * 9, 0);
+    if constexpr (sizeof(T) == 4)
+        if (tile_y == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_step_kernel<T, 8>, 64 * 13, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template int adjoint_occupancy<float>(int);
+template int adjoint_occupancy<double>(int);
+
 hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
                                   hipStream_t s)
 {

@@ -566,6 +566,23 @@ hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems
     });
 }
 
+template <typename T>
+int fused_occupancy(int tile_x, int tile_y)
+{
+    int n = 0;
+    const hipError_t e = with_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_step_kernel<T, C>, C::THREADS, 0);
+    });
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template int fused_occupancy<float>(int, int);
+template int fused_occupancy<double>(int, int);
 template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, int, int, int, int, int,
                                           hipStream_t);
 template hipError_t launch_batched<double>(const BoxDesc<double> *, const int2 *, int, int, int, int, int,

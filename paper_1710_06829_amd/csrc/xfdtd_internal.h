@@ -66,6 +66,12 @@ template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
                         int tile_y, int zchunk, hipStream_t s);
 
+// Workgroups of the fused step (tile_x x tile_y tiles) resident per CU on
+// the current device, from the HIP occupancy calculator; 0 if unknown (no
+// device, unsupported tile).
+template <typename T>
+int fused_occupancy(int tile_x, int tile_y);
+
 // One box of a batch: state f and scratch s (the step alternates between
 // them), its grid, weights and tiling (tile_x x tile_y x zchunk, ntx x nty
 // tiles per z-chunk).
@@ -89,6 +95,9 @@ struct Scale12 {
     double s[12];
 };
 int adjoint_blocks(Dims d, int tile_y, int zchunk);
+// Workgroups of the adjoint step (64 x tile_y tiles) resident per CU, or 0.
+template <typename T>
+int adjoint_occupancy(int tile_y);
 // accumulate != 0: add to the per-workgroup slots instead of overwriting.
 template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,

@@ -146,6 +146,30 @@ def test_default_tile_width(nx, tx):
     B.lib().xfdtd_destroy(h)
 
 
+@pytest.mark.parametrize("shape", [(96, 96, 96), (128, 128, 128), (256, 256, 512), (192, 192, 352), (9, 40, 70),
+                                   (300, 8, 8)])
+def test_default_zchunk_minimises_round_cost(shape):
+    """Without a device the library assumes 256 CUs with one resident
+    workgroup each; the default z-chunk then minimises rounds x (z + 3) over
+    the balanced chunk lengths ceil(nz / c) >= 8 (or nz), checked by brute
+    force over every chunk count c."""
+    rc, h = _create(shape=shape)
+    assert rc == 0
+    v = [ctypes.c_int() for _ in range(4)]
+    assert B.lib().xfdtd_launch_config(h, *[ctypes.byref(x) for x in v]) == 0
+    B.lib().xfdtd_destroy(h)
+    tx, ty, zc = v[0].value, v[1].value, v[2].value
+    nz, ny, nx = shape
+    tiles = -(-nx // tx) * -(-ny // ty)
+
+    def cost(z):
+        return -(-tiles * -(-nz // z) // 256) * (z + 3)
+
+    zs = [-(-nz // c) for c in range(1, nz + 1)]
+    zs = [z for z in zs if z >= 8 or z == nz]
+    assert cost(zc) == min(cost(z) for z in zs)
+
+
 def test_calls_without_bound_fields_are_state_errors():
     rc, h = _create()
     assert rc == 0
