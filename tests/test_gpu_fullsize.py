@@ -5,7 +5,9 @@ benchmark times (fused kernel, default tiles and z-chunks):
   FP64 oracle (stored by tests/golden/make_c2_samples.py): FP64 to 1e-12,
   FP32 to 1e-5 relative L2 (FP32 convention of tests/_fp32.py);
 * 3 steps, full field, against the C oracle;
-* 1000 steps of an exact discrete eigenmode against its closed form.
+* 1000 steps of an exact discrete eigenmode against its closed form;
+* the 1024x256x256 pulse of the sustained run: 100 steps against sampled
+  outputs of the FP64 oracle (tests/golden/make_c5a_samples.py), same bars.
 """
 import os
 
@@ -50,6 +52,25 @@ def test_c2_pulse_1000_steps_vs_oracle_samples(dtype, variant, tol):
     got = _sampled(t, ref["idx"])
     err = _rel(got, ref["vals"])
     print(f"c2 {variant}: sampled rel L2 = {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("dtype,variant,tol", [(torch.float64, "exact", 1e-12),
+                                               (torch.float32, "fp32", 1e-5)])
+def test_c5a_pulse_100_steps_vs_oracle_samples(dtype, variant, tol):
+    path = os.path.join(GOLD, f"c5a_pulse_{variant}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    ref = np.load(path)
+    f0, c, dt, sp = W.c5a_inputs()
+    assert np.array_equal(ref["coeffs"], c) and float(ref["dt"]) == dt
+    t = to_dev(f0, dtype)
+    del f0
+    s = pkg.Solver(t, dt, c, spacing=sp)
+    s.run(int(ref["steps"]))
+    got = _sampled(t, ref["idx"])
+    err = _rel(got, ref["vals"])
+    print(f"c5a {variant}: sampled rel L2 = {err:.3e}")
     assert err < tol
 
 

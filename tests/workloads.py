@@ -22,6 +22,21 @@ def c2_inputs(shape=C2_SHAPE):
     return f, c, dt, sp
 
 
+C5A_SHAPE = (256, 256, 1024)
+
+
+def c5a_inputs(shape=C5A_SHAPE):
+    """1024x256x256 box: extended set (seed 601), Gaussian pulse along x with
+    wavelength 20, waist 40, duration 50 cells (the 512x256x256 pulse scaled),
+    x0 = nx/4, no noise; dt = 0.95 x the stability bound."""
+    beta, delta = S.extended_beta_delta(601)
+    c = O.coeffs_from(beta, delta)
+    sp = (1.0, 1.0, 1.0)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f = S.gaussian_pulse(shape, dt, wavelength=20.0, waist=40.0, duration=50.0)
+    return f, c, dt, sp
+
+
 def pulse_target_loss_setup(shape, steps, wavelength, waist, duration, x0, dt):
     """Probe plane and target of the field-misfit loss.
 
