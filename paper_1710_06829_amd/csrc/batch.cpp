@@ -332,19 +332,20 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
     bool narrow = false;  // 32-column candidates where some box leaves 64-wide tiles part idle
     for (const xfdtd_grid &g : b->g)
         if (g.nx % 64 != 0 && g.nx % 64 <= 32) narrow = true;
-    for (int tx : {64, 32})
-    for (int ty : tys) {
+    for (int tx : {64, 32}) {
         if (tx == 32 && !narrow) continue;
-        if (b->dtype == XFDTD_F64 && ty == 16) continue;
-        for (int zs : {1, 2, 4})
-            for (int gm : {0, 1, 2}) {
-                Config c;
-                c.tile_x = tx;
-                c.tile_y = ty;
-                c.zsplit = zs;
-                c.grid = gm == 0 ? 0 : gm * ncu;
-                cands.push_back(c);
-            }
+        for (int ty : tys) {
+            if (b->dtype == XFDTD_F64 && ty == 16) continue;
+            for (int zs : {1, 2, 4})
+                for (int gm : {0, 1, 2}) {
+                    Config c;
+                    c.tile_x = tx;
+                    c.tile_y = ty;
+                    c.zsplit = zs;
+                    c.grid = gm == 0 ? 0 : gm * ncu;
+                    cands.push_back(c);
+                }
+        }
     }
     hipEvent_t e0, e1;
     BTRY(hipEventCreate(&e0), "hipEventCreate");
@@ -357,6 +358,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
     // candidate keeps its faster pass.
     std::vector<double> per(cands.size(), INFINITY);
     std::vector<int> reps(cands.size(), 0);
+    const Config prev = b->cfg;
     int rc = XFDTD_OK;
     auto timed = [&](int r, float *ms) {
         int q = hipEventRecord(e0, b->stream) == hipSuccess ? XFDTD_OK : set_error(XFDTD_EHIP, "event record");
@@ -381,9 +383,15 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (rc) return rc;
+    if (rc) {  // keep the configuration the batch had (its error, if any, is secondary)
+        const std::string msg = xfdtd_last_error();
+        b->cfg = prev;
+        build(b);
+        set_error(rc, "%s", msg.c_str());
+        return rc;
+    }
     double best = INFINITY;
-    Config bestc = b->cfg;
+    Config bestc = prev;
     for (size_t i = 0; i < cands.size(); ++i)
         if (per[i] < best) {
             best = per[i];

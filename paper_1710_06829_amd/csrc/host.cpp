@@ -393,7 +393,8 @@ int tune_t(xfdtd_t h, double *best_ms)
     for (int tx : {64, 32})
         for (int ty : tys) {
             const int64_t nz = h->g.nz;
-            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty)), nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
+            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty)),
+                                   nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
             std::vector<int> seen;
             for (int64_t z : zs) {
                 if (z > nz) z = nz;
