@@ -77,6 +77,44 @@ int cus()
     return n > 0 ? n : 256;
 }
 
+// z-chunk length of a box under a z-split (at least 4 planes, or the depth)
+int64_t box_zchunk(const xfdtd_grid &g, int zsplit)
+{
+    int64_t zc = (g.nz + zsplit - 1) / zsplit;
+    if (zc < 4) zc = std::min<int64_t>(4, g.nz);
+    return zc;
+}
+
+// Untuned z-split of a batch from a cost model of one step: the work items
+// (tiles x z-chunks of every box) cost their chunk plus a 3-plane warm-up in
+// plane iterations, run `slots` at a time (CUs x resident workgroups), and
+// no item can finish before its own chunk, so a step takes about
+// max(total / slots, longest item).  Small batches need the z-split to fill
+// the CUs at all: one 96^3 box with z-split 1 gives 24 work items.
+int model_zsplit(const xfdtd_batch_s *b, int tile_x, int tile_y)
+{
+    const int per = b->dtype == XFDTD_F32 ? fused_occupancy<float>(tile_x, tile_y)
+                                          : fused_occupancy<double>(tile_x, tile_y);
+    const double slots = (double)cus() * (per > 0 ? per : 1);
+    int best_s = 1;
+    double best = INFINITY;
+    for (int zs = 1; zs <= 64; zs *= 2) {
+        double total = 0, longest = 0;
+        for (const xfdtd_grid &g : b->g) {
+            const int64_t zc = box_zchunk(g, zs);
+            const double tiles = (double)((g.nx + tile_x - 1) / tile_x) * (double)((g.ny + tile_y - 1) / tile_y);
+            total += tiles * (double)((g.nz + zc - 1) / zc) * (double)(zc + 3);
+            longest = std::max(longest, (double)(zc + 3));
+        }
+        const double cost = std::max(std::ceil(total / slots), longest);
+        if (cost < best) {
+            best = cost;
+            best_s = zs;
+        }
+    }
+    return best_s;
+}
+
 void drop_graph(xfdtd_batch_t b)
 {
     if (b->gexec) {
@@ -114,9 +152,7 @@ int build_t(xfdtd_batch_t b)
         d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
         const double sp[3] = {g.dx, g.dy, g.dz};
         d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
-        int zc = (int)((g.nz + b->cfg.zsplit - 1) / b->cfg.zsplit);
-        if (zc < 4) zc = (int)std::min<int64_t>(4, g.nz);
-        d.zchunk = zc;
+        d.zchunk = (int)box_zchunk(g, b->cfg.zsplit);
         d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
         d.nty = (int)((g.ny + ty - 1) / ty);
         d.pad = 0;
@@ -238,6 +274,7 @@ int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double 
     b->coeffs.assign(coeffs, coeffs + 12 * m);
     b->cfg.tile_x = prefer_narrow(b) ? 32 : 64;
     b->cfg.tile_y = 8;
+    b->cfg.zsplit = model_zsplit(b, b->cfg.tile_x, b->cfg.tile_y);
     b->key = shape_key(b);
     *out = b;
     return XFDTD_OK;
@@ -336,7 +373,9 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         if (tx == 32 && !narrow) continue;
         for (int ty : tys) {
             if (b->dtype == XFDTD_F64 && ty == 16) continue;
-            for (int zs : {1, 2, 4})
+            const int zm = model_zsplit(b, tx, ty);
+            for (int zs : {1, 2, 4, zm}) {
+                if (zs == zm && (zm == 1 || zm == 2 || zm == 4)) continue;  // already a candidate
                 for (int gm : {0, 1, 2}) {
                     Config c;
                     c.tile_x = tx;
@@ -345,6 +384,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
                     c.grid = gm == 0 ? 0 : gm * ncu;
                     cands.push_back(c);
                 }
+            }
         }
     }
     hipEvent_t e0, e1;
@@ -512,9 +552,7 @@ BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, cons
     d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
     const double sp[3] = {g.dx, g.dy, g.dz};
     d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
-    int zc = (int)((g.nz + b->cfg.zsplit - 1) / b->cfg.zsplit);
-    if (zc < 4) zc = (int)std::min<int64_t>(4, g.nz);
-    d.zchunk = zc;
+    d.zchunk = (int)box_zchunk(g, b->cfg.zsplit);
     d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
     d.nty = (int)((g.ny + b->cfg.tile_y - 1) / b->cfg.tile_y);
     d.pad = 0;

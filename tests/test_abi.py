@@ -241,6 +241,31 @@ def test_batch_create_validates_every_box():
     assert B.lib().xfdtd_batch_create(grids, dts, cc, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
 
 
+def test_batch_default_zsplit_fills_the_cus():
+    """Untuned batches split z so that a small batch still has work for every
+    CU (one 96^3 box: 24 tiles), but leave large boxes whole."""
+    beta, delta = S.extended_beta_delta(9)
+    c = O.coeffs_from(beta, delta)
+    dt = 0.9 * O.cfl_dt(c)
+
+    def zsplit(shapes):
+        m = len(shapes)
+        grids = (B.Grid * m)(*[B.make_grid(sh) for sh in shapes])
+        dts = (ctypes.c_double * m)(*([dt] * m))
+        cc = (ctypes.c_double * (12 * m))(*(list(c) * m))
+        h = ctypes.c_void_p()
+        assert B.lib().xfdtd_batch_create(grids, dts, cc, m, B.XFDTD_F32, 0, ctypes.byref(h)) == 0
+        v = [ctypes.c_int() for _ in range(5)]
+        assert B.lib().xfdtd_batch_get_config(h, *[ctypes.byref(x) for x in v]) == 0
+        B.lib().xfdtd_batch_destroy(h)
+        return v[0].value, v[1].value, v[2].value
+
+    tx, ty, zs = zsplit([(96, 96, 96)])
+    chunk = max(-(-96 // zs), 4)
+    assert -(-96 // tx) * -(-96 // ty) * -(-96 // chunk) >= 256
+    assert zsplit([(256, 256, 512)])[2] == 1
+
+
 def test_batch_bind_rejects_overlap_before_device_work():
     c = O.yee_coeffs()
     grids = (B.Grid * 2)(B.make_grid((4, 4, 4)), B.make_grid((4, 4, 4)))
