@@ -220,7 +220,7 @@ int64_t adjoint_slots(int dtype, int tile_y)
 // z-chunk length of a z-march launch over (tile_x x tile_y) tiles.  The
 // workgroups run in rounds of `slots` (all CUs, each with its resident
 // workgroups), a round taking about z + 3 plane iterations (the chunk and its
-// 3-plane warm-up), so the chunk minimises rounds x (z + 3) over z >= 8 (or
+// 3-plane warm-up), so the chunk minimises rounds x (z + 3) over z >= 4 (or
 // the whole depth).  A chunk count just above a multiple of `slots` would
 // leave most CUs idle in its last round (the 96^3 adjoint: 264 workgroups of
 // 9 planes, 44.8 us per step, against 216 of 11 planes, 28.1 us).  Measured
@@ -237,7 +237,7 @@ int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int64_t slots)
     double best = INFINITY;
     for (int64_t c = 1; c <= max_chunks && c <= nz; ++c) {
         const int64_t z = (nz + c - 1) / c;
-        if (z < 8 && z < nz) break;
+        if (z < 4 && z < nz) break;
         const int64_t chunks = (nz + z - 1) / z;
         const int64_t rounds = (tiles * chunks + slots - 1) / slots;
         const double cost = (double)rounds * (double)(z + 3);
@@ -398,7 +398,7 @@ int tune_t(xfdtd_t h, double *best_ms)
             std::vector<int> seen;
             for (int64_t z : zs) {
                 if (z > nz) z = nz;
-                if (z < 1 || (z < 8 && z < nz)) continue;
+                if (z < 1 || (z < 4 && z < nz)) continue;
                 bool dup = false;
                 for (int q : seen) dup = dup || q == (int)z;
                 if (dup) continue;

@@ -151,7 +151,7 @@ def test_default_tile_width(nx, tx):
 def test_default_zchunk_minimises_round_cost(shape):
     """Without a device the library assumes 256 CUs with one resident
     workgroup each; the default z-chunk then minimises rounds x (z + 3) over
-    the balanced chunk lengths ceil(nz / c) >= 8 (or nz), checked by brute
+    the balanced chunk lengths ceil(nz / c) >= 4 (or nz), checked by brute
     force over every chunk count c."""
     rc, h = _create(shape=shape)
     assert rc == 0
@@ -166,7 +166,7 @@ def test_default_zchunk_minimises_round_cost(shape):
         return -(-tiles * -(-nz // z) // 256) * (z + 3)
 
     zs = [-(-nz // c) for c in range(1, nz + 1)]
-    zs = [z for z in zs if z >= 8 or z == nz]
+    zs = [z for z in zs if z >= 4 or z == nz]
     assert cost(zc) == min(cost(z) for z in zs)
 
 
