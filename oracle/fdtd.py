@@ -449,15 +449,20 @@ def laplacian_star(X, coeffs, d):
 # ----------------------------------------------------------------------------
 # special inputs: exact eigenmode and the D*-divergence-free projection
 # ----------------------------------------------------------------------------
-def plane_wave(shape, modes, dt, coeffs, d=(1.0, 1.0, 1.0), pol=(0.3, -0.5, 0.8)):
-    """Exact discrete eigenmode with integer mode numbers ``modes`` = (mx,my,mz).
+STAGGER = ((0.5, 0, 0), (0, 0.5, 0), (0, 0, 0.5), (0, 0.5, 0.5), (0.5, 0, 0.5), (0.5, 0.5, 0))
+
+
+def plane_wave_params(shape, modes, dt, coeffs, d=(1.0, 1.0, 1.0), pol=(0.3, -0.5, 0.8)):
+    """Parameters of the exact discrete eigenmode with integer mode numbers
+    ``modes`` = (mx, my, mz) on a periodic ``shape`` = (nz, ny, nx) grid.
 
     Fourier symbols (Sec. 3): D_a -> i K_a, D*_a -> i K_a A_a with
     K_a = 2 sin(theta_a/2)/d_a, and the time difference -> -i W with
     W = 2 sin(omega dt/2)/dt.  Then Ehat is any unit vector with K.Ehat = 0 and
     Bhat = (K* x Ehat)/W, K*_a = K_a A_a, W^2 = K.K* (eq. dispersion_relation).
-    E is sampled at t = 0, B at t = -dt/2, each at its staggered sites.
-    Returns (fields, omega, Ehat, Bhat, k).
+    Component c of the mode at step n is amp_c cos(k . x_c - omega t_c) at its
+    staggered sites x_c (``STAGGER``), with t = n dt for E and (n - 1/2) dt
+    for B.  Returns (omega, Ehat, Bhat, k).
     """
     nz, ny, nx = shape
     n = (nx, ny, nz)
@@ -474,7 +479,33 @@ def plane_wave(shape, modes, dt, coeffs, d=(1.0, 1.0, 1.0), pol=(0.3, -0.5, 0.8)
     Eh = p - (p @ Kh) * Kh
     Eh /= np.linalg.norm(Eh)
     Bh = np.cross(Ks, Eh) / W
-    stag = ((0.5, 0, 0), (0, 0.5, 0), (0, 0, 0.5), (0, 0.5, 0.5), (0.5, 0, 0.5), (0.5, 0.5, 0))
+    return w, Eh, Bh, k
+
+
+def plane_wave_sample(shape, params, comp, flat_idx, nsteps, dt, d=(1.0, 1.0, 1.0)):
+    """Component ``comp`` (0..5 = Ex..Bz) of the eigenmode ``params`` after
+    ``nsteps`` steps at the flat storage indices ``flat_idx`` ((k ny + j) nx + i)."""
+    w, Eh, Bh, k = params
+    nz, ny, nx = shape
+    d = np.asarray(d, dtype=np.float64)
+    idx = np.asarray(flat_idx, dtype=np.int64)
+    i, j, kk = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    ox, oy, oz = STAGGER[comp]
+    phase = k[0] * (i + ox) * d[0] + k[1] * (j + oy) * d[1] + k[2] * (kk + oz) * d[2]
+    if comp < 3:
+        return Eh[comp] * np.cos(phase - w * nsteps * dt)
+    return Bh[comp - 3] * np.cos(phase - w * (nsteps - 0.5) * dt)
+
+
+def plane_wave(shape, modes, dt, coeffs, d=(1.0, 1.0, 1.0), pol=(0.3, -0.5, 0.8)):
+    """Exact discrete eigenmode with integer mode numbers ``modes`` = (mx,my,mz)
+    (see ``plane_wave_params``): E sampled at t = 0, B at t = -dt/2, each at
+    its staggered sites.  Returns (fields, omega, Ehat, Bhat, k).
+    """
+    nz, ny, nx = shape
+    d = np.asarray(d, dtype=np.float64)
+    w, Eh, Bh, k = plane_wave_params(shape, modes, dt, coeffs, d, pol)
+    stag = STAGGER
     fields = []
     for c in range(6):
         ox, oy, oz = stag[c]

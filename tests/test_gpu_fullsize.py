@@ -7,7 +7,10 @@ benchmark times (fused kernel, tiling chosen by the autotuner):
 * 3 steps, full field, against the C oracle;
 * 1000 steps of an exact discrete eigenmode against its closed form;
 * the 1024x256x256 pulse of the sustained run: 100 steps against sampled
-  outputs of the FP64 oracle (tests/golden/make_c5a_samples.py), same bars.
+  outputs of the FP64 oracle (tests/golden/make_c5a_samples.py), same bars;
+* the largest plane the library accepts (16384 x 16384 = 2^28 cells, where
+  the kernels' 32-bit lane byte offsets come closest to their limit): an
+  exact eigenmode after 20 steps against its closed form at sampled sites.
 """
 import os
 
@@ -16,6 +19,7 @@ import pytest
 import torch
 
 import oracle
+import synthetic as S
 from oracle import fdtd as O
 import paper_1710_06829_amd as pkg
 from tests import _fp32
@@ -106,4 +110,43 @@ def test_c2_eigenmode_1000_steps(dtype, tol):
     got = to_host(t)
     err = rel_l2(got, exp)
     print(f"eigenmode {dtype}: rel L2 = {err:.3e}")
+    assert err < tol
+
+
+def _mode_on_device(shape, params, dt, d, dtype):
+    """The eigenmode of the oracle's plane_wave_params at t = 0 (E) and
+    t = -dt/2 (B), evaluated on the device in float64 and cast once."""
+    w, Eh, Bh, k = params
+    nz, ny, nx = shape
+    ar = lambda n, o, h: (torch.arange(n, dtype=torch.float64, device=DEV) + o) * h
+    out = []
+    for c in range(6):
+        ox, oy, oz = O.STAGGER[c]
+        phase = (k[0] * ar(nx, ox, d[0]))[None, None, :] + (k[1] * ar(ny, oy, d[1]))[None, :, None] \
+            + (k[2] * ar(nz, oz, d[2]))[:, None, None]
+        amp, shift = (Eh[c], 0.0) if c < 3 else (Bh[c - 3], 0.5 * w * dt)
+        out.append((float(amp) * torch.cos(phase + shift)).to(dtype).contiguous())
+        del phase
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+def test_largest_plane_eigenmode(dtype, tol):
+    shape = (1, 16384, 16384)
+    _, c, dt, sp = W.c2_inputs((4, 4, 4))  # the c2 coefficients and dt
+    if dtype == torch.float32:
+        ce, spe = _fp32.effective(c, dt, sp)
+    else:
+        ce, spe = c, sp
+    params = O.plane_wave_params(shape, (640, 1000, 0), dt, ce, spe)
+    t = _mode_on_device(shape, params, dt, spe, dtype)
+    s = pkg.Solver(t, dt, c, spacing=sp)
+    assert s.launch_config()["workgroups"] > 0
+    n = 20
+    s.run(n)
+    idx = S.rng(2026).choice(shape[1] * shape[2], size=4096, replace=False)
+    got = _sampled(t, idx)
+    exp = np.stack([O.plane_wave_sample(shape, params, comp, idx, n, dt, spe) for comp in range(6)], axis=1)
+    err = _rel(got, exp)
+    print(f"largest plane {dtype}: sampled rel L2 = {err:.3e}")
     assert err < tol
