@@ -157,3 +157,56 @@ def test_c4_fp32_gradients_vs_fp64_finite_differences():
     gE = to_host([f.grad for f in fields[:3]])
     dE = sum(float(np.sum(gE[a] * u[a])) for a in range(3))
     assert abs(dE - float(ref["dir_e0"])) < 1e-4 * abs(float(ref["dir_e0"]))
+
+
+def test_largest_plane_adjoint_identities_fp64():
+    """On the largest plane the library accepts (16384 x 16384 cells, where the
+    32-bit lane byte offsets come closest to their limit), two properties that
+    hold at any size: the dot-product identity <M^2 x, y> = <x, (M^T)^2 y>
+    (M one fused step, M^T one adjoint step) and the coefficient gradient of
+    L(theta) = <M(theta) x, y>, which is affine in theta, against a central
+    difference."""
+    shape = (1, 16384, 16384)
+    c = _coeffs(621)
+    dt = 0.95 * O.cfl_dt(c)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(622)
+    rnd = lambda: [torch.rand(shape, dtype=torch.float64, device=DEV, generator=gen) * 2 - 1 for _ in range(6)]
+    x, y = rnd(), rnd()
+
+    def dot(a, b):
+        return sum(float((u * v).sum()) for u, v in zip(a, b)), sum(float((u * v).abs().sum()) for u, v in zip(a, b))
+
+    tx = [t.clone() for t in x]
+    pkg.Solver(tx, dt, c).run(2)  # two fused steps
+    s = pkg.Solver([t.clone() for t in x], dt, c, scratch=False)
+    l1 = [torch.empty_like(t) for t in y]
+    l2 = [torch.empty_like(t) for t in y]
+    g = torch.zeros(12, dtype=torch.float64, device=DEV)
+    s.adjoint_step(y, l1, x[:3], g)
+    s.adjoint_step(l1, l2, x[:3], g)
+    lhs, scale = dot(tx, y)
+    rhs, _ = dot(x, l2)
+    del tx, l1, l2
+    assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs, scale)
+
+    # gradient of L(theta) = <M(theta) x, y> for one step, E^0 = x's E
+    lo = [torch.empty_like(t) for t in y]
+    g = torch.zeros(12, dtype=torch.float64, device=DEV)
+    s.adjoint_step(y, lo, x[:3], g)
+    del lo
+    h = 1e-2
+    fd = []
+    for j in range(12):
+        vals = []
+        for sgn in (1.0, -1.0):
+            cp = np.array(c, dtype=np.float64)
+            cp[j] += sgn * h
+            t = [u.clone() for u in x]
+            pkg.Solver(t, dt, cp, scratch=False, allow_unstable=True).run(1)
+            vals.append(dot(t, y)[0])
+            del t
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    got = g.cpu().numpy()
+    fd = np.array(fd)
+    assert np.abs(got - fd).max() <= 1e-7 * np.abs(fd).max(), (got, fd)
