@@ -93,3 +93,29 @@ def test_config3_64_boxes_500_steps():
         worst = max(worst, e)
     print(f"c3 worst sampled rel L2 over 64 boxes: {worst:.3e}")
     assert worst < 1e-5
+
+
+def test_batch_with_largest_plane_box_equals_single_runs_fp32():
+    """A batch holding a box on the largest accepted plane (16384 x 16384
+    cells) next to a tiny box gives bitwise the results of single-box runs
+    (every tiling evaluates the same arithmetic per cell)."""
+    shapes = [(1, 16384, 16384), (5, 4, 3)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(731)
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.distinct_beta_delta(732 + b)
+        c = O.coeffs_from(beta, delta)
+        dt = 0.95 * O.cfl_dt(c)
+        f = [torch.rand(shape, device="cuda", generator=gen) * 2 - 1 for _ in range(6)]
+        boxes.append((f, dt, c))
+    single = []
+    for f, dt, c in boxes:
+        t = [u.clone() for u in f]
+        pkg.Solver(t, dt, c).run(4)
+        single.append(t)
+    bt = pkg.Batch([(f, dt, c) for f, dt, c in boxes], tune=False)
+    bt.run(4)
+    torch.cuda.synchronize()
+    for (f, _, _), t in zip(boxes, single):
+        assert all(torch.equal(a, b) for a, b in zip(f, t))
