@@ -241,6 +241,20 @@ def test_batch_create_validates_every_box():
     assert B.lib().xfdtd_batch_create(grids, dts, cc, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
 
 
+def test_empty_inputs():
+    """Zero-length requests are valid no-ops that touch no pointer; negative
+    lengths and empty batches are argument errors (no device work either)."""
+    g = B.make_grid((4, 4, 4))
+    c = B.dbl_array(O.yee_coeffs(), 12)
+    assert B.lib().xfdtd_dispersion(ctypes.byref(g), 0.3, c, None, 0, None, None, None, None) == 0
+    assert B.lib().xfdtd_dispersion(ctypes.byref(g), 0.3, c, None, -1, None, None, None, None) == -1
+    h = ctypes.c_void_p()
+    grids = (B.Grid * 1)(g)
+    dts = (ctypes.c_double * 1)(0.3)
+    assert B.lib().xfdtd_batch_create(grids, dts, c, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
+    assert b"box count" in B.lib().xfdtd_last_error()
+
+
 def test_batch_default_zsplit_fills_the_cus():
     """Untuned batches split z so that a small batch still has work for every
     CU (one 96^3 box: 24 tiles), but leave large boxes whole."""
