@@ -293,7 +293,11 @@ int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double
  *   e_n[3]     : device, the step's primal input E^n.
  *   grad       : device, 12 doubles; this step's coefficient gradient is added.
  * Arrays have the handle's grid and dtype.  Requires xfdtd_bind (for the
- * stream; the bound fields are not touched).
+ * stream; the bound fields are not touched).  The adjoint's tiling (64 or 32
+ * columns, 4 or 8 rows, z-chunk) is chosen at xfdtd_create like the fused
+ * step's and can be overridden with XFDTD_ADJ_TILE_X / XFDTD_ADJ_TILE_Y /
+ * XFDTD_ADJ_ZCHUNK; lam_out is bitwise the same for every tiling, the
+ * gradient up to the summation order of its FP64 partial sums.
  */
 int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
                        const void *const e_n[3], double *grad);

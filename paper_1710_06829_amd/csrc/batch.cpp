@@ -559,7 +559,13 @@ BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, cons
     return d;
 }
 
-int adj_tile(const xfdtd_batch_s *b) { return b->dtype == XFDTD_F64 ? 4 : (b->cfg.tile_y > 8 ? 8 : b->cfg.tile_y); }
+// The batched adjoint takes the forward's tile width and a tile height it
+// supports (4 or 8; the 64x8 FP64 tile does not fit in LDS).
+int adj_tile(const xfdtd_batch_s *b)
+{
+    if (b->dtype == XFDTD_F64 && b->cfg.tile_x == 64) return 4;
+    return b->cfg.tile_y > 8 ? 8 : b->cfg.tile_y;
+}
 
 template <typename T>
 AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, const Fields<T> &lout,
@@ -573,7 +579,7 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
     a.d = f.d;
     a.w = f.w;
     a.zchunk = f.zchunk;
-    a.ntx = (int)((b->g[i].nx + 63) / 64);  // the adjoint's tiles are 64 wide
+    a.ntx = (int)((b->g[i].nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
     a.nty = (int)((b->g[i].ny + adj_tile(b) - 1) / adj_tile(b));
     a.pad = 0;
     return a;
@@ -754,7 +760,7 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
                                   grid_of(b), b->stream);
         } else {
             e = launch_batched_adjoint<T>(d_a + order[k].off, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
-                                          adj_tile(b), ga, b->stream);
+                                          b->cfg.tile_x, adj_tile(b), ga, b->stream);
             first = false;
         }
         if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));

@@ -211,9 +211,10 @@ int64_t fused_slots(int dtype, int tile_x, int tile_y)
     return (int64_t)device_cus() * (per > 0 ? per : 1);
 }
 
-int64_t adjoint_slots(int dtype, int tile_y)
+int64_t adjoint_slots(int dtype, int tile_x, int tile_y)
 {
-    const int per = dtype == XFDTD_F32 ? adjoint_occupancy<float>(tile_y) : adjoint_occupancy<double>(tile_y);
+    const int per = dtype == XFDTD_F32 ? adjoint_occupancy<float>(tile_x, tile_y)
+                                       : adjoint_occupancy<double>(tile_x, tile_y);
     return (int64_t)device_cus() * (per > 0 ? per : 1);
 }
 
@@ -298,7 +299,7 @@ struct xfdtd_s {
     bool have_scratch;
     hipStream_t stream;
     int tile_x, tile_y, zchunk;  // fused step
-    int atile_y, azchunk;  // adjoint step
+    int atile_x, atile_y, azchunk;  // adjoint step
     int device;
     double *partials;  // device, for reductions
     int npartials;
@@ -539,10 +540,14 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
     // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
     // fit in LDS), its own z-chunk for that tile height
-    h->atile_y = dtype == XFDTD_F64 ? 4 : 8;
+    h->atile_x = pick_tile_x(*g);
+    const char *atx = getenv("XFDTD_ADJ_TILE_X");
+    if (atx && (atoi(atx) == 32 || atoi(atx) == 64)) h->atile_x = atoi(atx);
+    h->atile_y = dtype == XFDTD_F64 && h->atile_x == 64 ? 4 : 8;
     const char *aty = getenv("XFDTD_ADJ_TILE_Y");
-    if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && dtype == XFDTD_F32))) h->atile_y = atoi(aty);
-    h->azchunk = auto_zchunk(*g, 64, h->atile_y, adjoint_slots(dtype, h->atile_y));
+    if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && (dtype == XFDTD_F32 || h->atile_x == 32))))
+        h->atile_y = atoi(aty);
+    h->azchunk = auto_zchunk(*g, h->atile_x, h->atile_y, adjoint_slots(dtype, h->atile_x, h->atile_y));
     if (getenv("XFDTD_ZCHUNK") && atoi(getenv("XFDTD_ZCHUNK")) > 0) h->azchunk = atoi(getenv("XFDTD_ZCHUNK"));
     const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
     if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
@@ -787,7 +792,7 @@ int adjoint_tile_y(const xfdtd_s *h) { return h->atile_y; }
 
 int ensure_adjoint_buffers(xfdtd_t h)
 {
-    const int nb = adjoint_blocks(dims_of(h->g), adjoint_tile_y(h), h->azchunk);
+    const int nb = adjoint_blocks(dims_of(h->g), h->atile_x, adjoint_tile_y(h), h->azchunk);
     if (h->napartials < nb) {
         if (h->apartials) {
             HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -818,11 +823,12 @@ int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T 
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
     const int ty = adjoint_tile_y(h);
-    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, ty, h->azchunk, h->apartials, accumulate, h->stream),
+    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, h->atile_x, ty, h->azchunk, h->apartials, accumulate,
+                              h->stream),
             "adjoint launch");
     if (reduce)
-        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, ty, h->azchunk), grad_scale(h), grad,
-                                       h->stream),
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, h->atile_x, ty, h->azchunk), grad_scale(h),
+                                       grad, h->stream),
                 "reduce launch");
     return XFDTD_OK;
 }
@@ -956,7 +962,8 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
         }
     }
     if (!first)
-        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, adjoint_tile_y(h), h->azchunk), grad_scale(h),
+        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, h->atile_x, adjoint_tile_y(h), h->azchunk),
+                                       grad_scale(h),
                                        h->grad_acc, h->stream),
                 "reduce launch");
     if (lcur.c[0] != lamU.c[0])

@@ -62,37 +62,53 @@ __device__ __forceinline__ void st_plane_a(gptr_a<T> plane, uint32_t off, T v)
     __builtin_nontemporal_store(v, (gptr_a<T>)((gptr_a<char>)plane + off * (uint32_t)sizeof(T)));
 }
 
-constexpr int ATILE_X = 64;
+// Tiling of the adjoint step: a TX x TY tile (TX = 64 or 32 columns) with
+// one row per lane; a row wave holds 64 / TX rows (lane = slot * TX + x) of
+// the TY + 4 rows y = -2 .. TY + 1, and one more wave the four halo columns
+// x = -2, -1, TXe, TXe + 1 over those rows.
+template <int TX_, int TY_>
+struct AdjCfg {
+    static constexpr int TX = TX_;
+    static constexpr int TY = TY_;
+    static constexpr int SLOTS = 64 / TX_;
+    static constexpr int ROWW = (TY_ + 4) / SLOTS;  // row waves
+    static constexpr int WAVES = ROWW + 1;
+    static constexpr int THREADS = 64 * WAVES;
+    static_assert(TX_ == 64 || TX_ == 32, "tile width");
+    static_assert((TY_ + 4) % SLOTS == 0, "rows per row wave");
+    static_assert(4 * (TY_ + 4) <= 64, "halo wave must cover 4 columns x TY + 4 rows");
+};
 
 // gradient slots: the 12-coefficient order (alpha, beta_t1, beta_t2, delta per axis)
 // One workgroup barrier per plane: iteration k forms mu(k+1) and the stars of
 // plane k, and outputs plane k-1 (whose stars' neighbours were written in
 // iteration k-1).  accumulate != 0 adds this step's sums to `partials`
 // (each workgroup owns its 12 slots), else overwrites them.
-template <typename T, int TY>
+template <typename T, typename C>
 struct AdjSmem {
-    static constexpr int PX = ATILE_X + 4;
-    static constexpr int PY = TY + 4;
+    static constexpr int PX = C::TX + 4;
+    static constexpr int PY = C::TY + 4;
     static constexpr int P = PX * PY;
     T LEbuf[2][3][P];  // lE'(k+1), lE'(k+2)
     T Mbuf[2][3][P];   // mu(k), mu(k+1)
     T Sbuf[2][6][P];   // stars of mu at planes k-1, k
     T Ebuf[2][3][P];   // primal E(k), E(k+1)
-    double red[12][TY + 5];
+    double red[12][C::WAVES];
 };
 
 // One tile (number `logical`) of the adjoint step.  slot: this tile's 12
 // gradient sums (written, or added to when accumulate != 0).
-template <typename T, int TY>
+template <typename T, typename C>
 __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<T> &lout,
                                              const T *__restrict__ en_x, const T *__restrict__ en_y,
                                              const T *__restrict__ en_z, const Dims &d, const Weights<T> &w,
-                                             int zchunk, int ntx, int nty, int logical, AdjSmem<T, TY> &sm,
+                                             int zchunk, int ntx, int nty, int logical, AdjSmem<T, C> &sm,
                                              double *__restrict__ slot, int accumulate)
 {
-    constexpr int PX = AdjSmem<T, TY>::PX;
-    constexpr int PY = AdjSmem<T, TY>::PY;
-    constexpr int P = AdjSmem<T, TY>::P;
+    constexpr int TX = C::TX, TY = C::TY;
+    constexpr int PX = AdjSmem<T, C>::PX;
+    constexpr int PY = AdjSmem<T, C>::PY;
+    constexpr int P = AdjSmem<T, C>::P;
     auto &LEbuf = sm.LEbuf;
     auto &Mbuf = sm.Mbuf;
     auto &Sbuf = sm.Sbuf;
@@ -102,16 +118,16 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     const int rest = logical / ntx;
     const int ty = rest % nty;
     const int zc = rest / nty;
-    const int x0 = tx * ATILE_X, y0 = ty * TY, k0 = zc * zchunk;
-    const int TXe = min(ATILE_X, d.nx - x0), TYe = min(TY, d.ny - y0);
+    const int x0 = tx * TX, y0 = ty * TY, k0 = zc * zchunk;
+    const int TXe = min(TX, d.nx - x0), TYe = min(TY, d.ny - y0);
     const int KZe = min(zchunk, d.nz - k0);
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int rx = 0, ry = 0;
     bool valid;
-    if (wave < TY + 4) {
-        ry = wave - 2;
-        rx = lane;
+    if (wave < C::ROWW) {
+        ry = wave * C::SLOTS + lane / TX - 2;
+        rx = lane % TX;
         valid = rx < TXe && ry < TYe + 2;
     } else {
         const int sel = lane / PY;
@@ -337,35 +353,35 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     __syncthreads();
     if (threadIdx.x < 12) {
         double v = 0.0;
-        for (int wv = 0; wv < TY + 5; ++wv) v += red[threadIdx.x][wv];
+        for (int wv = 0; wv < C::WAVES; ++wv) v += red[threadIdx.x][wv];
         slot[threadIdx.x] = accumulate ? slot[threadIdx.x] + v : v;
     }
 }
 
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void adjoint_step_kernel(
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void adjoint_step_kernel(
     Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
     const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
     double *__restrict__ partials, int accumulate)
 {
-    __shared__ AdjSmem<T, TY> sm;
+    __shared__ AdjSmem<T, C> sm;
     const int nb = gridDim.x, bid = blockIdx.x;
     const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
     const int logical = xcd * q + min(xcd, r) + (bid >> 3);
-    adjoint_tile<T, TY>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, logical, sm,
-                        partials + (int64_t)blockIdx.x * 12, accumulate);
+    adjoint_tile<T, C>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, logical, sm,
+                       partials + (int64_t)blockIdx.x * 12, accumulate);
 }
 
 // Batched adjoint step: work item i is tile items[i].y of box items[i].x;
 // its 12 gradient sums live at partials[12 i] (the item list is fixed for a
 // batch, so the sums accumulate per item across steps).
-template <typename T, int TY>
-__global__ __launch_bounds__(64 * (TY + 5)) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
-                                                                        const int2 *__restrict__ items,
-                                                                        int nitems, double *__restrict__ partials,
-                                                                        int accumulate)
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
+                                                                     const int2 *__restrict__ items,
+                                                                     int nitems, double *__restrict__ partials,
+                                                                     int accumulate)
 {
-    __shared__ AdjSmem<T, TY> sm;
+    __shared__ AdjSmem<T, C> sm;
     const int nb = gridDim.x, bid = blockIdx.x;
     const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
     const int slot = xcd * q + min(xcd, r) + (bid >> 3);
@@ -374,8 +390,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void batched_adjoint_kernel(const Ad
         if (i >= nitems) break;
         const int2 it = items[i];
         const AdjDesc<T> &b = boxes[it.x];
-        adjoint_tile<T, TY>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
-                            partials + (int64_t)i * 12, accumulate);
+        adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
+                           partials + (int64_t)i * 12, accumulate);
         __syncthreads();
     }
 }
@@ -424,11 +440,27 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
     if (threadIdx.x < 12) grad[threadIdx.x] += sc.s[threadIdx.x] * sm[threadIdx.x][0];
 }
 
+// Calls f(C{}) with the adjoint tile configuration of (tile_x, tile_y); the
+// 64x8 tile is FP32 only (in FP64 it would exceed the 160 KiB of LDS).
+template <typename T, typename F>
+hipError_t with_adj_tile(int tile_x, int tile_y, F &&f)
+{
+    if (tile_x == 64) {
+        if (tile_y == 4) return f(AdjCfg<64, 4>{});
+        if constexpr (sizeof(T) == 4)
+            if (tile_y == 8) return f(AdjCfg<64, 8>{});
+    } else if (tile_x == 32) {
+        if (tile_y == 4) return f(AdjCfg<32, 4>{});
+        if (tile_y == 8) return f(AdjCfg<32, 8>{});
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-int adjoint_blocks(Dims d, int tile_y, int zchunk)
+int adjoint_blocks(Dims d, int tile_x, int tile_y, int zchunk)
 {
-    const int ntx = (d.nx + ATILE_X - 1) / ATILE_X;
+    const int ntx = (d.nx + tile_x - 1) / tile_x;
     const int nty = (d.ny + tile_y - 1) / tile_y;
     const int nzc = (d.nz + zchunk - 1) / zchunk;
     return ntx * nty * nzc;
@@ -436,40 +468,29 @@ int adjoint_blocks(Dims d, int tile_y, int zchunk)
 
 template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
-                          const Weights<T> &w, int tile_y, int zchunk, double *partials, int accumulate,
-                          hipStream_t s)
+                          const Weights<T> &w, int tile_x, int tile_y, int zchunk, double *partials,
+                          int accumulate, hipStream_t s)
 {
-    const int ntx = (d.nx + ATILE_X - 1) / ATILE_X;
+    if (tile_x != 64 && tile_x != 32) return hipErrorInvalidValue;
+    const int ntx = (d.nx + tile_x - 1) / tile_x;
     const int nty = (d.ny + tile_y - 1) / tile_y;
-    const int nb = adjoint_blocks(d, tile_y, zchunk);
-    switch (tile_y) {
-    case 4:
-        hipLaunchKernelGGL((adjoint_step_kernel<T, 4>), dim3(nb), dim3(64 * 9), 0, s, lin, lout, en[0],
+    const int nb = adjoint_blocks(d, tile_x, tile_y, zchunk);
+    return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((adjoint_step_kernel<T, C>), dim3(nb), dim3(C::THREADS), 0, s, lin, lout, en[0],
                            en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
-        break;
-    case 8:  // FP32 only: the FP64 tile would exceed the 160 KiB of LDS
-        if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((adjoint_step_kernel<T, 8>), dim3(nb), dim3(64 * 13), 0, s, lin, lout, en[0],
-                               en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
-            break;
-        } else {
-            return hipErrorInvalidValue;
-        }
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
-int adjoint_occupancy(int tile_y)
+int adjoint_occupancy(int tile_x, int tile_y)
 {
     int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    if (tile_y == 4)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_step_kernel<T, 4>, 64 * 9, 0);
-    if constexpr (sizeof(T) == 4)
-        if (tile_y == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_step_kernel<T, 8>, 64 * 13, 0);
+    const hipError_t e = with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_step_kernel<T, C>, C::THREADS, 0);
+    });
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -477,8 +498,8 @@ int adjoint_occupancy(int tile_y)
     return n;
 }
 
-template int adjoint_occupancy<float>(int);
-template int adjoint_occupancy<double>(int);
+template int adjoint_occupancy<float>(int, int);
+template int adjoint_occupancy<double>(int, int);
 
 hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
                                   hipStream_t s)
@@ -489,27 +510,16 @@ hipError_t launch_reduce_partials(const double *partials, int nblocks, const Sca
 
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, int nitems, double *partials,
-                                 int accumulate, int tile_y, int grid, hipStream_t s)
+                                 int accumulate, int tile_x, int tile_y, int grid, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     if (grid <= 0 || grid > nitems) grid = nitems;
-    switch (tile_y) {
-    case 4:
-        hipLaunchKernelGGL((batched_adjoint_kernel<T, 4>), dim3(grid), dim3(64 * 9), 0, s, boxes, items, nitems,
-                           partials, accumulate);
-        break;
-    case 8:  // FP32 only, as above
-        if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((batched_adjoint_kernel<T, 8>), dim3(grid), dim3(64 * 13), 0, s, boxes, items,
-                               nitems, partials, accumulate);
-            break;
-        } else {
-            return hipErrorInvalidValue;
-        }
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((batched_adjoint_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items,
+                           nitems, partials, accumulate);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
@@ -520,13 +530,13 @@ hipError_t launch_reduce_boxes(const double *partials, const int *first, int nbo
 }
 
 template hipError_t launch_batched_adjoint<float>(const AdjDesc<float> *, const int2 *, int, double *, int, int,
-                                                  int, hipStream_t);
+                                                  int, int, hipStream_t);
 template hipError_t launch_batched_adjoint<double>(const AdjDesc<double> *, const int2 *, int, double *, int, int,
-                                                   int, hipStream_t);
+                                                   int, int, hipStream_t);
 template hipError_t launch_adjoint<float>(const Fields<float> &, const Fields<float> &, const float *const[3],
-                                          Dims, const Weights<float> &, int, int, double *, int, hipStream_t);
+                                          Dims, const Weights<float> &, int, int, int, double *, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const Fields<double> &, const Fields<double> &,
-                                           const double *const[3], Dims, const Weights<double> &, int, int,
+                                           const double *const[3], Dims, const Weights<double> &, int, int, int,
                                            double *, int, hipStream_t);
 
 }  // namespace xfdtd

@@ -94,15 +94,16 @@ hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems
 struct Scale12 {
     double s[12];
 };
-int adjoint_blocks(Dims d, int tile_y, int zchunk);
-// Workgroups of the adjoint step (64 x tile_y tiles) resident per CU, or 0.
+// Tiles of tile_x (64 or 32) x tile_y (4, or 8 in FP32) cells.
+int adjoint_blocks(Dims d, int tile_x, int tile_y, int zchunk);
+// Workgroups of the adjoint step (tile_x x tile_y tiles) resident per CU, or 0.
 template <typename T>
-int adjoint_occupancy(int tile_y);
+int adjoint_occupancy(int tile_x, int tile_y);
 // accumulate != 0: add to the per-workgroup slots instead of overwriting.
 template <typename T>
 hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], Dims d,
-                          const Weights<T> &w, int tile_y, int zchunk, double *partials, int accumulate,
-                          hipStream_t s);
+                          const Weights<T> &w, int tile_x, int tile_y, int zchunk, double *partials,
+                          int accumulate, hipStream_t s);
 // One box of a batched adjoint step: lambda in/out, the step's primal E.
 template <typename T>
 struct AdjDesc {
@@ -114,7 +115,7 @@ struct AdjDesc {
 };
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, int nitems, double *partials,
-                                 int accumulate, int tile_y, int grid, hipStream_t s);
+                                 int accumulate, int tile_x, int tile_y, int grid, hipStream_t s);
 // grad[12b + j] += scale[12b + j] * sum_{i in [first[b], first[b+1])} partials[12i + j]
 hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
                                double *grad, hipStream_t s);

@@ -23,8 +23,11 @@ def _coeffs(seed):
     return O.coeffs_from(beta, delta)
 
 
+@pytest.mark.parametrize("tile", [("64", "4"), ("32", "4"), ("32", "8")])
 @pytest.mark.parametrize("shape", [(20, 18, 70), (7, 9, 130), (5, 4, 3), (1, 3, 1), (3, 1, 66)])
-def test_adjoint_step_matches_oracle_fp64(shape):
+def test_adjoint_step_matches_oracle_fp64(monkeypatch, shape, tile):
+    monkeypatch.setenv("XFDTD_ADJ_TILE_X", tile[0])
+    monkeypatch.setenv("XFDTD_ADJ_TILE_Y", tile[1])
     c = _coeffs(601)
     sp = (1.0, 0.8, 1.3)
     dt = 0.95 * O.cfl_dt(c, sp)
@@ -39,6 +42,36 @@ def test_adjoint_step_matches_oracle_fp64(shape):
     assert rel_l2(got, exp) < 1e-13
     g = grad.cpu().numpy()
     assert np.abs(g - gexp).max() <= 1e-12 * np.abs(gexp).max()
+
+
+@pytest.mark.parametrize("shape", [(37, 45, 150), (16, 33, 64), (3, 17, 5)])
+def test_adjoint_tilings_agree_fp32(monkeypatch, shape):
+    """Every FP32 adjoint tiling (64 and 32 columns, 4 and 8 rows) and z-chunk
+    evaluates the same arithmetic per cell: the adjoint fields are bitwise
+    equal; the FP64 gradient sums differ only by their summation order."""
+    c = _coeffs(641)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    lam = to_dev(S.uniform_fields(shape, 642), torch.float32)
+    en = to_dev(S.uniform_fields(shape, 643)[:3], torch.float32)
+    outs, grads = [], []
+    for tx in ("64", "32"):
+        for ty in ("4", "8"):
+            for zc in ("3", "64"):
+                monkeypatch.setenv("XFDTD_ADJ_TILE_X", tx)
+                monkeypatch.setenv("XFDTD_ADJ_TILE_Y", ty)
+                monkeypatch.setenv("XFDTD_ADJ_ZCHUNK", zc)
+                s = pkg.Solver(to_dev(S.uniform_fields(shape, 644), torch.float32), dt, c, spacing=sp,
+                               scratch=False)
+                lo = [torch.empty_like(t) for t in lam]
+                g = torch.zeros(12, dtype=torch.float64, device=DEV)
+                s.adjoint_step(lam, lo, en, g)
+                outs.append(to_host(lo))
+                grads.append(g.cpu().numpy())
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+    for g in grads[1:]:
+        assert np.abs(g - grads[0]).max() <= 1e-12 * np.abs(grads[0]).max()
 
 
 def test_adjoint_dot_product_gpu_fp64():
