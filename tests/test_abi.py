@@ -241,6 +241,33 @@ def test_batch_create_validates_every_box():
     assert B.lib().xfdtd_batch_create(grids, dts, cc, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
 
 
+def test_error_messages_are_per_thread():
+    """xfdtd_last_error reports the last failure of the calling thread: two
+    threads failing with different errors at the same time each read their
+    own message (ctypes releases the GIL around the calls)."""
+    import threading
+
+    barrier = threading.Barrier(2)
+    seen = {}
+
+    def worker(name, shape, dt):
+        g = B.make_grid(shape)
+        h = ctypes.c_void_p()
+        c = B.dbl_array(O.yee_coeffs(), 12)
+        for _ in range(200):
+            barrier.wait()
+            rc = B.lib().xfdtd_create(ctypes.byref(g), dt, c, B.XFDTD_F64, 0, ctypes.byref(h))
+            barrier.wait()
+            seen.setdefault(name, set()).add((rc, B.lib().xfdtd_last_error()))
+
+    t1 = threading.Thread(target=worker, args=("grid", (0, 4, 4), 0.3))
+    t2 = threading.Thread(target=worker, args=("dt", (4, 4, 4), -1.0))
+    t1.start(), t2.start()
+    t1.join(), t2.join()
+    assert seen["grid"] == {(-1, b"invalid grid (sizes >= 1, spacings > 0)")}
+    assert len(seen["dt"]) == 1 and b"dt" in next(iter(seen["dt"]))[1]
+
+
 def test_empty_inputs():
     """Zero-length requests are valid no-ops that touch no pointer; negative
     lengths and empty batches are argument errors (no device work either)."""
