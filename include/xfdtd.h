@@ -289,7 +289,9 @@ int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double
  *
  * One reverse step on the handle's stream:
  *   lam_in[6]  : device, dL/d(E^{n+1}, B^{n+1/2}) (Ex..Bz), read only.
- *   lam_out[6] : device, receives dL/d(E^n, B^{n-1/2}); must not overlap lam_in.
+ *   lam_out[6] : device, receives dL/d(E^n, B^{n-1/2}); each array must be
+ *                disjoint from every lam_in, e_n and other lam_out array
+ *                (checked on the host: XFDTD_EINVAL).
  *   e_n[3]     : device, the step's primal input E^n.
  *   grad       : device, 12 doubles; this step's coefficient gradient is added.
  * Arrays have the handle's grid and dtype.  Requires xfdtd_bind (for the

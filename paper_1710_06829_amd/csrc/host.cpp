@@ -921,8 +921,6 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
     Fields<T> lamS = state_at<T>(ws, fb, 6 * nck + 6);
     Fields<T> lamU = as_fields<T>(lam);
     auto segE = [&](int64_t i) {  // E snapshot of step s0 + i, i in [1, seg)
-        T *const *p = nullptr;
-        (void)p;
         Fields<T> f;
         for (int c = 0; c < 3; ++c) f.c[c] = (T *)(ws + (size_t)(6 * nck + 12 + 3 * (i - 1) + c) * fb);
         return f;
@@ -963,8 +961,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
     }
     if (!first)
         HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, h->atile_x, adjoint_tile_y(h), h->azchunk),
-                                       grad_scale(h),
-                                       h->grad_acc, h->stream),
+                                       grad_scale(h), h->grad_acc, h->stream),
                 "reduce launch");
     if (lcur.c[0] != lamU.c[0])
         for (int c = 0; c < 6; ++c)
@@ -992,13 +989,27 @@ extern "C" {
 int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6], const void *const e_n[3],
                        double *grad)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
+    if (!h) return fail(XFDTD_EINVAL, "null handle");
     if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
     for (int c = 0; c < 6; ++c)
-        if (!lam_in[c] || !lam_out[c] || lam_in[c] == lam_out[c]) return fail(XFDTD_EINVAL, "bad lambda arrays");
+        if (!lam_in[c] || !lam_out[c]) return fail(XFDTD_EINVAL, "lambda array %d is null", c);
     for (int c = 0; c < 3; ++c)
         if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
+    // every output array must be disjoint from all inputs and the other outputs
+    const uint64_t bytes = (uint64_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
+    auto overlap = [bytes](const void *a, const void *b) {
+        const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+        return pa < pb + bytes && pb < pa + bytes;
+    };
+    for (int c = 0; c < 6; ++c) {
+        for (int q = 0; q < 6; ++q)
+            if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
+                return fail(XFDTD_EINVAL, "lam_out[%d] overlaps another lambda array", c);
+        for (int q = 0; q < 3; ++q)
+            if (overlap(lam_out[c], e_n[q])) return fail(XFDTD_EINVAL, "lam_out[%d] overlaps e_n[%d]", c, q);
+    }
+    int rc = check_bound(h);
+    if (rc) return rc;
     rc = ensure_adjoint_buffers(h);
     if (rc) return rc;
     if (h->dtype == XFDTD_F32) {

@@ -241,6 +241,26 @@ def test_batch_create_validates_every_box():
     assert B.lib().xfdtd_batch_create(grids, dts, cc, 0, B.XFDTD_F32, 0, ctypes.byref(h)) == -1
 
 
+def test_adjoint_step_rejects_aliased_arrays_before_device_work():
+    rc, h = _create(shape=(4, 4, 4))
+    assert rc == 0
+    nbytes = 64 * 8
+    base = 1 << 40
+    lin = (ctypes.c_void_p * 6)(*[base + i * nbytes for i in range(6)])
+    lout = (ctypes.c_void_p * 6)(*[base + (6 + i) * nbytes for i in range(6)])
+    en = (ctypes.c_void_p * 3)(*[base + (12 + i) * nbytes for i in range(3)])
+    g = (ctypes.c_double * 12)()
+    # valid pointers: passes the host checks, then fails for lack of bound fields
+    assert B.lib().xfdtd_adjoint_step(h, lin, lout, en, g) == -5
+    shifted = (ctypes.c_void_p * 6)(*[base + (5 + i) * nbytes + 8 for i in range(6)])  # overlaps lin[5]
+    assert B.lib().xfdtd_adjoint_step(h, lin, shifted, en, g) == -1
+    on_e = (ctypes.c_void_p * 6)(*[base + (6 + i) * nbytes for i in range(5)] + [base + 13 * nbytes])
+    assert B.lib().xfdtd_adjoint_step(h, lin, on_e, en, g) == -1
+    dup = (ctypes.c_void_p * 6)(*[base + (6 + i) * nbytes for i in range(5)] + [base + 6 * nbytes])
+    assert B.lib().xfdtd_adjoint_step(h, lin, dup, en, g) == -1
+    B.lib().xfdtd_destroy(h)
+
+
 def test_error_messages_are_per_thread():
     """xfdtd_last_error reports the last failure of the calling thread: two
     threads failing with different errors at the same time each read their
