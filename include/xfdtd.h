@@ -142,7 +142,8 @@ int xfdtd_step_ampere(xfdtd_t h);
  *   E^{n+1} = E^n + dt (D x B^{n+1/2}) - dt J^{n+1/2},
  * in place on the bound fields.  J: three device arrays (Jx, Jy, Jz) of the
  * handle's dtype and grid shape, at the staggered sites of Ex, Ey, Ez;
- * caller-owned, read only.  dt is rounded once to the dtype.  A hook for
+ * caller-owned, read only, and must not overlap the bound E arrays
+ * (XFDTD_EINVAL).  dt is rounded once to the dtype.  A hook for
  * particle codes: the discrete continuity D.E^{n+1} - D.E^n = -dt D.J holds
  * exactly (up to rounding).  Asynchronous on the bound stream.
  */
@@ -315,12 +316,15 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
  * xfdtd_grad_workspace: bytes of device workspace for (n, seg).
  * xfdtd_grad_forward:   n steps from the bound fields; the final state is in
  *                       the bound fields, checkpoints in ws (caller-owned,
- *                       ws_bytes >= the workspace size, 256-byte aligned).
+ *                       ws_bytes >= the workspace size, 256-byte aligned,
+ *                       disjoint from the bound fields).
  * xfdtd_grad_backward:  lam[6] (device, handle dtype) holds dL/d(final state)
  *                       on entry and dL/d(initial state) on return; grad
  *                       (host, 12 doubles) receives dL/dcoeffs.  ws must be
  *                       the workspace filled by xfdtd_grad_forward with the
- *                       same n and seg.  Synchronises the stream.
+ *                       same n and seg; the six lam arrays are disjoint from
+ *                       each other and from ws.  Synchronises the stream.
+ * Argument errors are XFDTD_EINVAL, found on the host before any device work.
  */
 int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes);
 int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes);

@@ -327,6 +327,17 @@ Fields<T> as_fields(void *const p[6])
 
 Dims dims_of(const xfdtd_grid &g) { return Dims{(int)g.nx, (int)g.ny, (int)g.nz}; }
 
+bool ranges_overlap(const void *a, uint64_t na, const void *b, uint64_t nb)
+{
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+uint64_t raw_field_bytes(const xfdtd_s *h)
+{
+    return (uint64_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
+}
+
 int check_bound(xfdtd_t h)
 {
     if (!h) return fail(XFDTD_EINVAL, "null handle");
@@ -641,8 +652,12 @@ int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3])
     if (rc) return rc;
     if (!J || !J[0] || !J[1] || !J[2]) return fail(XFDTD_EINVAL, "J must be three device arrays");
     const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
         if ((uintptr_t)J[c] % esz) return fail(XFDTD_EINVAL, "J[%d] is misaligned", c);
+        for (int q = 0; q < 3; ++q)  // E is updated in place while J is read
+            if (ranges_overlap(J[c], raw_field_bytes(h), h->fields[q], raw_field_bytes(h)))
+                return fail(XFDTD_EINVAL, "J[%d] overlaps the bound E[%d]", c, q);
+    }
     const Dims d = dims_of(h->g);
     if (h->dtype == XFDTD_F32) {
         const float *j[3] = {(const float *)J[0], (const float *)J[1], (const float *)J[2]};
@@ -996,11 +1011,8 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
     for (int c = 0; c < 3; ++c)
         if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
     // every output array must be disjoint from all inputs and the other outputs
-    const uint64_t bytes = (uint64_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
-    auto overlap = [bytes](const void *a, const void *b) {
-        const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
-        return pa < pb + bytes && pb < pa + bytes;
-    };
+    const uint64_t bytes = raw_field_bytes(h);
+    auto overlap = [bytes](const void *a, const void *b) { return ranges_overlap(a, bytes, b, bytes); };
     for (int c = 0; c < 6; ++c) {
         for (int q = 0; q < 6; ++q)
             if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
@@ -1036,6 +1048,10 @@ int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_
     seg = default_seg(n, seg);
     rc = check_ws(h, n, seg, ws, ws_bytes);
     if (rc) return rc;
+    const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h);
+    for (int c = 0; c < 6; ++c)
+        if (ranges_overlap(ws, wsb, h->fields[c], raw_field_bytes(h)))
+            return fail(XFDTD_EINVAL, "the workspace overlaps bound field %d", c);
     return h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
                                  : grad_forward_t<double>(h, n, seg, (char *)ws);
 }
@@ -1051,6 +1067,12 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
     seg = default_seg(n, seg);
     rc = check_ws(h, n, seg, ws, ws_bytes);
     if (rc) return rc;
+    const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h), fb = raw_field_bytes(h);
+    for (int c = 0; c < 6; ++c) {
+        if (ranges_overlap(ws, wsb, lam[c], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps the workspace", c);
+        for (int q = c + 1; q < 6; ++q)
+            if (ranges_overlap(lam[c], fb, lam[q], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps lam[%d]", c, q);
+    }
     return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
                                  : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
 }
