@@ -387,6 +387,9 @@ int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
  *   grad : host, m*12 doubles, dL/dcoeffs of each box.
  * The forward leaves the final states in the bound fields.  Both synchronise
  * the stream and allocate small internal buffers (launch descriptors).
+ * Workspaces must be disjoint from each other and (forward) from the bound
+ * fields and scratch arrays; (backward) the lambda arrays from each other and
+ * from the workspaces.  Violations are XFDTD_EINVAL before any device work.
  */
 int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t *bytes);
 int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws,

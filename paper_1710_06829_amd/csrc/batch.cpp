@@ -788,17 +788,39 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     return rc;
 }
 
-int check_bws(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)
+// Workspaces: present, aligned, large enough and disjoint from each other.
+// Forward (lam == nullptr): also disjoint from the bound arrays, which it
+// reads and writes.  Backward: the lambda arrays (it does not touch the bound
+// arrays) disjoint from each other and from the workspaces.
+int check_bws(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes,
+              void *const *lam = nullptr)
 {
     if (!b) return set_error(XFDTD_EINVAL, "null handle");
     if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
     if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
     if (!ws || !ws_bytes) return set_error(XFDTD_EINVAL, "null workspace list");
+    const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int64_t i = 0; i < b->m; ++i) {
-        if (!ws[i] || (uintptr_t)ws[i] % 256) return set_error(XFDTD_EINVAL, "box %lld: workspace null or not 256-byte aligned", (long long)i);
+        if (!ws[i] || (uintptr_t)ws[i] % 256)
+            return set_error(XFDTD_EINVAL, "box %lld: workspace null or not 256-byte aligned", (long long)i);
         const uint64_t need = bws_arrays(n, seg) * box_field_bytes(b, i);
         if (ws_bytes[i] < need) return set_error(XFDTD_EINVAL, "box %lld: workspace too small", (long long)i);
+        spans.push_back({(uintptr_t)ws[i], (uintptr_t)ws[i] + need});
+        const size_t bytes = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
+        for (int c = 0; c < 6; ++c) {
+            if (lam) {
+                spans.push_back({(uintptr_t)lam[6 * i + c], (uintptr_t)lam[6 * i + c] + bytes});
+            } else {
+                spans.push_back({(uintptr_t)b->f[6 * i + c], (uintptr_t)b->f[6 * i + c] + bytes});
+                spans.push_back({(uintptr_t)b->s[6 * i + c], (uintptr_t)b->s[6 * i + c] + bytes});
+            }
+        }
     }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second)
+            return set_error(XFDTD_EINVAL, "workspaces, lambda arrays and bound arrays must not overlap");
     return XFDTD_OK;
 }
 
@@ -827,11 +849,12 @@ int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *con
                               void *const *lam, double *grad)
 {
     seg = bseg(n, seg);
-    int rc = check_bws(b, n, seg, ws, ws_bytes);
-    if (rc) return rc;
+    if (!b) return set_error(XFDTD_EINVAL, "null handle");
     if (!lam || !grad) return set_error(XFDTD_EINVAL, "null argument");
     for (int64_t i = 0; i < 6 * b->m; ++i)
         if (!lam[i]) return set_error(XFDTD_EINVAL, "lam[%lld] is null", (long long)i);
+    int rc = check_bws(b, n, seg, ws, ws_bytes, lam);
+    if (rc) return rc;
     return b->dtype == XFDTD_F32 ? bgrad_backward_t<float>(b, n, seg, ws, lam, grad)
                                  : bgrad_backward_t<double>(b, n, seg, ws, lam, grad);
 }

@@ -243,3 +243,25 @@ def test_largest_plane_adjoint_identities_fp64():
     got = g.cpu().numpy()
     fd = np.array(fd)
     assert np.abs(got - fd).max() <= 1e-7 * np.abs(fd).max(), (got, fd)
+
+
+def test_grad_rejects_aliased_arrays():
+    """Aliased adjoint arrays are argument errors found before device work."""
+    shape = (6, 5, 7)
+    c = _coeffs(651)
+    dt = 0.9 * O.cfl_dt(c)
+    s = pkg.Solver(to_dev(S.uniform_fields(shape, 652)), dt, c, scratch=False)
+    n = 4
+    ws = torch.empty(s.grad_workspace_bytes(n), dtype=torch.uint8, device=DEV)
+    s.grad_forward(n, ws)
+    lam = to_dev(S.uniform_fields(shape, 653))
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws, [lam[0], lam[0]] + lam[2:])
+    inside = ws[: lam[0].numel() * 8].view(torch.float64).view(shape)  # overlaps the workspace
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws, [inside] + lam[1:])
+    lo = [torch.empty_like(t) for t in lam]
+    g = torch.zeros(12, dtype=torch.float64, device=DEV)
+    with pytest.raises(pkg.XfdtdError):
+        s.adjoint_step(lam, [lam[3]] + lo[1:], lam[:3], g)
+    s.grad_backward(n, ws, lam)  # the valid call still works

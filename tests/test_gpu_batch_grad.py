@@ -127,3 +127,22 @@ def test_config5_16_boxes_96cube_300_steps_vs_finite_differences():
     for i in range(len(boxes)):
         got = float(np.dot(g[i], ref["dirs"][i]))
         assert abs(got - dd[i]) < 1e-4 * max(abs(dd[i]), 1e-2 * scale), (i, got, dd[i])
+
+
+def test_batch_grad_rejects_aliased_lambda():
+    """Two boxes handed the same adjoint arrays: an argument error found before
+    device work; distinct arrays then go through."""
+    shape = (6, 5, 7)
+    boxes = []
+    for b in range(2):
+        beta, delta = S.distinct_beta_delta(961 + b)
+        c = O.coeffs_from(beta, delta)
+        boxes.append((to_dev(S.uniform_fields(shape, 963 + b)), 0.9 * O.cfl_dt(c), c))
+    bt = pkg.Batch(boxes, tune=False)
+    n = 3
+    ws = bt.grad_workspaces(n)
+    bt.grad_forward(n, ws)
+    lam = to_dev(S.uniform_fields(shape, 965))
+    with pytest.raises(pkg.XfdtdError):
+        bt.grad_backward(n, ws, [lam, lam])
+    bt.grad_backward(n, ws, [lam, [t.clone() for t in lam]])
