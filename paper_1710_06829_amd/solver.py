@@ -160,9 +160,36 @@ class Solver:
         B.check(B.lib().xfdtd_get_weights(self._h, w, ctypes.byref(nw)))
         return [w[i] for i in range(nw.value)]
 
+    def _check_like(self, tensors, count, what):
+        """``count`` contiguous tensors of the field shape, dtype and device
+        (the library sees only pointers, so sizes are checked here)."""
+        tensors = list(tensors)
+        if len(tensors) != count:
+            raise ValueError(f"{what}: need {count} tensors")
+        for t in tensors:
+            if (not isinstance(t, torch.Tensor) or tuple(t.shape) != self.shape or t.dtype != self.dtype
+                    or t.device != self.device or not t.is_contiguous()):
+                raise ValueError(f"{what}: tensors must be contiguous, of shape {self.shape}, "
+                                 f"dtype {self.dtype} and on {self.device}")
+        return tensors
+
+    def _check_grad(self, grad):
+        if (not isinstance(grad, torch.Tensor) or grad.dtype != torch.float64 or grad.numel() != 12
+                or grad.device != self.device or not grad.is_contiguous()):
+            raise ValueError(f"grad must be a contiguous float64 tensor of 12 values on {self.device}")
+
+    def _check_ws(self, ws):
+        if (not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or ws.device != self.device
+                or not ws.is_contiguous()):
+            raise ValueError(f"the workspace must be a contiguous uint8 tensor on {self.device}")
+
     def adjoint_step(self, lam_in, lam_out, e_n, grad):
         """One reverse step: lam_out = adjoint(lam_in) with primal input E ``e_n``;
         adds this step's coefficient gradient to ``grad`` (float64 CUDA (12,))."""
+        lam_in = self._check_like(lam_in, 6, "lam_in")
+        lam_out = self._check_like(lam_out, 6, "lam_out")
+        e_n = self._check_like(e_n, 3, "e_n")
+        self._check_grad(grad)
         self._bind()
         li = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam_in])
         lo = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam_out])
@@ -175,12 +202,15 @@ class Solver:
         return b.value
 
     def grad_forward(self, n, ws, seg=0):
+        self._check_ws(ws)
         self._bind()
         B.check(B.lib().xfdtd_grad_forward(self._h, int(n), int(seg), _ptr(ws), ws.numel()))
 
     def grad_backward(self, n, ws, lam, seg=0):
         """lam: six tensors, dL/d(final state) in, dL/d(initial state) out.
         Returns dL/dcoeffs as 12 floats."""
+        self._check_ws(ws)
+        lam = self._check_like(lam, 6, "lam")
         self._bind()
         arr = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in lam])
         g = (ctypes.c_double * 12)()
@@ -197,6 +227,9 @@ class Solver:
 
     def divergence_max(self, ref_b=None, ref_e=None, raise_nonfinite=True):
         """(max|D*.B - ref_b|, max|D.E - ref_e|, #non-finite) reduced on the GPU."""
+        for r, name in ((ref_b, "ref_b"), (ref_e, "ref_e")):
+            if r is not None:
+                self._check_like([r], 1, name)
         self._bind()
         out = (ctypes.c_double * 3)()
         rc = B.lib().xfdtd_divergence_max(self._h, _ptr(ref_b) if ref_b is not None else None,

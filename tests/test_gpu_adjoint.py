@@ -265,3 +265,34 @@ def test_grad_rejects_aliased_arrays():
     with pytest.raises(pkg.XfdtdError):
         s.adjoint_step(lam, [lam[3]] + lo[1:], lam[:3], g)
     s.grad_backward(n, ws, lam)  # the valid call still works
+
+
+def test_wrappers_check_tensor_shapes_before_the_library():
+    """The library sees only pointers: the torch wrappers check the count,
+    shape, dtype, device and layout of every tensor they pass."""
+    shape = (6, 5, 7)
+    c = _coeffs(661)
+    dt = 0.9 * O.cfl_dt(c)
+    s = pkg.Solver(to_dev(S.uniform_fields(shape, 662)), dt, c, scratch=False)
+    lam = to_dev(S.uniform_fields(shape, 663))
+    lo = [torch.empty_like(t) for t in lam]
+    g = torch.zeros(12, dtype=torch.float64, device=DEV)
+    small = [t[:, :, :6].contiguous() for t in lo]
+    with pytest.raises(ValueError):
+        s.adjoint_step(lam, small, lam[:3], g)                      # wrong shape
+    with pytest.raises(ValueError):
+        s.adjoint_step(lam, [t.float() for t in lo], lam[:3], g)    # wrong dtype
+    with pytest.raises(ValueError):
+        s.adjoint_step(lam, lo, lam[:2], g)                         # wrong count
+    with pytest.raises(ValueError):
+        s.adjoint_step(lam, lo, lam[:3], g.float())                 # gradient dtype
+    with pytest.raises(ValueError):
+        s.adjoint_step(lam, [t.transpose(0, 1) for t in lo], lam[:3], g)  # not contiguous
+    ws = torch.empty(s.grad_workspace_bytes(2), dtype=torch.uint8, device=DEV)
+    with pytest.raises(ValueError):
+        s.grad_forward(2, ws.view(torch.float32))                    # workspace not in bytes
+    with pytest.raises(ValueError):
+        s.grad_backward(2, ws, small)
+    with pytest.raises(ValueError):
+        s.divergence_max(ref_b=small[0])
+    s.adjoint_step(lam, lo, lam[:3], g)                             # the valid call
