@@ -42,8 +42,9 @@ class Batch:
                                      "of the batch dtype and device")
             grids[i] = B.make_grid(fields[0].shape, sp)
             dts[i] = float(dt)
-            for j, v in enumerate(c):
-                coeffs[12 * i + j] = float(v)
+            cv = B.dbl_array(c, 12)  # exactly 12 coefficients per box
+            for j in range(12):
+                coeffs[12 * i + j] = cv[j]
             self.fields.append(fields)
             self.scratch.append([torch.empty_like(t) for t in fields])
         h = ctypes.c_void_p()
