@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "xfdtd_internal.h"
 
 namespace xfdtd {
@@ -66,14 +68,16 @@ __global__ __launch_bounds__(256) void divergence_kernel(Fields<T> f, Dims d, Di
                                                          T *de_out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return;
-    double dsb, de;
-    div_at(f, d, cf, i, j, k, dsb, de);
-    const int64_t p = ((int64_t)k * d.ny + j) * d.nx + i;
-    if (dsb_out) dsb_out[p] = (T)dsb;
-    if (de_out) de_out[p] = (T)de;
+    if (i >= d.nx) return;
+    // y and z loop over the grid (its y and z dimensions are capped)
+    for (int k = blockIdx.z; k < d.nz; k += gridDim.z)
+        for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < d.ny; j += gridDim.y * blockDim.y) {
+            double dsb, de;
+            div_at(f, d, cf, i, j, k, dsb, de);
+            const int64_t p = ((int64_t)k * d.ny + j) * d.nx + i;
+            if (dsb_out) dsb_out[p] = (T)dsb;
+            if (de_out) de_out[p] = (T)de;
+        }
 }
 
 // Per-block partial results: max |D*.B - ref_b|, max |D.E - ref_e|, count of
@@ -131,12 +135,9 @@ struct DispCoef {
 //         + delta_a (1 + 2 cos(k_a d_a)),
 //   omega = (2/dt) asin(dt sqrt(F)) on the principal branch,
 //   d omega/d k_a = 2 dt (dF/dk_a) / sin(omega dt).
-__global__ __launch_bounds__(256) void dispersion_kernel(const double *kv, int64_t n, DispCoef cf,
-                                                         double *omega, double *vph, double *vg,
-                                                         unsigned int *bad)
+__device__ __forceinline__ void dispersion_at(const double *kv, int64_t q, const DispCoef &cf, double *omega,
+                                              double *vph, double *vg, unsigned int *bad)
 {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= n) return;
     double th[3], s2[3], cs[3], sn[3], A[3];
     double kk = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -181,6 +182,15 @@ __global__ __launch_bounds__(256) void dispersion_kernel(const double *kv, int64
             vg[3 * q + a] = 2.0 * cf.dt * dF / swd;
         }
     }
+}
+
+// grid-stride over the n wave vectors (the grid is capped in the launcher)
+__global__ __launch_bounds__(256) void dispersion_kernel(const double *kv, int64_t n, DispCoef cf,
+                                                         double *omega, double *vph, double *vg,
+                                                         unsigned int *bad)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        dispersion_at(kv, q, cf, omega, vph, vg, bad);
 }
 
 // Dispersion norm of Sec. 4 (eq. norm): f_w = prod_a d_a * integral over
@@ -316,7 +326,8 @@ hipError_t launch_divergence(const Fields<T> &f, Dims d, const double coeffs[12]
     DivCoef cf;
     for (int i = 0; i < 12; ++i) cf.c[i] = coeffs[i];
     for (int a = 0; a < 3; ++a) cf.inv[a] = 1.0 / sp[a];
-    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (unsigned)std::min((d.ny + 3) / 4, 65535),
+                            (unsigned)std::min(d.nz, 65535));
     hipLaunchKernelGGL(divergence_kernel<T>, grd, blk, 0, s, f, d, cf, div_star_b, div_e);
     return hipGetLastError();
 }
@@ -342,7 +353,7 @@ hipError_t launch_dispersion(const double *k, int64_t n, double dt, const double
     for (int i = 0; i < 12; ++i) cf.c[i] = coeffs[i];
     for (int a = 0; a < 3; ++a) cf.sp[a] = sp[a];
     cf.dt = dt;
-    const int64_t nb = (n + 255) / 256;
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 1 << 16);
     hipLaunchKernelGGL(dispersion_kernel, dim3((unsigned)nb), dim3(256), 0, s, k, n, cf, omega, vph,
                        vg, bad);
     return hipGetLastError();

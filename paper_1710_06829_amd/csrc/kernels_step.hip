@@ -27,6 +27,8 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "xfdtd_internal.h"
@@ -95,12 +97,9 @@ __device__ __forceinline__ void st_plane(gptr<T> plane, uint32_t off, T v)
 // unfused Faraday: B += S(D* E) in place
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void faraday_kernel(Fields<T> f, Dims d, Weights<T> w)
+__device__ __forceinline__ void faraday_cell(const Fields<T> &f, const Dims &d, const Weights<T> &w, int i, int j,
+                                             int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return;
     // wrapped coordinates for offsets -1..+2
     int xs[4], ys[4], zs[4];
     for (int o = 0; o < 4; ++o) {
@@ -138,19 +137,28 @@ __global__ __launch_bounds__(256) void faraday_kernel(Fields<T> f, Dims d, Weigh
     f.c[5][p] = f.c[5][p] + bz;
 }
 
+// x from the grid's x dimension; y and z loop over the grid (whose y and z
+// dimensions are capped at 65535 blocks)
+template <typename T>
+__global__ __launch_bounds__(256) void faraday_kernel(Fields<T> f, Dims d, Weights<T> w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nx) return;
+    for (int k = blockIdx.z; k < d.nz; k += gridDim.z)
+        for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < d.ny; j += gridDim.y * blockDim.y)
+            faraday_cell(f, d, w, i, j, k);
+}
+
 // ---------------------------------------------------------------------------
 // unfused Ampere: E += dt (D x B) in place
 // ---------------------------------------------------------------------------
-template <typename T>
 // With a current source (jx non-null; App. A eq. update4-6 in c = mu_0 = 1
 // units): E += dt (D x B) - dt J, wj = dt rounded to T.
-__global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weights<T> w, const T *__restrict__ jx,
-                                                     const T *__restrict__ jy, const T *__restrict__ jz, T wj)
+template <typename T>
+__device__ __forceinline__ void ampere_cell(const Fields<T> &f, const Dims &d, const Weights<T> &w,
+                                            const T *__restrict__ jx, const T *__restrict__ jy,
+                                            const T *__restrict__ jz, T wj, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= d.nx || j >= d.ny) return;
     const int64_t nxy = (int64_t)d.nx * d.ny;
     const int64_t p = (int64_t)k * nxy + (int64_t)j * d.nx + i;
     const int64_t pxm = (int64_t)k * nxy + (int64_t)j * d.nx + wrap(i - 1, d.nx);
@@ -167,6 +175,17 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
     f.c[0][p] = ampere_eval(f.c[0][p], w.wa[1], bz, Bz[pym], w.wa[2], by, By[pzm]);
     f.c[1][p] = ampere_eval(f.c[1][p], w.wa[2], bx, Bx[pzm], w.wa[0], bz, Bz[pxm]);
     f.c[2][p] = ampere_eval(f.c[2][p], w.wa[0], by, By[pxm], w.wa[1], bx, Bx[pym]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weights<T> w, const T *__restrict__ jx,
+                                                     const T *__restrict__ jy, const T *__restrict__ jz, T wj)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nx) return;
+    for (int k = blockIdx.z; k < d.nz; k += gridDim.z)
+        for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < d.ny; j += gridDim.y * blockDim.y)
+            ampere_cell(f, d, w, jx, jy, jz, wj, i, j, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,10 +535,17 @@ hipError_t with_tile(int tile_x, int tile_y, F &&f)
 
 }  // namespace
 
+// grid of the unfused kernels: x covers nx; y and z are capped at 65535
+// blocks (the kernels loop over the rest)
+static dim3 unfused_grid(const Dims &d)
+{
+    return dim3((d.nx + 63) / 64, (unsigned)std::min((d.ny + 3) / 4, 65535), (unsigned)std::min(d.nz, 65535));
+}
+
 template <typename T>
 hipError_t launch_faraday(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s)
 {
-    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    dim3 blk(64, 4, 1), grd = unfused_grid(d);
     hipLaunchKernelGGL(faraday_kernel<T>, grd, blk, 0, s, f, d, w);
     return hipGetLastError();
 }
@@ -528,7 +554,7 @@ template <typename T>
 hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStream_t s, const T *const *j,
                          T wj)
 {
-    dim3 blk(64, 4, 1), grd((d.nx + 63) / 64, (d.ny + 3) / 4, d.nz);
+    dim3 blk(64, 4, 1), grd = unfused_grid(d);
     hipLaunchKernelGGL(ampere_kernel<T>, grd, blk, 0, s, f, d, w, j ? j[0] : nullptr, j ? j[1] : nullptr,
                        j ? j[2] : nullptr, wj);
     return hipGetLastError();

@@ -170,6 +170,28 @@ def test_divergence_fields_match_oracle():
     assert np.abs(de - O.div_E(f0[:3], sp)).max() < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(70000, 1, 2), (1, 270000, 1)])
+def test_long_boxes_beyond_65535_grid_blocks_fp64(shape):
+    """Boxes whose z extent, or y extent in 4-row blocks, exceeds 65535: the
+    unfused updates (step_faraday / step_ampere, the odd first step of run)
+    and the divergence loop over their capped grids; the fused step has a
+    one-dimensional grid."""
+    c = _coeffs(481)
+    dt = 0.9 * O.cfl_dt(c)
+    f0 = S.uniform_fields(shape, 482)
+    t = to_dev(f0)
+    s = pkg.Solver(t, dt, c)
+    s.step_faraday()
+    s.step_ampere()
+    s.run(3)  # one unfused step, then a fused pair
+    assert rel_l2(to_host(t), oracle.c_run(f0, 4, c, dt)) < 1e-13
+    f1 = to_host(t)
+    db, de = to_host(list(s.divergence()))
+    sp = (1.0, 1.0, 1.0)
+    assert np.abs(db - O.div_star_B(f1[3:], c, sp)).max() < 1e-12
+    assert np.abs(de - O.div_E(f1[:3], sp)).max() < 1e-12
+
+
 def test_divergence_max_reports_nonfinite():
     f0 = S.uniform_fields((4, 5, 6), 471)
     f0[2][1, 2, 3] = np.nan
