@@ -10,10 +10,12 @@
 // xfdtd_internal.h): per B component two stars, each of 7 g values, instead
 // of 2 x 12 raw taps.  The regrouping is exact in real arithmetic.
 //
-//   faraday_kernel / ampere_kernel : one thread per cell, in place, periodic
-//       indexing; neighbours come through the L1/L2 caches.
-//   fused_step_kernel : out of place.  A workgroup owns a 64 x TY tile of
-//       (x, y) columns and marches a chunk of z-planes.  Per plane it stages
+//   faraday_kernel / ampere_kernel : one thread per cell (x from the grid,
+//       y and z looping over a grid capped at 65535 blocks), in place,
+//       periodic indexing; neighbours come through the L1/L2 caches.
+//   fused_step_kernel : out of place.  A workgroup owns a TX x TY tile of
+//       (x, y) columns (TX = 64 or 32) and marches a chunk of z-planes.  Per
+//       plane it stages
 //       the next E plane (with a 2-cell halo) in LDS, forms the six g fields
 //       on the tile plus a 2/1-cell halo, evaluates B^{n+1/2} on the tile plus
 //       a 1-cell halo on the low x and y sides (redundantly with the
@@ -79,8 +81,10 @@ __device__ __forceinline__ void nt_store(gptr<T> p, T v)
 
 // Element `off` of a z-plane whose base pointer is uniform across the
 // workgroup: the byte offset is formed in 32 bits (planes are limited to
-// 2^32 bytes on the host), so the access takes a scalar base and a 32-bit
-// per-lane offset and needs no 64-bit address arithmetic per lane.
+// 2^28 cells on the host, < 2^31 bytes in FP64), so a load takes a scalar
+// base and a 32-bit per-lane offset and needs no 64-bit address arithmetic
+// per lane.  (The compiler emits the non-temporal store below with a 64-bit
+// vector address: one 64-bit add per store.)
 template <typename T>
 __device__ __forceinline__ T ld_plane(gptr<const T> plane, uint32_t off)
 {
