@@ -307,11 +307,13 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
 
 /*
  * Checkpointed gradient of n steps.  The forward pass stores the state every
- * `seg` steps (seg <= 0 selects ceil(sqrt(2 n)), the length that minimises
- * the workspace) and the E fields of the last
+ * `seg` steps (seg <= 0 selects ceil(sqrt(2 n))) and the E fields of the last
  * segment; the backward pass recomputes every other segment from its
  * checkpoint, keeping the E of each of its steps, and runs the adjoint steps
- * in reverse.  Memory: ceil(n/seg) + 2 states plus (seg - 1) E fields.
+ * in reverse.  It recomputes segment m - 1 on a second (internal) stream
+ * while it reverses segment m, so it holds two sets of E snapshots.
+ * Memory: ceil(n/seg) + 2 states plus 2 (seg - 1) E fields (seg - 1 when
+ * seg >= n: one segment, nothing to recompute).
  *
  * xfdtd_grad_workspace: bytes of device workspace for (n, seg).
  * xfdtd_grad_forward:   n steps from the bound fields; the final state is in

@@ -306,6 +306,8 @@ struct xfdtd_s {
     double *apartials;  // device, adjoint per-workgroup gradient sums
     int napartials;
     double *grad_acc;   // device, 12 doubles
+    hipStream_t aux;    // gradient backward: recompute stream (created on first use)
+    int aux_device;
 };
 
 namespace {
@@ -568,6 +570,8 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->apartials = nullptr;
     h->napartials = 0;
     h->grad_acc = nullptr;
+    h->aux = nullptr;
+    h->aux_device = -1;
     *out = h;
     return XFDTD_OK;
 }
@@ -576,6 +580,10 @@ void xfdtd_destroy(xfdtd_t h)
 {
     if (!h) return;
     if (h->partials || h->apartials || h->grad_acc) hipStreamSynchronize(h->stream);
+    if (h->aux) {
+        hipStreamSynchronize(h->aux);
+        hipStreamDestroy(h->aux);
+    }
     if (h->partials) hipFree(h->partials);
     if (h->apartials) hipFree(h->apartials);
     if (h->grad_acc) hipFree(h->grad_acc);
@@ -855,9 +863,10 @@ size_t field_bytes(const xfdtd_s *h)
     return (b + 255) / 256 * 256;
 }
 
-// Default segment length: the workspace holds 6 ceil(n/seg) + 12 + 3 (seg - 1)
-// field arrays, smallest at seg = sqrt(2 n); the backward pass recomputes
-// n - seg steps.
+// Default segment length ceil(sqrt(2 n)): the workspace holds
+// 6 ceil(n/seg) + 12 + 6 (seg - 1) field arrays (ws_arrays), within about 6 % of its
+// minimum (at sqrt(n)), and the backward pass recomputes n - seg steps,
+// fewer than at sqrt(n).
 int64_t default_seg(int64_t n, int64_t seg)
 {
     if (seg > 0) return seg;
@@ -869,11 +878,20 @@ int64_t default_seg(int64_t n, int64_t seg)
 //   [0, 6*nck)            checkpoints, state m at step m*seg
 //   [6*nck, 6*nck+6)      state A (forward ping-pong; backward: B ping-pong)
 //   [6*nck+6, 6*nck+12)   state B (forward ping-pong; backward: lambda scratch)
-//   [6*nck+12, ...)       (seg-1) E snapshots (3 arrays each)
+//   [6*nck+12, ...)       two sets of (seg-1) E snapshots (3 arrays each):
+//                         segment m uses set m & 1, so that the backward pass
+//                         recomputes segment m-1 while it reverses segment m
+//                         (one set when a single segment covers all n steps)
 uint64_t ws_arrays(int64_t n, int64_t seg)
 {
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
-    return (uint64_t)(6 * nck + 12 + 3 * (seg - 1));
+    return (uint64_t)(6 * nck + 12 + (nck > 1 ? 6 : 3) * (seg - 1));
+}
+
+// first array of E snapshot i (step s0 + i, i in [1, seg)) of a segment in set `set`
+int64_t snap_index(int64_t nck, int64_t seg, int set, int64_t i)
+{
+    return 6 * nck + 12 + (int64_t)set * 3 * (seg - 1) + 3 * (i - 1);
 }
 
 template <typename T>
@@ -908,8 +926,9 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
         } else if ((s + 1) % seg == 0) {
             dst = state_at<T>(ws, fb, 6 * ((s + 1) / seg));
         } else if (s >= s0_last) {
+            const int64_t e = snap_index(nck, seg, (int)((nck - 1) & 1), s + 1 - s0_last);
             for (int c = 0; c < 3; ++c) {
-                dst.c[c] = (T *)(ws + (size_t)(6 * nck + 12 + 3 * (s - s0_last) + c) * fb);
+                dst.c[c] = (T *)(ws + (size_t)(e + c) * fb);
                 dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
             }
         } else {
@@ -921,48 +940,121 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
     return XFDTD_OK;
 }
 
+// The recompute stream of the backward pass, on the handle's device.
+int ensure_aux_stream(xfdtd_t h)
+{
+    if (h->aux && h->aux_device == h->device) return XFDTD_OK;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != h->device) HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    hipError_t e = hipSuccess;
+    if (h->aux) {
+        e = hipStreamSynchronize(h->aux);
+        if (e == hipSuccess) e = hipStreamDestroy(h->aux);
+        h->aux = nullptr;
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+    if (cur != h->device) hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "creating the recompute stream");
+    h->aux_device = h->device;
+    return XFDTD_OK;
+}
+
+// Events of one backward pass (destroyed with it).
+struct EventSet {
+    std::vector<hipEvent_t> ev;
+    ~EventSet()
+    {
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+    }
+    hipError_t make(size_t n)
+    {
+        for (size_t i = 0; i < n; ++i) {
+            hipEvent_t e;
+            const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        return hipSuccess;
+    }
+};
+
+// Backward pass.  The adjoint steps run on the handle's stream, segment by
+// segment from the last; segment m - 1 is recomputed from its checkpoint on
+// the second stream meanwhile, into the other set of E snapshots (the forward
+// pass wrote the last segment's).  Events order the two: a recompute waits
+// until the adjoint has left the set it overwrites, an adjoint segment until
+// its recompute is done.
 template <typename T>
 int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam[6], double grad[12])
 {
     int rc = ensure_adjoint_buffers(h);
+    if (rc) return rc;
+    rc = ensure_aux_stream(h);
     if (rc) return rc;
     const size_t fb = field_bytes(h);
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
     const size_t raw = (size_t)h->g.nx * h->g.ny * h->g.nz * (h->dtype == XFDTD_F32 ? 4 : 8);
-    HIP_TRY(hipMemsetAsync(h->grad_acc, 0, sizeof(double) * 12, h->stream), "hipMemsetAsync");
+    hipStream_t mainS = h->stream, aux = h->aux;
+    HIP_TRY(hipMemsetAsync(h->grad_acc, 0, sizeof(double) * 12, mainS), "hipMemsetAsync");
     Fields<T> segB = state_at<T>(ws, fb, 6 * nck);   // two B buffers: comps 0..2 and 3..5
     Fields<T> lamS = state_at<T>(ws, fb, 6 * nck + 6);
     Fields<T> lamU = as_fields<T>(lam);
-    auto segE = [&](int64_t i) {  // E snapshot of step s0 + i, i in [1, seg)
+    auto segE = [&](int64_t m, int64_t i) {  // E snapshot of step m*seg + i of segment m, i in [1, seg)
         Fields<T> f;
-        for (int c = 0; c < 3; ++c) f.c[c] = (T *)(ws + (size_t)(6 * nck + 12 + 3 * (i - 1) + c) * fb);
+        const int64_t e = snap_index(nck, seg, (int)(m & 1), i);
+        for (int c = 0; c < 3; ++c) f.c[c] = (T *)(ws + (size_t)(e + c) * fb);
         return f;
     };
+    // events: [0] start, [1 + m] recompute of segment m done, [1 + nck + m]
+    // adjoint of segment m done
+    EventSet evs;
+    // on every return, the recompute stream has finished before the events go
+    struct AuxDrain {
+        hipStream_t s;
+        ~AuxDrain() { hipStreamSynchronize(s); }
+    } drain{aux};
+    HIP_TRY(evs.make((size_t)(1 + 2 * nck)), "hipEventCreate");
+    auto ev_rec = [&](int64_t m) { return evs.ev[(size_t)(1 + m)]; };
+    auto ev_adj = [&](int64_t m) { return evs.ev[(size_t)(1 + nck + m)]; };
+    HIP_TRY(hipEventRecord(evs.ev[0], mainS), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(aux, evs.ev[0], 0), "hipStreamWaitEvent");  // checkpoints are written
+
+    // recompute segment m on the second stream, keeping E of every step
+    auto recompute = [&](int64_t m) -> int {
+        const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        Fields<T> in = state_at<T>(ws, fb, 6 * m);
+        for (int64_t s = s0; s + 1 < s1; ++s) {
+            Fields<T> out;
+            Fields<T> e = segE(m, s + 1 - s0);
+            for (int c = 0; c < 3; ++c) out.c[c] = e.c[c];
+            for (int c = 0; c < 3; ++c) out.c[3 + c] = segB.c[3 * ((s - s0) & 1) + c];
+            HIP_TRY(launch_fused<T>(in, out, d, w, h->tile_x, h->tile_y, h->zchunk, aux), "fused launch");
+            in = out;
+        }
+        HIP_TRY(hipEventRecord(ev_rec(m), aux), "hipEventRecord");
+        return XFDTD_OK;
+    };
+
     Fields<T> lcur = lamU, lnext = lamS;
     bool first = true;
+    if (n > 0 && nck >= 2) {
+        rc = recompute(nck - 2);
+        if (rc) return rc;
+    }
     for (int64_t m = nck - 1; m >= 0 && n > 0; --m) {
         const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
         Fields<T> ck = state_at<T>(ws, fb, 6 * m);
-        // recompute the segment, keeping E of every step (the forward pass
-        // already stored those of the last segment)
-        Fields<T> in = ck;
-        for (int64_t s = s0; s + 1 < s1 && m != nck - 1; ++s) {
-            Fields<T> out;
-            Fields<T> e = segE(s + 1 - s0);
-            for (int c = 0; c < 3; ++c) out.c[c] = e.c[c];
-            for (int c = 0; c < 3; ++c) out.c[3 + c] = segB.c[3 * ((s - s0) & 1) + c];
-            HIP_TRY(launch_fused<T>(in, out, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
-            in = out;
-        }
+        if (m != nck - 1) HIP_TRY(hipStreamWaitEvent(mainS, ev_rec(m), 0), "hipStreamWaitEvent");
         // reverse through the segment
         for (int64_t s = s1 - 1; s >= s0; --s) {
             const T *en[3];
             if (s == s0) {
                 for (int c = 0; c < 3; ++c) en[c] = ck.c[c];
             } else {
-                Fields<T> e = segE(s - s0);
+                Fields<T> e = segE(m, s - s0);
                 for (int c = 0; c < 3; ++c) en[c] = e.c[c];
             }
             // the workgroup sums accumulate over all steps; one reduction at the end
@@ -973,16 +1065,23 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
             lcur = lnext;
             lnext = t;
         }
+        HIP_TRY(hipEventRecord(ev_adj(m), mainS), "hipEventRecord");
+        if (m >= 2) {  // segment m - 2 reuses this segment's E set
+            HIP_TRY(hipStreamWaitEvent(aux, ev_adj(m), 0), "hipStreamWaitEvent");
+            rc = recompute(m - 2);
+            if (rc) return rc;
+        }
     }
     if (!first)
         HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, h->atile_x, adjoint_tile_y(h), h->azchunk),
-                                       grad_scale(h), h->grad_acc, h->stream),
+                                       grad_scale(h), h->grad_acc, mainS),
                 "reduce launch");
     if (lcur.c[0] != lamU.c[0])
         for (int c = 0; c < 6; ++c)
-            HIP_TRY(hipMemcpyAsync(lamU.c[c], lcur.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
-    HIP_TRY(hipMemcpyAsync(grad, h->grad_acc, sizeof(double) * 12, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
-    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+            HIP_TRY(hipMemcpyAsync(lamU.c[c], lcur.c[c], raw, hipMemcpyDeviceToDevice, mainS), "hipMemcpyAsync");
+    HIP_TRY(hipMemcpyAsync(grad, h->grad_acc, sizeof(double) * 12, hipMemcpyDeviceToHost, mainS), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(mainS), "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(aux), "hipStreamSynchronize");
     return XFDTD_OK;
 }
 
