@@ -381,7 +381,10 @@ int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
 /*
  * Batched checkpointed gradients: the single-box schedule of
  * xfdtd_grad_forward / xfdtd_grad_backward for every box of the batch at once
- * (same n and seg for all boxes), one batched launch per step.
+ * (same n and seg for all boxes), one batched launch per step.  As there,
+ * the backward pass recomputes segment m - 1 of every box on a second
+ * (internal) stream while it reverses segment m, and each workspace holds two
+ * sets of E snapshots (one when seg >= n).
  *   bytes[m] / ws[m] / ws_bytes[m] : one workspace per box (device,
  *       256-byte aligned, caller-owned), sized by xfdtd_batch_grad_workspace.
  *   lam[m*6] : device, dL/d(final state) of each box in, dL/d(initial state)

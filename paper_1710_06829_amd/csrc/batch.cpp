@@ -51,6 +51,7 @@ struct xfdtd_batch_s {
     bool bound = false;
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;
+    hipStream_t aux = nullptr;  // recompute stream of the gradient's backward pass
     Config cfg;
     bool cfg_set = false;
     void *d_boxes = nullptr;
@@ -291,6 +292,7 @@ void xfdtd_batch_destroy(xfdtd_batch_t b)
                     (void *)b->d_grad})
         if (p) hipFree(p);
     if (b->capture) hipStreamDestroy(b->capture);
+    if (b->aux) hipStreamDestroy(b->aux);
     delete b;
 }
 
@@ -316,6 +318,7 @@ int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch,
     b->stream = (hipStream_t)stream;
     b->bound = true;
     if (!b->capture) BTRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+    if (!b->aux) BTRY(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking), "hipStreamCreate");
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(b->key);
@@ -519,10 +522,13 @@ int64_t bseg(int64_t n, int64_t seg)
     return s < 1 ? 1 : s;
 }
 
+// Per box: nck checkpoints, two scratch states, and E snapshots of one
+// segment, in two sets when there are several segments (the backward pass
+// recomputes one segment while it reverses through the next).
 uint64_t bws_arrays(int64_t n, int64_t seg)
 {
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
-    return (uint64_t)(6 * nck + 12 + 3 * (seg - 1));
+    return (uint64_t)(6 * nck + 12 + (nck > 1 ? 6 : 3) * (seg - 1));
 }
 
 template <typename T>
@@ -539,7 +545,11 @@ struct BoxWs {  // the workspace of one box, addressed like host.cpp's layout
     Fields<T> ck(int64_t m) const { return state(6 * m); }
     Fields<T> A() const { return state(6 * nck); }
     Fields<T> B() const { return state(6 * nck + 6); }
-    T *segE(int64_t i, int c) const { return (T *)(ws + (size_t)(6 * nck + 12 + 3 * (i - 1) + c) * fb); }
+    // E snapshot i (step s0 + i, i in [1, seg)) of a segment, in snapshot set `set`
+    T *segE(int set, int64_t seg, int64_t i, int c) const
+    {
+        return (T *)(ws + (size_t)(6 * nck + 12 + (int64_t)set * 3 * (seg - 1) + 3 * (i - 1) + c) * fb);
+    }
 };
 
 template <typename T>
@@ -664,7 +674,7 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
                 dst = W[i].ck((s + 1) / seg);
             } else if (s >= s0_last) {
                 for (int c = 0; c < 3; ++c) {
-                    dst.c[c] = W[i].segE(s + 1 - s0_last, c);
+                    dst.c[c] = W[i].segE((int)((nck - 1) & 1), seg, s + 1 - s0_last, c);
                     dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
                 }
             } else {
@@ -687,6 +697,12 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
     return rc;
 }
 
+// Batched backward pass, overlapped like the single-box one: the adjoint
+// launches run on the bound stream, segment by segment from the last, while
+// segment m - 1 is recomputed from its checkpoints on the batch's second
+// stream into the other set of E snapshots.  A recompute waits until the
+// adjoint has left the set it overwrites, an adjoint segment until its
+// recompute is done.
 template <typename T>
 int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, void *const *lam, double *grad)
 {
@@ -703,89 +719,128 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
         lcur[i] = lamU[i];
         lnext[i] = lamS[i];
     }
-    // descriptors of every launch, in launch order
+    // descriptors of every launch; segment k's recompute launches start at
+    // rdesc[m * roff[k]], its adjoint launches at adesc[m * aoff[k]]
     std::vector<BoxDesc<T>> rdesc;
     std::vector<AdjDesc<T>> adesc;
-    struct Launch {
-        int kind;  // 0 recompute, 1 adjoint
-        int64_t off;
-    };
-    std::vector<Launch> order;
-    for (int64_t mseg = nck - 1; mseg >= 0 && n > 0; --mseg) {
-        const int64_t s0 = mseg * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
-        if (mseg != nck - 1) {
-            std::vector<Fields<T>> in(m);
-            for (int64_t i = 0; i < m; ++i) in[i] = W[i].ck(mseg);
-            for (int64_t s = s0; s + 1 < s1; ++s) {
-                order.push_back({0, (int64_t)rdesc.size()});
-                for (int64_t i = 0; i < m; ++i) {
-                    Fields<T> out;
-                    const Fields<T> A = W[i].A();
-                    for (int c = 0; c < 3; ++c) {
-                        out.c[c] = W[i].segE(s + 1 - s0, c);
-                        out.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
-                    }
-                    rdesc.push_back(fwd_desc<T>(b, i, in[i], out));
-                    in[i] = out;
+    std::vector<int64_t> roff(nck + 1, 0), aoff(nck + 1, 0);
+    for (int64_t k = 0; k < nck && n > 0; ++k) {
+        const int64_t s0 = k * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        roff[k] = (int64_t)rdesc.size() / m;
+        if (k == nck - 1) continue;  // the forward pass left this segment's snapshots
+        std::vector<Fields<T>> in(m);
+        for (int64_t i = 0; i < m; ++i) in[i] = W[i].ck(k);
+        for (int64_t s = s0; s + 1 < s1; ++s)
+            for (int64_t i = 0; i < m; ++i) {
+                Fields<T> out;
+                const Fields<T> A = W[i].A();
+                for (int c = 0; c < 3; ++c) {
+                    out.c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
+                    out.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
                 }
+                rdesc.push_back(fwd_desc<T>(b, i, in[i], out));
+                in[i] = out;
             }
-        }
-        for (int64_t s = s1 - 1; s >= s0; --s) {
-            order.push_back({1, (int64_t)adesc.size()});
+    }
+    roff[nck] = (int64_t)rdesc.size() / m;
+    for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
+        const int64_t s0 = k * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        aoff[k] = (int64_t)adesc.size() / m;
+        for (int64_t s = s1 - 1; s >= s0; --s)
             for (int64_t i = 0; i < m; ++i) {
                 T *en[3];
-                for (int c = 0; c < 3; ++c) en[c] = (s == s0) ? W[i].ck(mseg).c[c] : W[i].segE(s - s0, c);
+                for (int c = 0; c < 3; ++c)
+                    en[c] = (s == s0) ? W[i].ck(k).c[c] : W[i].segE((int)(k & 1), seg, s - s0, c);
                 adesc.push_back(adj_desc<T>(b, i, lcur[i], lnext[i], en));
                 std::swap(lcur[i], lnext[i]);
             }
-        }
     }
     BoxDesc<T> *d_r = nullptr;
     AdjDesc<T> *d_a = nullptr;
+    struct Free {
+        void *p[2];
+        ~Free()
+        {
+            for (void *q : p)
+                if (q) hipFree(q);
+        }
+    };
     BTRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     rc = upload(rdesc, &d_r);
-    if (!rc) rc = upload(adesc, &d_a);
-    if (!rc) {
-        hipError_t e = hipMemsetAsync(b->d_grad, 0, sizeof(double) * 12 * m, b->stream);
-        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    Free fr{{d_r, nullptr}};
+    if (rc) return rc;
+    rc = upload(adesc, &d_a);
+    fr.p[1] = d_a;
+    if (rc) return rc;
+    hipStream_t mainS = b->stream, aux = b->aux;
+    BTRY(hipMemsetAsync(b->d_grad, 0, sizeof(double) * 12 * m, mainS), "hipMemsetAsync");
+    // events: [0] start, [1 + k] recompute of segment k done, [1 + nck + k]
+    // adjoint of segment k done
+    struct Events {
+        std::vector<hipEvent_t> ev;
+        hipStream_t s[2];
+        ~Events()
+        {
+            // on every return both streams have drained before the events
+            // and descriptors go
+            for (hipStream_t q : s) hipStreamSynchronize(q);
+            for (hipEvent_t e : ev) hipEventDestroy(e);
+        }
+    } evs{{}, {mainS, aux}};
+    for (int64_t k = 0; k < 1 + 2 * nck; ++k) {
+        hipEvent_t e;
+        BTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        evs.ev.push_back(e);
     }
+    BTRY(hipEventRecord(evs.ev[0], mainS), "hipEventRecord");
+    BTRY(hipStreamWaitEvent(aux, evs.ev[0], 0), "hipStreamWaitEvent");
+    auto recompute = [&](int64_t k) -> int {
+        for (int64_t l = roff[k]; l < roff[k + 1]; ++l) {
+            hipError_t e = launch_batched<T>(d_r + l * m, b->d_items, b->nitems, 0, b->cfg.tile_x, b->cfg.tile_y,
+                                             grid_of(b), aux);
+            if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
+        }
+        BTRY(hipEventRecord(evs.ev[(size_t)(1 + k)], aux), "hipEventRecord");
+        return XFDTD_OK;
+    };
     // adjoint grid: the tuned persistent size if one is set, else one
     // workgroup per item
     const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems) ? b->cfg.grid : b->naitems;
     bool first = true;
-    for (size_t k = 0; k < order.size() && !rc; ++k) {
-        hipError_t e;
-        if (order[k].kind == 0) {
-            e = launch_batched<T>(d_r + order[k].off, b->d_items, b->nitems, 0, b->cfg.tile_x, b->cfg.tile_y,
-                                  grid_of(b), b->stream);
-        } else {
-            e = launch_batched_adjoint<T>(d_a + order[k].off, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
-                                          b->cfg.tile_x, adj_tile(b), ga, b->stream);
+    if (n > 0 && nck >= 2) {
+        rc = recompute(nck - 2);
+        if (rc) return rc;
+    }
+    for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
+        if (k != nck - 1) BTRY(hipStreamWaitEvent(mainS, evs.ev[(size_t)(1 + k)], 0), "hipStreamWaitEvent");
+        const int64_t nl = (k > 0 ? aoff[k - 1] : (int64_t)adesc.size() / m) - aoff[k];
+        for (int64_t l = aoff[k]; l < aoff[k] + nl; ++l) {
+            hipError_t e = launch_batched_adjoint<T>(d_a + l * m, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
+                                                     b->cfg.tile_x, adj_tile(b), ga, mainS);
+            if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
             first = false;
         }
-        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
+        BTRY(hipEventRecord(evs.ev[(size_t)(1 + nck + k)], mainS), "hipEventRecord");
+        if (k >= 2) {  // segment k - 2 reuses this segment's E set
+            BTRY(hipStreamWaitEvent(aux, evs.ev[(size_t)(1 + nck + k)], 0), "hipStreamWaitEvent");
+            rc = recompute(k - 2);
+            if (rc) return rc;
+        }
     }
-    if (!rc && !first) {
-        hipError_t e = launch_reduce_boxes(b->d_apart, b->d_afirst, (int)m, b->d_scale, b->d_grad, b->stream);
-        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "reduce launch: %s", hipGetErrorString(e));
+    if (!first) {
+        hipError_t e = launch_reduce_boxes(b->d_apart, b->d_afirst, (int)m, b->d_scale, b->d_grad, mainS);
+        if (e != hipSuccess) return set_error(XFDTD_EHIP, "reduce launch: %s", hipGetErrorString(e));
     }
-    for (int64_t i = 0; i < m && !rc; ++i)
+    for (int64_t i = 0; i < m; ++i)
         if (lcur[i].c[0] != lamU[i].c[0]) {
             const size_t raw = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * sizeof(T);
-            for (int c = 0; c < 6 && !rc; ++c) {
-                hipError_t e = hipMemcpyAsync(lamU[i].c[c], lcur[i].c[c], raw, hipMemcpyDeviceToDevice, b->stream);
-                if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-            }
+            for (int c = 0; c < 6; ++c)
+                BTRY(hipMemcpyAsync(lamU[i].c[c], lcur[i].c[c], raw, hipMemcpyDeviceToDevice, mainS), "hipMemcpyAsync");
         }
-    if (!rc) {
-        hipError_t e = hipMemcpyAsync(grad, b->d_grad, sizeof(double) * 12 * m, hipMemcpyDeviceToHost, b->stream);
-        if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-    }
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (!rc && e != hipSuccess) rc = set_error(XFDTD_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-    if (d_r) hipFree(d_r);
-    if (d_a) hipFree(d_a);
-    return rc;
+    BTRY(hipMemcpyAsync(grad, b->d_grad, sizeof(double) * 12 * m, hipMemcpyDeviceToHost, mainS), "hipMemcpyAsync");
+    BTRY(hipStreamSynchronize(mainS), "hipStreamSynchronize");
+    BTRY(hipStreamSynchronize(aux), "hipStreamSynchronize");
+    return XFDTD_OK;
 }
 
 // Workspaces: present, aligned, large enough and disjoint from each other.
