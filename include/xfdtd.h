@@ -323,9 +323,14 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
  * xfdtd_grad_backward:  lam[6] (device, handle dtype) holds dL/d(final state)
  *                       on entry and dL/d(initial state) on return; grad
  *                       (host, 12 doubles) receives dL/dcoeffs.  ws must be
- *                       the workspace filled by xfdtd_grad_forward with the
- *                       same n and seg; the six lam arrays are disjoint from
- *                       each other and from ws.  Synchronises the stream.
+ *                       the workspace filled by xfdtd_grad_forward on this
+ *                       handle with the same n and seg; the six lam arrays are
+ *                       disjoint from each other and from ws.  It overwrites
+ *                       the E snapshots in ws, so it consumes that forward
+ *                       pass: another backward needs another forward.  The
+ *                       handle remembers which workspaces hold an unconsumed
+ *                       forward pass (its last 64) and rejects any other ws,
+ *                       n or seg with XFDTD_EINVAL.  Synchronises the stream.
  * Argument errors are XFDTD_EINVAL, found on the host before any device work.
  */
 int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes);
@@ -391,7 +396,10 @@ int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
  *       out (box-major, Ex..Bz).
  *   grad : host, m*12 doubles, dL/dcoeffs of each box.
  * The forward leaves the final states in the bound fields.  Both synchronise
- * the stream and allocate small internal buffers (launch descriptors).
+ * the stream and allocate small internal buffers (launch descriptors).  The
+ * backward consumes the forward pass like xfdtd_grad_backward: it needs the
+ * same ws list, n and seg as an unconsumed forward on this batch, else
+ * XFDTD_EINVAL.
  * Workspaces must be disjoint from each other and (forward) from the bound
  * fields and scratch arrays; (backward) the lambda arrays from each other and
  * from the workspaces.  Violations are XFDTD_EINVAL before any device work.

@@ -31,6 +31,9 @@ class _Propagate(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, *grads):
+        if ctx.ws is None:
+            raise RuntimeError("propagate: the backward pass consumes the forward pass's checkpoints; "
+                               "run propagate again for a second backward pass")
         solver = ctx.solver
         ref = solver.fields[0]
         lam = [torch.zeros_like(ref) if g is None else g.detach().to(ref.dtype).contiguous().clone()

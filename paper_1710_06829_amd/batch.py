@@ -106,7 +106,8 @@ class Batch:
 
     def grad_backward(self, n, ws, lams, seg=0):
         """lams: per box six tensors dL/d(final state) in, dL/d(initial state)
-        out.  Returns the per-box coefficient gradients (m lists of 12)."""
+        out.  Returns the per-box coefficient gradients (m lists of 12).
+        Consumes the forward pass stored in ``ws`` (same list, n and seg)."""
         p, sz = self._ws_args(ws)
         lams = [list(l) for l in lams]
         if len(lams) != self.m or any(len(l) != 6 for l in lams):

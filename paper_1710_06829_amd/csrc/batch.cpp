@@ -67,6 +67,14 @@ struct xfdtd_batch_s {
     double *d_apart = nullptr;
     int *d_afirst = nullptr;
     double *d_scale = nullptr, *d_grad = nullptr;
+    // Workspace lists filled by a forward pass and not yet consumed by a
+    // backward pass (which overwrites their E snapshots).
+    struct Tape {
+        std::vector<uintptr_t> ws;  // per box: start
+        uint64_t arrays;            // field arrays per box
+        int64_t n, seg;
+    };
+    std::vector<Tape> tapes;
 };
 
 namespace {
@@ -879,6 +887,35 @@ int check_bws(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const ui
     return XFDTD_OK;
 }
 
+// At most this many workspace lists per batch are remembered as holding a
+// forward pass; the oldest is forgotten first.
+constexpr size_t kMaxTapes = 64;
+
+// Forget every remembered workspace list that overlaps one of ws[0..m).
+void drop_tapes(xfdtd_batch_t b, void *const *ws, int64_t n, int64_t seg)
+{
+    std::vector<xfdtd_batch_s::Tape> &t = b->tapes;
+    if (t.empty()) return;
+    // the new workspaces are disjoint (checked), so sorted by start their ends
+    // are sorted too: a span [e0, e1) meets one of them iff the first whose
+    // end lies beyond e0 starts before e1
+    std::vector<std::pair<uintptr_t, uintptr_t>> span;  // (end, start)
+    for (int64_t i = 0; i < b->m; ++i) {
+        const uintptr_t a0 = (uintptr_t)ws[i];
+        span.push_back({a0 + bws_arrays(n, seg) * box_field_bytes(b, i), a0});
+    }
+    std::sort(span.begin(), span.end());
+    auto hit = [&](const xfdtd_batch_s::Tape &e) {
+        for (int64_t j = 0; j < b->m; ++j) {
+            const uintptr_t e0 = e.ws[j], e1 = e0 + e.arrays * box_field_bytes(b, j);
+            auto it = std::upper_bound(span.begin(), span.end(), std::make_pair(e0, UINTPTR_MAX));
+            if (it != span.end() && it->second < e1) return true;
+        }
+        return false;
+    };
+    t.erase(std::remove_if(t.begin(), t.end(), hit), t.end());
+}
+
 }  // namespace
 
 extern "C" {
@@ -897,7 +934,14 @@ int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *cons
     seg = bseg(n, seg);
     int rc = check_bws(b, n, seg, ws, ws_bytes);
     if (rc) return rc;
-    return b->dtype == XFDTD_F32 ? bgrad_forward_t<float>(b, n, seg, ws) : bgrad_forward_t<double>(b, n, seg, ws);
+    drop_tapes(b, ws, n, seg);
+    rc = b->dtype == XFDTD_F32 ? bgrad_forward_t<float>(b, n, seg, ws) : bgrad_forward_t<double>(b, n, seg, ws);
+    if (rc) return rc;
+    if (b->tapes.size() >= kMaxTapes) b->tapes.erase(b->tapes.begin());
+    xfdtd_batch_s::Tape t{{}, bws_arrays(n, seg), n, seg};
+    for (int64_t i = 0; i < b->m; ++i) t.ws.push_back((uintptr_t)ws[i]);
+    b->tapes.push_back(std::move(t));
+    return XFDTD_OK;
 }
 
 int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes,
@@ -910,6 +954,17 @@ int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *con
         if (!lam[i]) return set_error(XFDTD_EINVAL, "lam[%lld] is null", (long long)i);
     int rc = check_bws(b, n, seg, ws, ws_bytes, lam);
     if (rc) return rc;
+    auto it = std::find_if(b->tapes.begin(), b->tapes.end(), [&](const xfdtd_batch_s::Tape &e) {
+        if (e.n != n || e.seg != seg) return false;
+        for (int64_t i = 0; i < b->m; ++i)
+            if (e.ws[i] != (uintptr_t)ws[i]) return false;
+        return true;
+    });
+    if (it == b->tapes.end())
+        return set_error(XFDTD_EINVAL, "the workspaces hold no forward pass of n = %lld, seg = %lld on this batch "
+                                       "(a backward pass consumes it; run xfdtd_batch_grad_forward again)",
+                         (long long)n, (long long)seg);
+    b->tapes.erase(it);
     return b->dtype == XFDTD_F32 ? bgrad_backward_t<float>(b, n, seg, ws, lam, grad)
                                  : bgrad_backward_t<double>(b, n, seg, ws, lam, grad);
 }

@@ -308,6 +308,13 @@ struct xfdtd_s {
     double *grad_acc;   // device, 12 doubles
     hipStream_t aux;    // gradient backward: recompute stream (created on first use)
     int aux_device;
+    // Workspaces filled by a forward pass and not yet consumed by a backward
+    // pass (which overwrites their E snapshots): start, bytes used, n, seg.
+    struct Tape {
+        uintptr_t ws, bytes;
+        int64_t n, seg;
+    };
+    std::vector<Tape> tapes;
 };
 
 namespace {
@@ -1085,6 +1092,20 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
     return XFDTD_OK;
 }
 
+// At most this many workspaces per handle are remembered as holding a
+// forward pass; the oldest is forgotten first.
+constexpr size_t kMaxTapes = 64;
+
+// Forget every workspace that overlaps [ws, ws + bytes).
+void drop_tapes(xfdtd_t h, const void *ws, uint64_t bytes)
+{
+    const uintptr_t a = (uintptr_t)ws, b = a + bytes;
+    std::vector<xfdtd_s::Tape> &t = h->tapes;
+    t.erase(std::remove_if(t.begin(), t.end(),
+                           [&](const xfdtd_s::Tape &e) { return e.ws < b && a < e.ws + e.bytes; }),
+            t.end());
+}
+
 int check_ws(xfdtd_t h, int64_t n, int64_t seg, const void *ws, uint64_t ws_bytes)
 {
     if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
@@ -1151,8 +1172,13 @@ int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_
     for (int c = 0; c < 6; ++c)
         if (ranges_overlap(ws, wsb, h->fields[c], raw_field_bytes(h)))
             return fail(XFDTD_EINVAL, "the workspace overlaps bound field %d", c);
-    return h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
-                                 : grad_forward_t<double>(h, n, seg, (char *)ws);
+    drop_tapes(h, ws, wsb);
+    rc = h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
+                               : grad_forward_t<double>(h, n, seg, (char *)ws);
+    if (rc) return rc;
+    if (h->tapes.size() >= kMaxTapes) h->tapes.erase(h->tapes.begin());
+    h->tapes.push_back({(uintptr_t)ws, (uintptr_t)wsb, n, seg});
+    return XFDTD_OK;
 }
 
 int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes, void *const lam[6],
@@ -1172,6 +1198,14 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
         for (int q = c + 1; q < 6; ++q)
             if (ranges_overlap(lam[c], fb, lam[q], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps lam[%d]", c, q);
     }
+    auto it = std::find_if(h->tapes.begin(), h->tapes.end(), [&](const xfdtd_s::Tape &e) {
+        return e.ws == (uintptr_t)ws && e.n == n && e.seg == seg;
+    });
+    if (it == h->tapes.end())
+        return fail(XFDTD_EINVAL, "the workspace holds no forward pass of n = %lld, seg = %lld on this handle "
+                                  "(a backward pass consumes it; run xfdtd_grad_forward again)",
+                    (long long)n, (long long)seg);
+    h->tapes.erase(it);
     return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
                                  : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
 }

@@ -208,7 +208,8 @@ class Solver:
 
     def grad_backward(self, n, ws, lam, seg=0):
         """lam: six tensors, dL/d(final state) in, dL/d(initial state) out.
-        Returns dL/dcoeffs as 12 floats."""
+        Returns dL/dcoeffs as 12 floats.  Consumes the forward pass stored in
+        ``ws`` (same n and seg): a second backward needs a new grad_forward."""
         self._check_ws(ws)
         lam = self._check_like(lam, 6, "lam")
         self._bind()

@@ -267,6 +267,53 @@ def test_grad_rejects_aliased_arrays():
     s.grad_backward(n, ws, lam)  # the valid call still works
 
 
+def test_grad_backward_consumes_the_forward():
+    """The backward pass overwrites the workspace's E snapshots, so it needs
+    a forward pass of the same n and seg into that workspace before it: a
+    second backward, or one with another n or seg, is an argument error; a
+    new forward from the same state gives the same result bit for bit."""
+    shape = (6, 5, 7)
+    c = _coeffs(671)
+    dt = 0.9 * O.cfl_dt(c)
+    f0 = to_dev(S.uniform_fields(shape, 672))
+    s = pkg.Solver([t.clone() for t in f0], dt, c, scratch=False)
+    n, seg = 9, 2  # five segments: the recompute uses both snapshot sets twice
+    ws = torch.empty(s.grad_workspace_bytes(n, seg), dtype=torch.uint8, device=DEV)
+    lamN = to_dev(S.uniform_fields(shape, 673))
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws, [t.clone() for t in lamN], seg)  # no forward yet
+    s.grad_forward(n, ws, seg)
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n - 1, ws, [t.clone() for t in lamN], seg)
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws, [t.clone() for t in lamN], seg + 1)
+    l1 = [t.clone() for t in lamN]
+    g1 = s.grad_backward(n, ws, l1, seg)
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws, [t.clone() for t in lamN], seg)
+    for a in range(6):
+        s.fields[a].copy_(f0[a])
+    s.grad_forward(n, ws, seg)
+    l2 = [t.clone() for t in lamN]
+    g2 = s.grad_backward(n, ws, l2, seg)
+    assert list(g1) == list(g2)
+    for a in range(6):
+        assert torch.equal(l1[a], l2[a]), a
+
+
+def test_autograd_second_backward_raises():
+    shape, n = (6, 5, 7), 5
+    c = _coeffs(681)
+    dt = 0.9 * O.cfl_dt(c)
+    fields = [x.requires_grad_() for x in to_dev(S.uniform_fields(shape, 682))]
+    coeffs = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+    out = pkg.propagate(fields, coeffs, n, dt)
+    loss = sum((o * o).sum() for o in out)
+    loss.backward(retain_graph=True)
+    with pytest.raises(RuntimeError, match="consumes"):
+        loss.backward()
+
+
 def test_wrappers_check_tensor_shapes_before_the_library():
     """The library sees only pointers: the torch wrappers check the count,
     shape, dtype, device and layout of every tensor they pass."""

@@ -31,7 +31,7 @@ def _boxes(seed):
     return out
 
 
-@pytest.mark.parametrize("n,seg", [(7, 0), (7, 3), (9, 9), (1, 0), (0, 0)])
+@pytest.mark.parametrize("n,seg", [(7, 0), (7, 3), (10, 2), (5, 1), (9, 9), (1, 0), (0, 0)])
 @pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 3), (4, 1, 0, 32)])
 def test_batch_grad_matches_oracle_fp64(n, seg, cfg):
     boxes = _boxes(900)
@@ -146,3 +146,41 @@ def test_batch_grad_rejects_aliased_lambda():
     with pytest.raises(pkg.XfdtdError):
         bt.grad_backward(n, ws, [lam, lam])
     bt.grad_backward(n, ws, [lam, [t.clone() for t in lam]])
+
+
+def test_batch_grad_backward_consumes_the_forward():
+    """As for one box: the backward pass needs a forward pass of the same n
+    and seg into the same workspaces before it."""
+    shape = (6, 5, 7)
+    boxes = []
+    for b in range(2):
+        beta, delta = S.distinct_beta_delta(971 + b)
+        c = O.coeffs_from(beta, delta)
+        boxes.append((to_dev(S.uniform_fields(shape, 973 + b)), 0.9 * O.cfl_dt(c), c))
+    f0 = [[t.clone() for t in f] for (f, _, _) in boxes]
+    bt = pkg.Batch(boxes, tune=False)
+    n, seg = 9, 2
+    ws = bt.grad_workspaces(n, seg)
+    lamN = [to_dev(S.uniform_fields(shape, 975 + b)) for b in range(2)]
+    fresh = lambda: [[t.clone() for t in l] for l in lamN]
+    with pytest.raises(pkg.XfdtdError):
+        bt.grad_backward(n, ws, fresh(), seg)
+    bt.grad_forward(n, ws, seg)
+    with pytest.raises(pkg.XfdtdError):
+        bt.grad_backward(n, ws[::-1], fresh(), seg)  # workspaces of other boxes
+    with pytest.raises(pkg.XfdtdError):
+        bt.grad_backward(n - 1, ws, fresh(), seg)
+    l1 = fresh()
+    g1 = bt.grad_backward(n, ws, l1, seg)
+    with pytest.raises(pkg.XfdtdError):
+        bt.grad_backward(n, ws, fresh(), seg)
+    for b, (f, _, _) in enumerate(boxes):
+        for a in range(6):
+            f[a].copy_(f0[b][a])
+    bt.grad_forward(n, ws, seg)
+    l2 = fresh()
+    g2 = bt.grad_backward(n, ws, l2, seg)
+    assert [list(g) for g in g1] == [list(g) for g in g2]
+    for b in range(2):
+        for a in range(6):
+            assert torch.equal(l1[b][a], l2[b][a]), (b, a)
