@@ -118,13 +118,16 @@ def fwd_adj_ratio(steps=200):
     plain = [x.clone() for x in f32]
     sp = pkg.Solver(plain, dt, coeffs)
     sp.run(10)
-    torch.cuda.synchronize()
-    e0, e1 = ev(), ev()
-    e0.record()
-    sp.run(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    t_fwd = e0.elapsed_time(e1)
+    fwd_times = []
+    for rep in range(3):  # the same protocol as the fwd+adj timing below: min of 3
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        sp.run(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        fwd_times.append(e0.elapsed_time(e1))
+    t_fwd = min(fwd_times)
 
     seg = int(math.ceil(math.sqrt(2 * steps)))  # the library's default segment
     work = [x.clone() for x in f32]
@@ -133,13 +136,14 @@ def fwd_adj_ratio(steps=200):
     lam = [torch.zeros_like(x) for x in work]
     xp = int(round(0.25 * shape[2] + steps * dt)) % shape[2]
     times = []
-    for rep in range(2):
+    for rep in range(3):
         for a in range(6):
             work[a].copy_(f32[a])
         torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
+        e0, em, e1 = ev(), ev(), ev()
         e0.record()
         sg.grad_forward(steps, ws, seg)
+        em.record()
         for a in range(6):
             lam[a].zero_()
         for a in range(3):
@@ -147,8 +151,8 @@ def fwd_adj_ratio(steps=200):
         sg.grad_backward(steps, ws, lam, seg)
         e1.record()
         torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    t_fa = min(times)
+        times.append((e0.elapsed_time(e1), e0.elapsed_time(em)))
+    t_fa, t_gf = min(times)
     # every E kept (one segment of n steps: no recompute), for comparison
     ws2 = torch.empty(sg.grad_workspace_bytes(steps, steps), dtype=torch.uint8, device=dev)
     for a in range(6):
@@ -166,6 +170,7 @@ def fwd_adj_ratio(steps=200):
     torch.cuda.synchronize()
     t_all = e0.elapsed_time(e1)
     return {"ratio": round(t_fa / t_fwd, 3), "fwd_ms": round(t_fwd, 3), "fwd_adj_ms": round(t_fa, 3),
+            "grad_forward_ms": round(t_gf, 3), "grad_backward_ms": round(t_fa - t_gf, 3),
             "steps": steps, "segment": seg,
             "ratio_all_E_kept": round(t_all / t_fwd, 3),
             "workload": "128^3 FP32 Gaussian pulse (wavelength 12), "

@@ -308,7 +308,7 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
 /*
  * Checkpointed gradient of n steps.  The forward pass stores the state every
  * `seg` steps (seg <= 0 selects ceil(sqrt(2 n))) and the E fields of the last
- * segment; the backward pass recomputes every other segment from its
+ * two segments; the backward pass recomputes every earlier segment from its
  * checkpoint, keeping the E of each of its steps, and runs the adjoint steps
  * in reverse.  It recomputes segment m - 1 on a second (internal) stream
  * while it reverses segment m, so it holds two sets of E snapshots.

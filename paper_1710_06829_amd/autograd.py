@@ -4,10 +4,10 @@ library's hand-written adjoint kernels and its checkpoint schedule.
 ``propagate(fields, coeffs, n, dt)`` returns the six fields after n steps;
 gradients flow to the initial fields and to the 12 coefficients (a float64
 tensor).  The forward pass keeps the state every ``seg`` steps (default
-ceil(sqrt(2 n)), a workspace of O(sqrt(n)) fields); the backward pass
-recomputes each segment from its checkpoint (the previous segment on a second
-stream while it reverses the current one) and runs the adjoint steps in
-reverse (see include/xfdtd.h).
+ceil(sqrt(2 n)), a workspace of O(sqrt(n)) fields) and the E fields of the
+last two segments; the backward pass recomputes each earlier segment from its
+checkpoint (the previous segment on a second stream while it reverses the
+current one) and runs the adjoint steps in reverse (see include/xfdtd.h).
 """
 from __future__ import annotations
 

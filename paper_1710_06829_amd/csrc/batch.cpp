@@ -658,7 +658,9 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
 {
     const int64_t m = b->m;
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
-    const int64_t s0_last = (nck - 1) * seg;
+    // the last two segments write their E snapshots (as in the single-box
+    // forward pass)
+    const int64_t s0_keep = (nck >= 2 ? nck - 2 : 0) * seg;
     std::vector<BoxWs<T>> W(m);
     std::vector<Fields<T>> cur(m), fields(m);
     for (int64_t i = 0; i < m; ++i) {
@@ -680,10 +682,11 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
                 dst = fields[i];
             } else if ((s + 1) % seg == 0) {
                 dst = W[i].ck((s + 1) / seg);
-            } else if (s >= s0_last) {
+            } else if (s >= s0_keep) {
+                const int64_t k = s / seg, s0 = k * seg;
                 for (int c = 0; c < 3; ++c) {
-                    dst.c[c] = W[i].segE((int)((nck - 1) & 1), seg, s + 1 - s0_last, c);
-                    dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
+                    dst.c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
+                    dst.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
                 }
             } else {
                 dst = (cur[i].c[0] == A.c[0]) ? Bs : A;
@@ -708,7 +711,8 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
 // Batched backward pass, overlapped like the single-box one: the adjoint
 // launches run on the bound stream, segment by segment from the last, while
 // segment m - 1 is recomputed from its checkpoints on the batch's second
-// stream into the other set of E snapshots.  A recompute waits until the
+// stream into the other set of E snapshots (the forward pass wrote those of
+// the last two segments).  A recompute waits until the
 // adjoint has left the set it overwrites, an adjoint segment until its
 // recompute is done.
 template <typename T>
@@ -735,7 +739,7 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     for (int64_t k = 0; k < nck && n > 0; ++k) {
         const int64_t s0 = k * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
         roff[k] = (int64_t)rdesc.size() / m;
-        if (k == nck - 1) continue;  // the forward pass left this segment's snapshots
+        if (k >= nck - 2) continue;  // the forward pass left these segments' snapshots
         std::vector<Fields<T>> in(m);
         for (int64_t i = 0; i < m; ++i) in[i] = W[i].ck(k);
         for (int64_t s = s0; s + 1 < s1; ++s)
@@ -815,12 +819,8 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     // workgroup per item
     const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems) ? b->cfg.grid : b->naitems;
     bool first = true;
-    if (n > 0 && nck >= 2) {
-        rc = recompute(nck - 2);
-        if (rc) return rc;
-    }
     for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
-        if (k != nck - 1) BTRY(hipStreamWaitEvent(mainS, evs.ev[(size_t)(1 + k)], 0), "hipStreamWaitEvent");
+        if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, evs.ev[(size_t)(1 + k)], 0), "hipStreamWaitEvent");
         const int64_t nl = (k > 0 ? aoff[k - 1] : (int64_t)adesc.size() / m) - aoff[k];
         for (int64_t l = aoff[k]; l < aoff[k] + nl; ++l) {
             hipError_t e = launch_batched_adjoint<T>(d_a + l * m, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,

@@ -872,8 +872,8 @@ size_t field_bytes(const xfdtd_s *h)
 
 // Default segment length ceil(sqrt(2 n)): the workspace holds
 // 6 ceil(n/seg) + 12 + 6 (seg - 1) field arrays (ws_arrays), within about 6 % of its
-// minimum (at sqrt(n)), and the backward pass recomputes n - seg steps,
-// fewer than at sqrt(n).
+// minimum (at sqrt(n)), and the backward pass recomputes about n - 2 seg
+// steps, fewer than at sqrt(n).
 int64_t default_seg(int64_t n, int64_t seg)
 {
     if (seg > 0) return seg;
@@ -922,9 +922,10 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
     for (int c = 0; c < 6; ++c)
         HIP_TRY(hipMemcpyAsync(ck0.c[c], fields.c[c], raw, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
     Fields<T> A = state_at<T>(ws, fb, 6 * nck), B = state_at<T>(ws, fb, 6 * nck + 6);
-    // The last segment's E fields go straight to the snapshot slots that the
-    // backward pass would otherwise recompute (B ping-pongs in state A).
-    const int64_t s0_last = (nck - 1) * seg;
+    // The E fields of the last two segments go straight to their snapshot
+    // sets (both are free during the forward pass), which the backward pass
+    // would otherwise recompute; B ping-pongs in state A there.
+    const int64_t s0_keep = (nck >= 2 ? nck - 2 : 0) * seg;
     Fields<T> cur = ck0;
     for (int64_t s = 0; s < n; ++s) {
         Fields<T> dst;
@@ -932,11 +933,12 @@ int grad_forward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws)
             dst = fields;
         } else if ((s + 1) % seg == 0) {
             dst = state_at<T>(ws, fb, 6 * ((s + 1) / seg));
-        } else if (s >= s0_last) {
-            const int64_t e = snap_index(nck, seg, (int)((nck - 1) & 1), s + 1 - s0_last);
+        } else if (s >= s0_keep) {
+            const int64_t m = s / seg, s0 = m * seg;
+            const int64_t e = snap_index(nck, seg, (int)(m & 1), s + 1 - s0);
             for (int c = 0; c < 3; ++c) {
                 dst.c[c] = (T *)(ws + (size_t)(e + c) * fb);
-                dst.c[3 + c] = A.c[3 * ((s - s0_last) & 1) + c];
+                dst.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
             }
         } else {
             dst = (cur.c[0] == A.c[0]) ? B : A;
@@ -989,9 +991,9 @@ struct EventSet {
 // Backward pass.  The adjoint steps run on the handle's stream, segment by
 // segment from the last; segment m - 1 is recomputed from its checkpoint on
 // the second stream meanwhile, into the other set of E snapshots (the forward
-// pass wrote the last segment's).  Events order the two: a recompute waits
-// until the adjoint has left the set it overwrites, an adjoint segment until
-// its recompute is done.
+// pass wrote those of the last two segments).  Events order the two: a
+// recompute waits until the adjoint has left the set it overwrites, an
+// adjoint segment until its recompute is done.
 template <typename T>
 int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam[6], double grad[12])
 {
@@ -1047,14 +1049,10 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
 
     Fields<T> lcur = lamU, lnext = lamS;
     bool first = true;
-    if (n > 0 && nck >= 2) {
-        rc = recompute(nck - 2);
-        if (rc) return rc;
-    }
     for (int64_t m = nck - 1; m >= 0 && n > 0; --m) {
         const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
         Fields<T> ck = state_at<T>(ws, fb, 6 * m);
-        if (m != nck - 1) HIP_TRY(hipStreamWaitEvent(mainS, ev_rec(m), 0), "hipStreamWaitEvent");
+        if (m < nck - 2) HIP_TRY(hipStreamWaitEvent(mainS, ev_rec(m), 0), "hipStreamWaitEvent");
         // reverse through the segment
         for (int64_t s = s1 - 1; s >= s0; --s) {
             const T *en[3];
