@@ -67,6 +67,7 @@ struct xfdtd_batch_s {
     double *d_apart = nullptr;
     int *d_afirst = nullptr;
     double *d_scale = nullptr, *d_grad = nullptr;
+    int atx = 64;  // adjoint tile width, chosen when the work list is built
     // Workspace lists filled by a forward pass and not yet consumed by a
     // backward pass (which overwrites their E snapshots).
     struct Tape {
@@ -577,11 +578,28 @@ BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, cons
     return d;
 }
 
-// The batched adjoint takes the forward's tile width and a tile height it
-// supports (4 or 8; the 64x8 FP64 tile does not fit in LDS).
+// Tile width of the batched adjoint: the forward's, or 32 columns when every
+// box is at most 96 cells wide and 32-column tiles load fewer columns in all
+// (tile plus its 4 halo columns, summed over the boxes' rows): nx = 96 loads
+// 3 x 36 columns instead of 2 x 68.
+int pick_adj_tx(const xfdtd_batch_s *b)
+{
+    if (b->cfg.tile_x == 32) return 32;
+    double c64 = 0, c32 = 0;
+    for (const xfdtd_grid &g : b->g) {
+        if (g.nx > 96) return 64;
+        const double rows = (double)g.ny * (double)g.nz;
+        c64 += (double)((g.nx + 63) / 64 * 68) * rows;
+        c32 += (double)((g.nx + 31) / 32 * 36) * rows;
+    }
+    return c32 < c64 ? 32 : 64;
+}
+
+// The batched adjoint's tile height: one it supports (4 or 8; the 64x8 FP64
+// tile does not fit in LDS).
 int adj_tile(const xfdtd_batch_s *b)
 {
-    if (b->dtype == XFDTD_F64 && b->cfg.tile_x == 64) return 4;
+    if (b->dtype == XFDTD_F64 && b->atx == 64) return 4;
     return b->cfg.tile_y > 8 ? 8 : b->cfg.tile_y;
 }
 
@@ -597,7 +615,7 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
     a.d = f.d;
     a.w = f.w;
     a.zchunk = f.zchunk;
-    a.ntx = (int)((b->g[i].nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
+    a.ntx = (int)((b->g[i].nx + b->atx - 1) / b->atx);
     a.nty = (int)((b->g[i].ny + adj_tile(b) - 1) / adj_tile(b));
     a.pad = 0;
     return a;
@@ -719,6 +737,7 @@ template <typename T>
 int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, void *const *lam, double *grad)
 {
     const int64_t m = b->m;
+    b->atx = pick_adj_tx(b);
     int rc = build_adjoint<T>(b);
     if (rc) return rc;
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
@@ -815,16 +834,17 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
         BTRY(hipEventRecord(evs.ev[(size_t)(1 + k)], aux), "hipEventRecord");
         return XFDTD_OK;
     };
-    // adjoint grid: the tuned persistent size if one is set, else one
-    // workgroup per item
-    const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems) ? b->cfg.grid : b->naitems;
+    // adjoint grid: the tuned persistent size if one is set (and the adjoint
+    // tiles are as wide as the forward's), else one workgroup per item
+    const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems && b->atx == b->cfg.tile_x) ? b->cfg.grid
+                                                                                        : b->naitems;
     bool first = true;
     for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
         if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, evs.ev[(size_t)(1 + k)], 0), "hipStreamWaitEvent");
         const int64_t nl = (k > 0 ? aoff[k - 1] : (int64_t)adesc.size() / m) - aoff[k];
         for (int64_t l = aoff[k]; l < aoff[k] + nl; ++l) {
             hipError_t e = launch_batched_adjoint<T>(d_a + l * m, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
-                                                     b->cfg.tile_x, adj_tile(b), ga, mainS);
+                                                     b->atx, adj_tile(b), ga, mainS);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
             first = false;
         }
