@@ -436,6 +436,8 @@ def main():
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
     ap.add_argument("--grad-batch-only", action="store_true", help="only the batched gradient measurement")
     ap.add_argument("--norm-only", action="store_true", help="only the dispersion-norm measurement")
+    ap.add_argument("--fp64-only", action="store_true", help="only the FP64 512x256x256 measurement")
+    ap.add_argument("--batch-only", action="store_true", help="only the 64-box batched measurement")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 1024x256x256 sustained run and the 64-box batch")
     args = ap.parse_args()
@@ -455,6 +457,12 @@ def main():
         return
     if args.grad_batch_only:
         print(json.dumps({"batched_grads_16x96cube": batched_grads()}), flush=True)
+        return
+    if args.fp64_only:
+        print(json.dumps({"fp64_512x256x256": fp64_step()}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched_64_boxes": batched_boxes()}), flush=True)
         return
     steps = args.steps + (args.steps & 1)  # the fused kernel runs in pairs
     fields, coeffs, dt, f64 = make_inputs(SHAPE, torch.float32)
