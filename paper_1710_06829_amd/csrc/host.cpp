@@ -883,7 +883,8 @@ int64_t default_seg(int64_t n, int64_t seg)
 
 // Workspace layout, in units of one field array (field_bytes):
 //   [0, 6*nck)            checkpoints, state m at step m*seg
-//   [6*nck, 6*nck+6)      state A (forward ping-pong; backward: B ping-pong)
+//   [6*nck, 6*nck+6)      state A (forward ping-pong, B ping-pong in the last
+//                         two segments; backward: B ping-pong of the recompute)
 //   [6*nck+6, 6*nck+12)   state B (forward ping-pong; backward: lambda scratch)
 //   [6*nck+12, ...)       two sets of (seg-1) E snapshots (3 arrays each):
 //                         segment m uses set m & 1, so that the backward pass

@@ -301,6 +301,21 @@ def test_grad_backward_consumes_the_forward():
         assert torch.equal(l1[a], l2[a]), a
 
 
+def test_grad_handle_remembers_its_last_64_forward_passes():
+    shape, n = (4, 3, 5), 2
+    c = _coeffs(691)
+    s = pkg.Solver(to_dev(S.uniform_fields(shape, 692)), 0.9 * O.cfl_dt(c), c, scratch=False)
+    nb = s.grad_workspace_bytes(n)
+    ws = [torch.empty(nb, dtype=torch.uint8, device=DEV) for _ in range(65)]
+    for w in ws:
+        s.grad_forward(n, w)
+    lam = to_dev(S.uniform_fields(shape, 693))
+    with pytest.raises(pkg.XfdtdError):
+        s.grad_backward(n, ws[0], [t.clone() for t in lam])  # forgotten: the oldest of 65
+    s.grad_backward(n, ws[1], [t.clone() for t in lam])
+    s.grad_backward(n, ws[64], [t.clone() for t in lam])
+
+
 def test_autograd_second_backward_raises():
     shape, n = (6, 5, 7), 5
     c = _coeffs(681)
