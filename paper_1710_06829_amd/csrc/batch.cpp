@@ -15,8 +15,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -243,6 +247,20 @@ std::string shape_key(const xfdtd_batch_t b)
     return k;
 }
 
+// Runs an entry point's body; host allocation failures (and any other C++
+// exception) become an error code instead of crossing the C interface.
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return set_error(XFDTD_EINVAL, "out of host memory");
+    } catch (const std::exception &e) {
+        return set_error(XFDTD_EINVAL, "%s", e.what());
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -250,44 +268,47 @@ extern "C" {
 int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double *coeffs, int64_t m, int dtype,
                        int allow_unstable, xfdtd_batch_t *out)
 {
-    if (!out) return set_error(XFDTD_EINVAL, "out is null");
-    *out = nullptr;
-    if (m < 1 || m > (1 << 20)) return set_error(XFDTD_EINVAL, "box count must be in [1, 2^20]");
-    if (!grids || !dts || !coeffs) return set_error(XFDTD_EINVAL, "null argument");
-    if (dtype != XFDTD_F32 && dtype != XFDTD_F64) return set_error(XFDTD_EINVAL, "bad dtype");
-    for (int64_t i = 0; i < m; ++i) {
-        const xfdtd_grid &g = grids[i];
-        if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > (1 << 30) || g.ny > (1 << 30) || g.nz > (1 << 30) ||
-            (double)g.nx * g.ny * g.nz > 4.0e9 || (double)g.nx * g.ny > (double)(1 << 28) || !(g.dx > 0) ||
-            !(g.dy > 0) || !(g.dz > 0) ||
-            !isfinite(g.dx) || !isfinite(g.dy) || !isfinite(g.dz))
-            return set_error(XFDTD_EINVAL, "box %lld: invalid grid", (long long)i);
-        if (!(dts[i] > 0) || !isfinite(dts[i])) return set_error(XFDTD_EINVAL, "box %lld: bad dt", (long long)i);
-        for (int j = 0; j < 12; ++j)
-            if (!isfinite(coeffs[12 * i + j])) return set_error(XFDTD_EINVAL, "box %lld: bad coeffs", (long long)i);
-        if (!allow_unstable) {
-            const double sp[3] = {g.dx, g.dy, g.dz};
-            double lo, hi;
-            f_range(sp, &coeffs[12 * i], &lo, &hi);
-            if (lo < -1e-12 * fmax(1.0, fabs(hi)))
-                return set_error(XFDTD_EUNSTABLE, "box %lld: F_min < 0", (long long)i);
-            if (dts[i] * dts[i] * hi > 1.0 + 1e-12)
-                return set_error(XFDTD_EUNSTABLE, "box %lld: dt exceeds the stability bound", (long long)i);
+    return guarded([&]() -> int {
+        if (!out) return set_error(XFDTD_EINVAL, "out is null");
+        *out = nullptr;
+        if (m < 1 || m > (1 << 20)) return set_error(XFDTD_EINVAL, "box count must be in [1, 2^20]");
+        if (!grids || !dts || !coeffs) return set_error(XFDTD_EINVAL, "null argument");
+        if (dtype != XFDTD_F32 && dtype != XFDTD_F64) return set_error(XFDTD_EINVAL, "bad dtype");
+        for (int64_t i = 0; i < m; ++i) {
+            const xfdtd_grid &g = grids[i];
+            if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > (1 << 30) || g.ny > (1 << 30) || g.nz > (1 << 30) ||
+                (double)g.nx * g.ny * g.nz > 4.0e9 || (double)g.nx * g.ny > (double)(1 << 28) || !(g.dx > 0) ||
+                !(g.dy > 0) || !(g.dz > 0) ||
+                !isfinite(g.dx) || !isfinite(g.dy) || !isfinite(g.dz))
+                return set_error(XFDTD_EINVAL, "box %lld: invalid grid", (long long)i);
+            if (!(dts[i] > 0) || !isfinite(dts[i])) return set_error(XFDTD_EINVAL, "box %lld: bad dt", (long long)i);
+            for (int j = 0; j < 12; ++j)
+                if (!isfinite(coeffs[12 * i + j])) return set_error(XFDTD_EINVAL, "box %lld: bad coeffs", (long long)i);
+            if (!allow_unstable) {
+                const double sp[3] = {g.dx, g.dy, g.dz};
+                double lo, hi;
+                f_range(sp, &coeffs[12 * i], &lo, &hi);
+                if (lo < -1e-12 * fmax(1.0, fabs(hi)))
+                    return set_error(XFDTD_EUNSTABLE, "box %lld: F_min < 0", (long long)i);
+                if (dts[i] * dts[i] * hi > 1.0 + 1e-12)
+                    return set_error(XFDTD_EUNSTABLE, "box %lld: dt exceeds the stability bound", (long long)i);
+            }
         }
-    }
-    xfdtd_batch_s *b = new (std::nothrow) xfdtd_batch_s();
-    if (!b) return set_error(XFDTD_EINVAL, "out of host memory");
-    b->m = m;
-    b->dtype = dtype;
-    b->g.assign(grids, grids + m);
-    b->dt.assign(dts, dts + m);
-    b->coeffs.assign(coeffs, coeffs + 12 * m);
-    b->cfg.tile_x = prefer_narrow(b) ? 32 : 64;
-    b->cfg.tile_y = 8;
-    b->cfg.zsplit = model_zsplit(b, b->cfg.tile_x, b->cfg.tile_y);
-    b->key = shape_key(b);
-    *out = b;
-    return XFDTD_OK;
+        std::unique_ptr<xfdtd_batch_s> hold(new (std::nothrow) xfdtd_batch_s());
+        xfdtd_batch_s *b = hold.get();
+        if (!b) return set_error(XFDTD_EINVAL, "out of host memory");
+        b->m = m;
+        b->dtype = dtype;
+        b->g.assign(grids, grids + m);
+        b->dt.assign(dts, dts + m);
+        b->coeffs.assign(coeffs, coeffs + 12 * m);
+        b->cfg.tile_x = prefer_narrow(b) ? 32 : 64;
+        b->cfg.tile_y = 8;
+        b->cfg.zsplit = model_zsplit(b, b->cfg.tile_x, b->cfg.tile_y);
+        b->key = shape_key(b);
+        *out = hold.release();
+        return XFDTD_OK;
+    });
 }
 
 void xfdtd_batch_destroy(xfdtd_batch_t b)
@@ -307,47 +328,51 @@ void xfdtd_batch_destroy(xfdtd_batch_t b)
 
 int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch, void *stream)
 {
-    if (!b || !fields || !scratch) return set_error(XFDTD_EINVAL, "null argument");
-    const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
-    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
-    for (int64_t i = 0; i < b->m; ++i) {
-        const size_t bytes = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
-        for (int c = 0; c < 6; ++c) {
-            for (void *p : {fields[6 * i + c], scratch[6 * i + c]}) {
-                if (!p || (uintptr_t)p % 16) return set_error(XFDTD_EINVAL, "box %lld: null or misaligned array", (long long)i);
-                spans.push_back({(uintptr_t)p, (uintptr_t)p + bytes});
+    return guarded([&]() -> int {
+        if (!b || !fields || !scratch) return set_error(XFDTD_EINVAL, "null argument");
+        const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
+        std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+        for (int64_t i = 0; i < b->m; ++i) {
+            const size_t bytes = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
+            for (int c = 0; c < 6; ++c) {
+                for (void *p : {fields[6 * i + c], scratch[6 * i + c]}) {
+                    if (!p || (uintptr_t)p % 16) return set_error(XFDTD_EINVAL, "box %lld: null or misaligned array", (long long)i);
+                    spans.push_back({(uintptr_t)p, (uintptr_t)p + bytes});
+                }
             }
         }
-    }
-    std::sort(spans.begin(), spans.end());
-    for (size_t i = 1; i < spans.size(); ++i)
-        if (spans[i].first < spans[i - 1].second) return set_error(XFDTD_EINVAL, "bound arrays overlap");
-    b->f.assign(fields, fields + 6 * b->m);
-    b->s.assign(scratch, scratch + 6 * b->m);
-    b->stream = (hipStream_t)stream;
-    b->bound = true;
-    if (!b->capture) BTRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
-    if (!b->aux) BTRY(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking), "hipStreamCreate");
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(b->key);
-        if (!b->cfg_set && it != g_cache.end()) b->cfg = it->second;
-    }
-    return build(b);
+        std::sort(spans.begin(), spans.end());
+        for (size_t i = 1; i < spans.size(); ++i)
+            if (spans[i].first < spans[i - 1].second) return set_error(XFDTD_EINVAL, "bound arrays overlap");
+        b->f.assign(fields, fields + 6 * b->m);
+        b->s.assign(scratch, scratch + 6 * b->m);
+        b->stream = (hipStream_t)stream;
+        b->bound = true;
+        if (!b->capture) BTRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "hipStreamCreate");
+        if (!b->aux) BTRY(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking), "hipStreamCreate");
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_cache.find(b->key);
+            if (!b->cfg_set && it != g_cache.end()) b->cfg = it->second;
+        }
+        return build(b);
+    });
 }
 
 int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_x, int tile_y, int zsplit, int grid)
 {
-    if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if ((tile_x != 32 && tile_x != 64) || (tile_y != 4 && tile_y != 8 && tile_y != 16) || zsplit < 1 ||
-        zsplit > 1024 || grid < 0 || (tile_y == 16 && b->dtype != XFDTD_F32))
-        return set_error(XFDTD_EINVAL, "bad configuration");
-    b->cfg.tile_x = tile_x;
-    b->cfg.tile_y = tile_y;
-    b->cfg.zsplit = zsplit;
-    b->cfg.grid = grid;
-    b->cfg_set = true;
-    return b->bound ? build(b) : XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if ((tile_x != 32 && tile_x != 64) || (tile_y != 4 && tile_y != 8 && tile_y != 16) || zsplit < 1 ||
+            zsplit > 1024 || grid < 0 || (tile_y == 16 && b->dtype != XFDTD_F32))
+            return set_error(XFDTD_EINVAL, "bad configuration");
+        b->cfg.tile_x = tile_x;
+        b->cfg.tile_y = tile_y;
+        b->cfg.zsplit = zsplit;
+        b->cfg.grid = grid;
+        b->cfg_set = true;
+        return b->bound ? build(b) : XFDTD_OK;
+    });
 }
 
 int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems)
@@ -363,150 +388,156 @@ int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zspli
 
 int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
 {
-    if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
-    if (!force) {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(b->key);
-        if (it != g_cache.end()) {
-            b->cfg = it->second;
-            b->cfg_set = true;
-            if (best_ms) *best_ms = -1.0;
-            return build(b);
+    return guarded([&]() -> int {
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
+        if (!force) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_cache.find(b->key);
+            if (it != g_cache.end()) {
+                b->cfg = it->second;
+                b->cfg_set = true;
+                if (best_ms) *best_ms = -1.0;
+                return build(b);
+            }
         }
-    }
-    const int ncu = cus();
-    std::vector<Config> cands;
-    const int tys[3] = {4, 8, 16};
-    bool narrow = false;  // 32-column candidates where some box leaves 64-wide tiles part idle
-    for (const xfdtd_grid &g : b->g)
-        if (g.nx % 64 != 0 && g.nx % 64 <= 32) narrow = true;
-    for (int tx : {64, 32}) {
-        if (tx == 32 && !narrow) continue;
-        for (int ty : tys) {
-            if (b->dtype == XFDTD_F64 && ty == 16) continue;
-            const int zm = model_zsplit(b, tx, ty);
-            for (int zs : {1, 2, 4, zm}) {
-                if (zs == zm && (zm == 1 || zm == 2 || zm == 4)) continue;  // already a candidate
-                for (int gm : {0, 1, 2}) {
-                    Config c;
-                    c.tile_x = tx;
-                    c.tile_y = ty;
-                    c.zsplit = zs;
-                    c.grid = gm == 0 ? 0 : gm * ncu;
-                    cands.push_back(c);
+        const int ncu = cus();
+        std::vector<Config> cands;
+        const int tys[3] = {4, 8, 16};
+        bool narrow = false;  // 32-column candidates where some box leaves 64-wide tiles part idle
+        for (const xfdtd_grid &g : b->g)
+            if (g.nx % 64 != 0 && g.nx % 64 <= 32) narrow = true;
+        for (int tx : {64, 32}) {
+            if (tx == 32 && !narrow) continue;
+            for (int ty : tys) {
+                if (b->dtype == XFDTD_F64 && ty == 16) continue;
+                const int zm = model_zsplit(b, tx, ty);
+                for (int zs : {1, 2, 4, zm}) {
+                    if (zs == zm && (zm == 1 || zm == 2 || zm == 4)) continue;  // already a candidate
+                    for (int gm : {0, 1, 2}) {
+                        Config c;
+                        c.tile_x = tx;
+                        c.tile_y = ty;
+                        c.zsplit = zs;
+                        c.grid = gm == 0 ? 0 : gm * ncu;
+                        cands.push_back(c);
+                    }
                 }
             }
         }
-    }
-    hipEvent_t e0, e1;
-    BTRY(hipEventCreate(&e0), "hipEventCreate");
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return set_error(XFDTD_EHIP, "hipEventCreate failed");
-    }
-    // Two interleaved passes over the candidates; each timing covers about
-    // 2 ms of steps (f -> s only: the bound state is not modified) and a
-    // candidate keeps its faster pass.
-    std::vector<double> per(cands.size(), INFINITY);
-    std::vector<int> reps(cands.size(), 0);
-    const Config prev = b->cfg;
-    int rc = XFDTD_OK;
-    auto timed = [&](int r, float *ms) {
-        int q = hipEventRecord(e0, b->stream) == hipSuccess ? XFDTD_OK : set_error(XFDTD_EHIP, "event record");
-        for (int i = 0; i < r && !q; ++i) q = launch_step(b, 0, b->stream);
-        if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = set_error(XFDTD_EHIP, "event record");
-        if (!q && hipEventSynchronize(e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event synchronize");
-        if (!q && hipEventElapsedTime(ms, e0, e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event time");
-        return q;
-    };
-    for (int pass = 0; pass < 2 && !rc; ++pass)
-        for (size_t i = 0; i < cands.size() && !rc; ++i) {
-            b->cfg = cands[i];
-            rc = build(b);
-            if (rc) break;
-            float ms = 0.f;
-            if (reps[i] == 0) {  // warm-up step, whose time sizes the repetitions
-                rc = timed(1, &ms);
-                reps[i] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
+        hipEvent_t e0, e1;
+        BTRY(hipEventCreate(&e0), "hipEventCreate");
+        if (hipEventCreate(&e1) != hipSuccess) {
+            hipEventDestroy(e0);
+            return set_error(XFDTD_EHIP, "hipEventCreate failed");
+        }
+        // Two interleaved passes over the candidates; each timing covers about
+        // 2 ms of steps (f -> s only: the bound state is not modified) and a
+        // candidate keeps its faster pass.
+        std::vector<double> per(cands.size(), INFINITY);
+        std::vector<int> reps(cands.size(), 0);
+        const Config prev = b->cfg;
+        int rc = XFDTD_OK;
+        auto timed = [&](int r, float *ms) {
+            int q = hipEventRecord(e0, b->stream) == hipSuccess ? XFDTD_OK : set_error(XFDTD_EHIP, "event record");
+            for (int i = 0; i < r && !q; ++i) q = launch_step(b, 0, b->stream);
+            if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = set_error(XFDTD_EHIP, "event record");
+            if (!q && hipEventSynchronize(e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event synchronize");
+            if (!q && hipEventElapsedTime(ms, e0, e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event time");
+            return q;
+        };
+        for (int pass = 0; pass < 2 && !rc; ++pass)
+            for (size_t i = 0; i < cands.size() && !rc; ++i) {
+                b->cfg = cands[i];
+                rc = build(b);
+                if (rc) break;
+                float ms = 0.f;
+                if (reps[i] == 0) {  // warm-up step, whose time sizes the repetitions
+                    rc = timed(1, &ms);
+                    reps[i] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
+                }
+                if (!rc) rc = timed(reps[i], &ms);
+                if (!rc) per[i] = std::min(per[i], (double)ms / reps[i]);
             }
-            if (!rc) rc = timed(reps[i], &ms);
-            if (!rc) per[i] = std::min(per[i], (double)ms / reps[i]);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc) {  // keep the configuration the batch had (its error, if any, is secondary)
+            const std::string msg = xfdtd_last_error();
+            b->cfg = prev;
+            build(b);
+            set_error(rc, "%s", msg.c_str());
+            return rc;
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (rc) {  // keep the configuration the batch had (its error, if any, is secondary)
-        const std::string msg = xfdtd_last_error();
-        b->cfg = prev;
-        build(b);
-        set_error(rc, "%s", msg.c_str());
-        return rc;
-    }
-    double best = INFINITY;
-    Config bestc = prev;
-    for (size_t i = 0; i < cands.size(); ++i)
-        if (per[i] < best) {
-            best = per[i];
-            bestc = cands[i];
+        double best = INFINITY;
+        Config bestc = prev;
+        for (size_t i = 0; i < cands.size(); ++i)
+            if (per[i] < best) {
+                best = per[i];
+                bestc = cands[i];
+            }
+        b->cfg = bestc;
+        b->cfg_set = true;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_cache[b->key] = bestc;
         }
-    b->cfg = bestc;
-    b->cfg_set = true;
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        g_cache[b->key] = bestc;
-    }
-    if (best_ms) *best_ms = best;
-    return build(b);
+        if (best_ms) *best_ms = best;
+        return build(b);
+    });
 }
 
 int xfdtd_batch_run(xfdtd_batch_t b, int64_t n)
 {
-    if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
-    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
-    if (n == 0) return XFDTD_OK;
-    if (b->graph_n != n || !b->gexec) {
-        drop_graph(b);
-        BTRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        int rc = XFDTD_OK;
-        int64_t left = n;
-        if (left & 1) {  // odd count: one in-place step keeps the result in the state arrays
-            rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->capture) : unfused_all<double>(b, b->capture);
-            --left;
+    return guarded([&]() -> int {
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
+        if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
+        if (n == 0) return XFDTD_OK;
+        if (b->graph_n != n || !b->gexec) {
+            drop_graph(b);
+            BTRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            int rc = XFDTD_OK;
+            int64_t left = n;
+            if (left & 1) {  // odd count: one in-place step keeps the result in the state arrays
+                rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->capture) : unfused_all<double>(b, b->capture);
+                --left;
+            }
+            for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->capture);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->capture, &graph);
+            if (rc) {
+                if (graph) hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess) return set_error(XFDTD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                b->gexec = nullptr;
+                return set_error(XFDTD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            b->graph_n = n;
         }
-        for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->capture);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(b->capture, &graph);
-        if (rc) {
-            if (graph) hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess) return set_error(XFDTD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            b->gexec = nullptr;
-            return set_error(XFDTD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-        }
-        b->graph_n = n;
-    }
-    BTRY(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
-    return XFDTD_OK;
+        BTRY(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n)
 {
-    if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
-    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
-    int rc = XFDTD_OK;
-    int64_t left = n;
-    if (left & 1) {
-        rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->stream) : unfused_all<double>(b, b->stream);
-        --left;
-    }
-    for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->stream);
-    return rc;
+    return guarded([&]() -> int {
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
+        if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
+        int rc = XFDTD_OK;
+        int64_t left = n;
+        if (left & 1) {
+            rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->stream) : unfused_all<double>(b, b->stream);
+            --left;
+        }
+        for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->stream);
+        return rc;
+    });
 }
 
 }  // extern "C"
@@ -690,34 +721,47 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
             BTRY(hipMemcpyAsync(ck0.c[c], fields[i].c[c], raw, hipMemcpyDeviceToDevice, b->stream), "hipMemcpyAsync");
         cur[i] = ck0;
     }
+    // Every box follows the same schedule, so a step's descriptors are fixed
+    // by box 0's source and destination arrays; steps with the same ones
+    // (the ping-pong, the snapshot slots of a set) share a descriptor array,
+    // which keeps the upload at O(m (n/seg + seg)) descriptors.
     std::vector<BoxDesc<T>> descs;
-    descs.reserve((size_t)(n * m));
-    for (int64_t s = 0; s < n; ++s)
+    std::map<std::array<uintptr_t, 4>, int64_t> seen;
+    std::vector<int64_t> off((size_t)n);
+    std::vector<Fields<T>> dst(m);
+    for (int64_t s = 0; s < n; ++s) {
         for (int64_t i = 0; i < m; ++i) {
-            Fields<T> dst;
             const Fields<T> A = W[i].A(), Bs = W[i].B();
             if (s + 1 == n) {
-                dst = fields[i];
+                dst[i] = fields[i];
             } else if ((s + 1) % seg == 0) {
-                dst = W[i].ck((s + 1) / seg);
+                dst[i] = W[i].ck((s + 1) / seg);
             } else if (s >= s0_keep) {
                 const int64_t k = s / seg, s0 = k * seg;
                 for (int c = 0; c < 3; ++c) {
-                    dst.c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
-                    dst.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
+                    dst[i].c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
+                    dst[i].c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
                 }
             } else {
-                dst = (cur[i].c[0] == A.c[0]) ? Bs : A;
+                dst[i] = (cur[i].c[0] == A.c[0]) ? Bs : A;
             }
-            descs.push_back(fwd_desc<T>(b, i, cur[i], dst));
-            cur[i] = dst;
         }
+        const std::array<uintptr_t, 4> key = {(uintptr_t)cur[0].c[0], (uintptr_t)cur[0].c[3],
+                                              (uintptr_t)dst[0].c[0], (uintptr_t)dst[0].c[3]};
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            it = seen.emplace(key, (int64_t)descs.size()).first;
+            for (int64_t i = 0; i < m; ++i) descs.push_back(fwd_desc<T>(b, i, cur[i], dst[i]));
+        }
+        off[(size_t)s] = it->second;
+        cur = dst;
+    }
     BoxDesc<T> *d_descs = nullptr;
     BTRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     int rc = upload(descs, &d_descs);
     if (rc) return rc;
     for (int64_t s = 0; s < n && !rc; ++s) {
-        hipError_t e = launch_batched<T>(d_descs + s * m, b->d_items, b->nitems, 0, b->cfg.tile_x,
+        hipError_t e = launch_batched<T>(d_descs + off[(size_t)s], b->d_items, b->nitems, 0, b->cfg.tile_x,
                                          b->cfg.tile_y, grid_of(b), b->stream);
         if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched launch: %s", hipGetErrorString(e));
     }
@@ -750,42 +794,64 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
         lcur[i] = lamU[i];
         lnext[i] = lamS[i];
     }
-    // descriptors of every launch; segment k's recompute launches start at
-    // rdesc[m * roff[k]], its adjoint launches at adesc[m * aoff[k]]
+    // Descriptors, shared between launches with the same arrays (as in the
+    // forward pass): recompute launch l of the whole pass uses rdesc[roff[l]],
+    // segment k's recompute launches are [rl[k], rl[k + 1]); adjoint launch l
+    // uses adesc[aoff[l]], segment k's adjoint launches are [al[k], aend(k)).
     std::vector<BoxDesc<T>> rdesc;
     std::vector<AdjDesc<T>> adesc;
-    std::vector<int64_t> roff(nck + 1, 0), aoff(nck + 1, 0);
+    std::vector<int64_t> roff, aoff, rl(nck + 1, 0), al(nck + 1, 0);
+    std::map<std::array<uintptr_t, 4>, int64_t> rseen, aseen;
     for (int64_t k = 0; k < nck && n > 0; ++k) {
         const int64_t s0 = k * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
-        roff[k] = (int64_t)rdesc.size() / m;
+        rl[k] = (int64_t)roff.size();
         if (k >= nck - 2) continue;  // the forward pass left these segments' snapshots
-        std::vector<Fields<T>> in(m);
+        std::vector<Fields<T>> in(m), out(m);
         for (int64_t i = 0; i < m; ++i) in[i] = W[i].ck(k);
-        for (int64_t s = s0; s + 1 < s1; ++s)
+        for (int64_t s = s0; s + 1 < s1; ++s) {
             for (int64_t i = 0; i < m; ++i) {
-                Fields<T> out;
                 const Fields<T> A = W[i].A();
                 for (int c = 0; c < 3; ++c) {
-                    out.c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
-                    out.c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
+                    out[i].c[c] = W[i].segE((int)(k & 1), seg, s + 1 - s0, c);
+                    out[i].c[3 + c] = A.c[3 * ((s - s0) & 1) + c];
                 }
-                rdesc.push_back(fwd_desc<T>(b, i, in[i], out));
-                in[i] = out;
             }
+            const std::array<uintptr_t, 4> key = {(uintptr_t)in[0].c[0], (uintptr_t)in[0].c[3],
+                                                  (uintptr_t)out[0].c[0], (uintptr_t)out[0].c[3]};
+            auto it = rseen.find(key);
+            if (it == rseen.end()) {
+                it = rseen.emplace(key, (int64_t)rdesc.size()).first;
+                for (int64_t i = 0; i < m; ++i) rdesc.push_back(fwd_desc<T>(b, i, in[i], out[i]));
+            }
+            roff.push_back(it->second);
+            in = out;
+        }
     }
-    roff[nck] = (int64_t)rdesc.size() / m;
+    rl[nck] = (int64_t)roff.size();
     for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
         const int64_t s0 = k * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
-        aoff[k] = (int64_t)adesc.size() / m;
-        for (int64_t s = s1 - 1; s >= s0; --s)
-            for (int64_t i = 0; i < m; ++i) {
-                T *en[3];
-                for (int c = 0; c < 3; ++c)
-                    en[c] = (s == s0) ? W[i].ck(k).c[c] : W[i].segE((int)(k & 1), seg, s - s0, c);
-                adesc.push_back(adj_desc<T>(b, i, lcur[i], lnext[i], en));
-                std::swap(lcur[i], lnext[i]);
+        al[k] = (int64_t)aoff.size();
+        for (int64_t s = s1 - 1; s >= s0; --s) {
+            const T *e0 = (s == s0) ? W[0].ck(k).c[0] : W[0].segE((int)(k & 1), seg, s - s0, 0);
+            const std::array<uintptr_t, 4> key = {(uintptr_t)lcur[0].c[0], (uintptr_t)lnext[0].c[0],
+                                                  (uintptr_t)e0, 0};
+            auto it = aseen.find(key);
+            if (it == aseen.end()) {
+                it = aseen.emplace(key, (int64_t)adesc.size()).first;
+                for (int64_t i = 0; i < m; ++i) {
+                    T *en[3];
+                    for (int c = 0; c < 3; ++c)
+                        en[c] = (s == s0) ? W[i].ck(k).c[c] : W[i].segE((int)(k & 1), seg, s - s0, c);
+                    adesc.push_back(adj_desc<T>(b, i, lcur[i], lnext[i], en));
+                }
             }
+            aoff.push_back(it->second);
+            for (int64_t i = 0; i < m; ++i) std::swap(lcur[i], lnext[i]);
+        }
     }
+    // segments are reversed from the last, so segment k's adjoint launches end
+    // where segment k - 1's begin
+    auto aend = [&](int64_t k) { return k > 0 ? al[k - 1] : (int64_t)aoff.size(); };
     BoxDesc<T> *d_r = nullptr;
     AdjDesc<T> *d_a = nullptr;
     struct Free {
@@ -805,8 +871,6 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     if (rc) return rc;
     hipStream_t mainS = b->stream, aux = b->aux;
     BTRY(hipMemsetAsync(b->d_grad, 0, sizeof(double) * 12 * m, mainS), "hipMemsetAsync");
-    // events: [0] start, [1 + k] recompute of segment k done, [1 + nck + k]
-    // adjoint of segment k done
     struct Events {
         std::vector<hipEvent_t> ev;
         hipStream_t s[2];
@@ -818,7 +882,12 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
             for (hipEvent_t e : ev) hipEventDestroy(e);
         }
     } evs{{}, {mainS, aux}};
-    for (int64_t k = 0; k < 1 + 2 * nck; ++k) {
+    // event slots as in the single-box backward pass: [0] start, [1 + (k & 3)]
+    // recompute of segment k done, [5 + (k & 3)] adjoint of segment k done
+    // (each record is waited for before its slot is recorded again)
+    auto ev_rec = [&](int64_t k) { return evs.ev[(size_t)(1 + (k & 3))]; };
+    auto ev_adj = [&](int64_t k) { return evs.ev[(size_t)(5 + (k & 3))]; };
+    for (int k = 0; k < 9; ++k) {
         hipEvent_t e;
         BTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
         evs.ev.push_back(e);
@@ -826,12 +895,12 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     BTRY(hipEventRecord(evs.ev[0], mainS), "hipEventRecord");
     BTRY(hipStreamWaitEvent(aux, evs.ev[0], 0), "hipStreamWaitEvent");
     auto recompute = [&](int64_t k) -> int {
-        for (int64_t l = roff[k]; l < roff[k + 1]; ++l) {
-            hipError_t e = launch_batched<T>(d_r + l * m, b->d_items, b->nitems, 0, b->cfg.tile_x, b->cfg.tile_y,
-                                             grid_of(b), aux);
+        for (int64_t l = rl[k]; l < rl[k + 1]; ++l) {
+            hipError_t e = launch_batched<T>(d_r + roff[(size_t)l], b->d_items, b->nitems, 0, b->cfg.tile_x,
+                                             b->cfg.tile_y, grid_of(b), aux);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
         }
-        BTRY(hipEventRecord(evs.ev[(size_t)(1 + k)], aux), "hipEventRecord");
+        BTRY(hipEventRecord(ev_rec(k), aux), "hipEventRecord");
         return XFDTD_OK;
     };
     // adjoint grid: the tuned persistent size if one is set (and the adjoint
@@ -840,17 +909,16 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
                                                                                         : b->naitems;
     bool first = true;
     for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
-        if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, evs.ev[(size_t)(1 + k)], 0), "hipStreamWaitEvent");
-        const int64_t nl = (k > 0 ? aoff[k - 1] : (int64_t)adesc.size() / m) - aoff[k];
-        for (int64_t l = aoff[k]; l < aoff[k] + nl; ++l) {
-            hipError_t e = launch_batched_adjoint<T>(d_a + l * m, b->d_aitems, b->naitems, b->d_apart, first ? 0 : 1,
-                                                     b->atx, adj_tile(b), ga, mainS);
+        if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, ev_rec(k), 0), "hipStreamWaitEvent");
+        for (int64_t l = al[k]; l < aend(k); ++l) {
+            hipError_t e = launch_batched_adjoint<T>(d_a + aoff[(size_t)l], b->d_aitems, b->naitems, b->d_apart,
+                                                     first ? 0 : 1, b->atx, adj_tile(b), ga, mainS);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
             first = false;
         }
-        BTRY(hipEventRecord(evs.ev[(size_t)(1 + nck + k)], mainS), "hipEventRecord");
+        BTRY(hipEventRecord(ev_adj(k), mainS), "hipEventRecord");
         if (k >= 2) {  // segment k - 2 reuses this segment's E set
-            BTRY(hipStreamWaitEvent(aux, evs.ev[(size_t)(1 + nck + k)], 0), "hipStreamWaitEvent");
+            BTRY(hipStreamWaitEvent(aux, ev_adj(k), 0), "hipStreamWaitEvent");
             rc = recompute(k - 2);
             if (rc) return rc;
         }
@@ -951,42 +1019,46 @@ int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t
 
 int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)
 {
-    seg = bseg(n, seg);
-    int rc = check_bws(b, n, seg, ws, ws_bytes);
-    if (rc) return rc;
-    drop_tapes(b, ws, n, seg);
-    rc = b->dtype == XFDTD_F32 ? bgrad_forward_t<float>(b, n, seg, ws) : bgrad_forward_t<double>(b, n, seg, ws);
-    if (rc) return rc;
-    if (b->tapes.size() >= kMaxTapes) b->tapes.erase(b->tapes.begin());
-    xfdtd_batch_s::Tape t{{}, bws_arrays(n, seg), n, seg};
-    for (int64_t i = 0; i < b->m; ++i) t.ws.push_back((uintptr_t)ws[i]);
-    b->tapes.push_back(std::move(t));
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        seg = bseg(n, seg);
+        int rc = check_bws(b, n, seg, ws, ws_bytes);
+        if (rc) return rc;
+        drop_tapes(b, ws, n, seg);
+        rc = b->dtype == XFDTD_F32 ? bgrad_forward_t<float>(b, n, seg, ws) : bgrad_forward_t<double>(b, n, seg, ws);
+        if (rc) return rc;
+        if (b->tapes.size() >= kMaxTapes) b->tapes.erase(b->tapes.begin());
+        xfdtd_batch_s::Tape t{{}, bws_arrays(n, seg), n, seg};
+        for (int64_t i = 0; i < b->m; ++i) t.ws.push_back((uintptr_t)ws[i]);
+        b->tapes.push_back(std::move(t));
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes,
                               void *const *lam, double *grad)
 {
-    seg = bseg(n, seg);
-    if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if (!lam || !grad) return set_error(XFDTD_EINVAL, "null argument");
-    for (int64_t i = 0; i < 6 * b->m; ++i)
-        if (!lam[i]) return set_error(XFDTD_EINVAL, "lam[%lld] is null", (long long)i);
-    int rc = check_bws(b, n, seg, ws, ws_bytes, lam);
-    if (rc) return rc;
-    auto it = std::find_if(b->tapes.begin(), b->tapes.end(), [&](const xfdtd_batch_s::Tape &e) {
-        if (e.n != n || e.seg != seg) return false;
-        for (int64_t i = 0; i < b->m; ++i)
-            if (e.ws[i] != (uintptr_t)ws[i]) return false;
-        return true;
+    return guarded([&]() -> int {
+        seg = bseg(n, seg);
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if (!lam || !grad) return set_error(XFDTD_EINVAL, "null argument");
+        for (int64_t i = 0; i < 6 * b->m; ++i)
+            if (!lam[i]) return set_error(XFDTD_EINVAL, "lam[%lld] is null", (long long)i);
+        int rc = check_bws(b, n, seg, ws, ws_bytes, lam);
+        if (rc) return rc;
+        auto it = std::find_if(b->tapes.begin(), b->tapes.end(), [&](const xfdtd_batch_s::Tape &e) {
+            if (e.n != n || e.seg != seg) return false;
+            for (int64_t i = 0; i < b->m; ++i)
+                if (e.ws[i] != (uintptr_t)ws[i]) return false;
+            return true;
+        });
+        if (it == b->tapes.end())
+            return set_error(XFDTD_EINVAL, "the workspaces hold no forward pass of n = %lld, seg = %lld on this batch "
+                                           "(a backward pass consumes it; run xfdtd_batch_grad_forward again)",
+                             (long long)n, (long long)seg);
+        b->tapes.erase(it);
+        return b->dtype == XFDTD_F32 ? bgrad_backward_t<float>(b, n, seg, ws, lam, grad)
+                                     : bgrad_backward_t<double>(b, n, seg, ws, lam, grad);
     });
-    if (it == b->tapes.end())
-        return set_error(XFDTD_EINVAL, "the workspaces hold no forward pass of n = %lld, seg = %lld on this batch "
-                                       "(a backward pass consumes it; run xfdtd_batch_grad_forward again)",
-                         (long long)n, (long long)seg);
-    b->tapes.erase(it);
-    return b->dtype == XFDTD_F32 ? bgrad_backward_t<float>(b, n, seg, ws, lam, grad)
-                                 : bgrad_backward_t<double>(b, n, seg, ws, lam, grad);
 }
 
 }  // extern "C"

@@ -1018,17 +1018,20 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
         for (int c = 0; c < 3; ++c) f.c[c] = (T *)(ws + (size_t)(e + c) * fb);
         return f;
     };
-    // events: [0] start, [1 + m] recompute of segment m done, [1 + nck + m]
-    // adjoint of segment m done
+    // events: [0] start, [1 + (m & 3)] recompute of segment m done,
+    // [5 + (m & 3)] adjoint of segment m done.  A stream wait takes the
+    // event's latest record when it is issued, and each record below is
+    // waited for before its slot is recorded again (a recompute event two
+    // segments later, an adjoint event at once), so four slots of each suffice.
     EventSet evs;
     // on every return, the recompute stream has finished before the events go
     struct AuxDrain {
         hipStream_t s;
         ~AuxDrain() { hipStreamSynchronize(s); }
     } drain{aux};
-    HIP_TRY(evs.make((size_t)(1 + 2 * nck)), "hipEventCreate");
-    auto ev_rec = [&](int64_t m) { return evs.ev[(size_t)(1 + m)]; };
-    auto ev_adj = [&](int64_t m) { return evs.ev[(size_t)(1 + nck + m)]; };
+    HIP_TRY(evs.make(9), "hipEventCreate");
+    auto ev_rec = [&](int64_t m) { return evs.ev[(size_t)(1 + (m & 3))]; };
+    auto ev_adj = [&](int64_t m) { return evs.ev[(size_t)(5 + (m & 3))]; };
     HIP_TRY(hipEventRecord(evs.ev[0], mainS), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(aux, evs.ev[0], 0), "hipStreamWaitEvent");  // checkpoints are written
 
