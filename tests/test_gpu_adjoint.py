@@ -102,7 +102,7 @@ def _probe_grad_out(xp, tgt):
     return g
 
 
-@pytest.mark.parametrize("seg", [0, 1, 5, 13, 40])
+@pytest.mark.parametrize("seg", [0, 1, 2, 3, 5, 13, 40])
 def test_grad_schedule_matches_oracle_fp64(seg):
     shape = (12, 10, 70)
     n = 13
