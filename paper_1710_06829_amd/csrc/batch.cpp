@@ -247,20 +247,6 @@ std::string shape_key(const xfdtd_batch_t b)
     return k;
 }
 
-// Runs an entry point's body; host allocation failures (and any other C++
-// exception) become an error code instead of crossing the C interface.
-template <typename F>
-int guarded(F &&f)
-{
-    try {
-        return f();
-    } catch (const std::bad_alloc &) {
-        return set_error(XFDTD_EINVAL, "out of host memory");
-    } catch (const std::exception &e) {
-        return set_error(XFDTD_EINVAL, "%s", e.what());
-    }
-}
-
 }  // namespace
 
 extern "C" {
@@ -948,8 +934,12 @@ int check_bws(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const ui
 {
     if (!b) return set_error(XFDTD_EINVAL, "null handle");
     if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
-    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
+    if (n < 0 || n > ((int64_t)1 << 40)) return set_error(XFDTD_EINVAL, "n must be in [0, 2^40]");
+    if (seg > ((int64_t)1 << 40)) return set_error(XFDTD_EINVAL, "seg must be <= 2^40");
     if (!ws || !ws_bytes) return set_error(XFDTD_EINVAL, "null workspace list");
+    for (int64_t i = 0; i < b->m; ++i)
+        if ((double)bws_arrays(n, seg) * (double)box_field_bytes(b, i) >= 0x1p63)
+            return set_error(XFDTD_EINVAL, "box %lld: workspace size exceeds 2^63 bytes", (long long)i);
     const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int64_t i = 0; i < b->m; ++i) {
@@ -1010,11 +1000,17 @@ extern "C" {
 
 int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t *bytes)
 {
-    if (!b || !bytes) return set_error(XFDTD_EINVAL, "null argument");
-    if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
-    seg = bseg(n, seg);
-    for (int64_t i = 0; i < b->m; ++i) bytes[i] = bws_arrays(n, seg) * box_field_bytes(b, i);
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!b || !bytes) return set_error(XFDTD_EINVAL, "null argument");
+        if (n < 0 || n > ((int64_t)1 << 40)) return set_error(XFDTD_EINVAL, "n must be in [0, 2^40]");
+        if (seg > ((int64_t)1 << 40)) return set_error(XFDTD_EINVAL, "seg must be <= 2^40");
+        seg = bseg(n, seg);
+        for (int64_t i = 0; i < b->m; ++i)
+            if ((double)bws_arrays(n, seg) * (double)box_field_bytes(b, i) >= 0x1p63)
+                return set_error(XFDTD_EINVAL, "box %lld: workspace size exceeds 2^63 bytes", (long long)i);
+        for (int64_t i = 0; i < b->m; ++i) bytes[i] = bws_arrays(n, seg) * box_field_bytes(b, i);
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)

@@ -24,16 +24,15 @@ using namespace xfdtd;
 
 namespace {
 
-thread_local std::string g_err;
+// message of the last failure on this thread (fixed size: never allocates)
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -41,12 +40,10 @@ int fail(int code, const char *fmt, ...)
 
 int xfdtd::set_error(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -487,104 +484,111 @@ extern "C" {
 
 int xfdtd_abi_version(void) { return 2; }
 
-const char *xfdtd_last_error(void) { return g_err.c_str(); }
+const char *xfdtd_last_error(void) { return g_err; }
 
 int xfdtd_consistent_alpha(double coeffs[12])
 {
-    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
-    for (int a = 0; a < 3; ++a)
-        coeffs[4 * a] = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+        for (int a = 0; a < 3; ++a)
+            coeffs[4 * a] = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_cfl_limit(const xfdtd_grid *g, const double coeffs[12], double *dt_max, double *f_min,
                     double *f_max)
 {
-    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
-    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
-    const double sp[3] = {g->dx, g->dy, g->dz};
-    double lo, hi;
-    f_range(sp, coeffs, &lo, &hi);
-    if (f_min) *f_min = lo;
-    if (f_max) *f_max = hi;
-    if (!(hi > 0.0)) {
-        if (dt_max) *dt_max = INFINITY;
-        return fail(XFDTD_EUNSTABLE, "F_max = %g <= 0: no stable positive frequency range", hi);
-    }
-    if (dt_max) *dt_max = 1.0 / sqrt(hi);
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
+        if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+        const double sp[3] = {g->dx, g->dy, g->dz};
+        double lo, hi;
+        f_range(sp, coeffs, &lo, &hi);
+        if (f_min) *f_min = lo;
+        if (f_max) *f_max = hi;
+        if (!(hi > 0.0)) {
+            if (dt_max) *dt_max = INFINITY;
+            return fail(XFDTD_EUNSTABLE, "F_max = %g <= 0: no stable positive frequency range", hi);
+        }
+        if (dt_max) *dt_max = 1.0 / sqrt(hi);
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dtype,
                  int allow_unstable, xfdtd_t *out)
 {
-    if (!out) return fail(XFDTD_EINVAL, "out is null");
-    *out = nullptr;
-    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid (sizes >= 1, spacings > 0)");
-    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
-    if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
-    if (dtype != XFDTD_F32 && dtype != XFDTD_F64) return fail(XFDTD_EINVAL, "dtype must be XFDTD_F32 or XFDTD_F64");
-    const double sp[3] = {g->dx, g->dy, g->dz};
-    double lo, hi;
-    f_range(sp, coeffs, &lo, &hi);
-    if (!allow_unstable) {
-        const double tol = 1e-12 * fmax(1.0, fabs(hi));
-        if (lo < -tol) return fail(XFDTD_EUNSTABLE, "F_min = %.17g < 0: dispersion relation ill-defined", lo);
-        if (dt * dt * hi > 1.0 + 1e-12)
-            return fail(XFDTD_EUNSTABLE, "dt = %.17g exceeds the stability bound %.17g", dt, 1.0 / sqrt(hi));
-    }
-    xfdtd_s *h = new (std::nothrow) xfdtd_s();
-    if (!h) return fail(XFDTD_EINVAL, "out of host memory");
-    h->g = *g;
-    h->dt = dt;
-    memcpy(h->coeffs, coeffs, sizeof h->coeffs);
-    h->dtype = dtype;
-    h->flags = 0;
-    for (int a = 0; a < 3; ++a) {
-        const double al = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
-        if (fabs(al - coeffs[4 * a]) > 1e-12) h->flags |= XFDTD_WARN_ALPHA;
-    }
-    if (dtype == XFDTD_F32)
-        h->wf = fold<float>(*h, h->w);
-    else
-        h->wd = fold<double>(*h, h->w);
-    h->bound = false;
-    h->have_scratch = false;
-    h->stream = nullptr;
-    h->tile_x = pick_tile_x(*g);
-    const char *tx = getenv("XFDTD_TILE_X");
-    if (tx && (atoi(tx) == 32 || atoi(tx) == 64)) h->tile_x = atoi(tx);
-    h->tile_y = pick_tile_y(*g, h->tile_x, dtype);
-    const char *ty = getenv("XFDTD_TILE_Y");
-    if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
-    h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
-    // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
-    // fit in LDS), its own z-chunk for that tile height
-    h->atile_x = pick_tile_x(*g);
-    const char *atx = getenv("XFDTD_ADJ_TILE_X");
-    if (atx && (atoi(atx) == 32 || atoi(atx) == 64)) h->atile_x = atoi(atx);
-    h->atile_y = dtype == XFDTD_F64 && h->atile_x == 64 ? 4 : 8;
-    const char *aty = getenv("XFDTD_ADJ_TILE_Y");
-    if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && (dtype == XFDTD_F32 || h->atile_x == 32))))
-        h->atile_y = atoi(aty);
-    h->azchunk = auto_zchunk(*g, h->atile_x, h->atile_y, adjoint_slots(dtype, h->atile_x, h->atile_y));
-    if (getenv("XFDTD_ZCHUNK") && atoi(getenv("XFDTD_ZCHUNK")) > 0) h->azchunk = atoi(getenv("XFDTD_ZCHUNK"));
-    const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
-    if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
-    h->device = -1;
-    h->partials = nullptr;
-    h->npartials = 0;
-    h->apartials = nullptr;
-    h->napartials = 0;
-    h->grad_acc = nullptr;
-    h->aux = nullptr;
-    h->aux_device = -1;
-    *out = h;
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!out) return fail(XFDTD_EINVAL, "out is null");
+        *out = nullptr;
+        if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid (sizes >= 1, spacings > 0)");
+        if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+        if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
+        if (dtype != XFDTD_F32 && dtype != XFDTD_F64) return fail(XFDTD_EINVAL, "dtype must be XFDTD_F32 or XFDTD_F64");
+        const double sp[3] = {g->dx, g->dy, g->dz};
+        double lo, hi;
+        f_range(sp, coeffs, &lo, &hi);
+        if (!allow_unstable) {
+            const double tol = 1e-12 * fmax(1.0, fabs(hi));
+            if (lo < -tol) return fail(XFDTD_EUNSTABLE, "F_min = %.17g < 0: dispersion relation ill-defined", lo);
+            if (dt * dt * hi > 1.0 + 1e-12)
+                return fail(XFDTD_EUNSTABLE, "dt = %.17g exceeds the stability bound %.17g", dt, 1.0 / sqrt(hi));
+        }
+        xfdtd_s *h = new (std::nothrow) xfdtd_s();
+        if (!h) return fail(XFDTD_EINVAL, "out of host memory");
+        h->g = *g;
+        h->dt = dt;
+        memcpy(h->coeffs, coeffs, sizeof h->coeffs);
+        h->dtype = dtype;
+        h->flags = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double al = 1.0 - 2.0 * coeffs[4 * a + 1] - 2.0 * coeffs[4 * a + 2] - 3.0 * coeffs[4 * a + 3];
+            if (fabs(al - coeffs[4 * a]) > 1e-12) h->flags |= XFDTD_WARN_ALPHA;
+        }
+        if (dtype == XFDTD_F32)
+            h->wf = fold<float>(*h, h->w);
+        else
+            h->wd = fold<double>(*h, h->w);
+        h->bound = false;
+        h->have_scratch = false;
+        h->stream = nullptr;
+        h->tile_x = pick_tile_x(*g);
+        const char *tx = getenv("XFDTD_TILE_X");
+        if (tx && (atoi(tx) == 32 || atoi(tx) == 64)) h->tile_x = atoi(tx);
+        h->tile_y = pick_tile_y(*g, h->tile_x, dtype);
+        const char *ty = getenv("XFDTD_TILE_Y");
+        if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
+        h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
+        // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
+        // fit in LDS), its own z-chunk for that tile height
+        h->atile_x = pick_tile_x(*g);
+        const char *atx = getenv("XFDTD_ADJ_TILE_X");
+        if (atx && (atoi(atx) == 32 || atoi(atx) == 64)) h->atile_x = atoi(atx);
+        h->atile_y = dtype == XFDTD_F64 && h->atile_x == 64 ? 4 : 8;
+        const char *aty = getenv("XFDTD_ADJ_TILE_Y");
+        if (aty && (atoi(aty) == 4 || (atoi(aty) == 8 && (dtype == XFDTD_F32 || h->atile_x == 32))))
+            h->atile_y = atoi(aty);
+        h->azchunk = auto_zchunk(*g, h->atile_x, h->atile_y, adjoint_slots(dtype, h->atile_x, h->atile_y));
+        if (getenv("XFDTD_ZCHUNK") && atoi(getenv("XFDTD_ZCHUNK")) > 0) h->azchunk = atoi(getenv("XFDTD_ZCHUNK"));
+        const char *azc = getenv("XFDTD_ADJ_ZCHUNK");
+        if (azc && atoi(azc) > 0) h->azchunk = atoi(azc);
+        h->device = -1;
+        h->partials = nullptr;
+        h->npartials = 0;
+        h->apartials = nullptr;
+        h->napartials = 0;
+        h->grad_acc = nullptr;
+        h->aux = nullptr;
+        h->aux_device = -1;
+        *out = h;
+        return XFDTD_OK;
+    });
 }
 
 void xfdtd_destroy(xfdtd_t h)
 {
+    // nothing here allocates or throws
     if (!h) return;
     if (h->partials || h->apartials || h->grad_acc) hipStreamSynchronize(h->stream);
     if (h->aux) {
@@ -601,213 +605,235 @@ int xfdtd_flags(xfdtd_t h) { return h ? h->flags : 0; }
 
 int xfdtd_bind(xfdtd_t h, void *const fields[6], void *const scratch[6], void *stream)
 {
-    if (!h) return fail(XFDTD_EINVAL, "null handle");
-    if (!fields) return fail(XFDTD_EINVAL, "fields is null");
-    const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
-    const size_t bytes = (size_t)h->g.nx * h->g.ny * h->g.nz * esz;
-    void *all[12];
-    int nall = 0;
-    for (int c = 0; c < 6; ++c) {
-        if (!fields[c]) return fail(XFDTD_EINVAL, "fields[%d] is null", c);
-        if ((uintptr_t)fields[c] % 16) return fail(XFDTD_EINVAL, "fields[%d] not 16-byte aligned", c);
-        all[nall++] = fields[c];
-    }
-    if (scratch) {
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        if (!fields) return fail(XFDTD_EINVAL, "fields is null");
+        const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
+        const size_t bytes = (size_t)h->g.nx * h->g.ny * h->g.nz * esz;
+        void *all[12];
+        int nall = 0;
         for (int c = 0; c < 6; ++c) {
-            if (!scratch[c]) return fail(XFDTD_EINVAL, "scratch[%d] is null (pass scratch = NULL for none)", c);
-            if ((uintptr_t)scratch[c] % 16) return fail(XFDTD_EINVAL, "scratch[%d] not 16-byte aligned", c);
-            all[nall++] = scratch[c];
+            if (!fields[c]) return fail(XFDTD_EINVAL, "fields[%d] is null", c);
+            if ((uintptr_t)fields[c] % 16) return fail(XFDTD_EINVAL, "fields[%d] not 16-byte aligned", c);
+            all[nall++] = fields[c];
         }
-    }
-    for (int a = 0; a < nall; ++a)
-        for (int b = a + 1; b < nall; ++b) {
-            const uintptr_t pa = (uintptr_t)all[a], pb = (uintptr_t)all[b];
-            if (pa < pb + bytes && pb < pa + bytes) return fail(XFDTD_EINVAL, "bound arrays %d and %d overlap", a, b);
+        if (scratch) {
+            for (int c = 0; c < 6; ++c) {
+                if (!scratch[c]) return fail(XFDTD_EINVAL, "scratch[%d] is null (pass scratch = NULL for none)", c);
+                if ((uintptr_t)scratch[c] % 16) return fail(XFDTD_EINVAL, "scratch[%d] not 16-byte aligned", c);
+                all[nall++] = scratch[c];
+            }
         }
-    for (int c = 0; c < 6; ++c) {
-        h->fields[c] = fields[c];
-        h->scratch[c] = scratch ? scratch[c] : nullptr;
-    }
-    h->have_scratch = scratch != nullptr;
-    h->stream = (hipStream_t)stream;
-    h->bound = true;
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    h->device = dev;
-    return XFDTD_OK;
+        for (int a = 0; a < nall; ++a)
+            for (int b = a + 1; b < nall; ++b) {
+                const uintptr_t pa = (uintptr_t)all[a], pb = (uintptr_t)all[b];
+                if (pa < pb + bytes && pb < pa + bytes) return fail(XFDTD_EINVAL, "bound arrays %d and %d overlap", a, b);
+            }
+        for (int c = 0; c < 6; ++c) {
+            h->fields[c] = fields[c];
+            h->scratch[c] = scratch ? scratch[c] : nullptr;
+        }
+        h->have_scratch = scratch != nullptr;
+        h->stream = (hipStream_t)stream;
+        h->bound = true;
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        h->device = dev;
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_step_faraday(xfdtd_t h)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    const Dims d = dims_of(h->g);
-    if (h->dtype == XFDTD_F32)
-        HIP_TRY(launch_faraday<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "faraday launch");
-    else
-        HIP_TRY(launch_faraday<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "faraday launch");
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        const Dims d = dims_of(h->g);
+        if (h->dtype == XFDTD_F32)
+            HIP_TRY(launch_faraday<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "faraday launch");
+        else
+            HIP_TRY(launch_faraday<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "faraday launch");
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_step_ampere(xfdtd_t h)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    const Dims d = dims_of(h->g);
-    if (h->dtype == XFDTD_F32)
-        HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "ampere launch");
-    else
-        HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "ampere launch");
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        const Dims d = dims_of(h->g);
+        if (h->dtype == XFDTD_F32)
+            HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream), "ampere launch");
+        else
+            HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream), "ampere launch");
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3])
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    if (!J || !J[0] || !J[1] || !J[2]) return fail(XFDTD_EINVAL, "J must be three device arrays");
-    const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
-    for (int c = 0; c < 3; ++c) {
-        if ((uintptr_t)J[c] % esz) return fail(XFDTD_EINVAL, "J[%d] is misaligned", c);
-        for (int q = 0; q < 3; ++q)  // E is updated in place while J is read
-            if (ranges_overlap(J[c], raw_field_bytes(h), h->fields[q], raw_field_bytes(h)))
-                return fail(XFDTD_EINVAL, "J[%d] overlaps the bound E[%d]", c, q);
-    }
-    const Dims d = dims_of(h->g);
-    if (h->dtype == XFDTD_F32) {
-        const float *j[3] = {(const float *)J[0], (const float *)J[1], (const float *)J[2]};
-        HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream, j, (float)h->dt),
-                "ampere launch");
-    } else {
-        const double *j[3] = {(const double *)J[0], (const double *)J[1], (const double *)J[2]};
-        HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream, j, h->dt),
-                "ampere launch");
-    }
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        if (!J || !J[0] || !J[1] || !J[2]) return fail(XFDTD_EINVAL, "J must be three device arrays");
+        const size_t esz = h->dtype == XFDTD_F32 ? 4 : 8;
+        for (int c = 0; c < 3; ++c) {
+            if ((uintptr_t)J[c] % esz) return fail(XFDTD_EINVAL, "J[%d] is misaligned", c);
+            for (int q = 0; q < 3; ++q)  // E is updated in place while J is read
+                if (ranges_overlap(J[c], raw_field_bytes(h), h->fields[q], raw_field_bytes(h)))
+                    return fail(XFDTD_EINVAL, "J[%d] overlaps the bound E[%d]", c, q);
+        }
+        const Dims d = dims_of(h->g);
+        if (h->dtype == XFDTD_F32) {
+            const float *j[3] = {(const float *)J[0], (const float *)J[1], (const float *)J[2]};
+            HIP_TRY(launch_ampere<float>(as_fields<float>(h->fields), d, h->wf, h->stream, j, (float)h->dt),
+                    "ampere launch");
+        } else {
+            const double *j[3] = {(const double *)J[0], (const double *)J[1], (const double *)J[2]};
+            HIP_TRY(launch_ampere<double>(as_fields<double>(h->fields), d, h->wd, h->stream, j, h->dt),
+                    "ampere launch");
+        }
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_run(xfdtd_t h, int64_t n)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
-    return h->dtype == XFDTD_F32 ? run_t<float>(h, n) : run_t<double>(h, n);
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+        return h->dtype == XFDTD_F32 ? run_t<float>(h, n) : run_t<double>(h, n);
+    });
 }
 
 int xfdtd_tune(xfdtd_t h, int force, double *best_ms)
 {
-    const int rc = check_bound(h);
-    if (rc) return rc;
-    if (!h->have_scratch) return fail(XFDTD_ESTATE, "tuning times the fused step: bind scratch arrays");
-    if (!force) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(tune_key(h));
-        if (it != g_tune.end()) {
-            h->tile_x = it->second[0];
-            h->tile_y = it->second[1];
-            h->zchunk = it->second[2];
-            if (best_ms) *best_ms = -1.0;
-            return XFDTD_OK;
+    return guarded([&]() -> int {
+        const int rc = check_bound(h);
+        if (rc) return rc;
+        if (!h->have_scratch) return fail(XFDTD_ESTATE, "tuning times the fused step: bind scratch arrays");
+        if (!force) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(tune_key(h));
+            if (it != g_tune.end()) {
+                h->tile_x = it->second[0];
+                h->tile_y = it->second[1];
+                h->zchunk = it->second[2];
+                if (best_ms) *best_ms = -1.0;
+                return XFDTD_OK;
+            }
         }
-    }
-    return h->dtype == XFDTD_F32 ? tune_t<float>(h, best_ms) : tune_t<double>(h, best_ms);
+        return h->dtype == XFDTD_F32 ? tune_t<float>(h, best_ms) : tune_t<double>(h, best_ms);
+    });
 }
 
 int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *workgroups)
 {
-    if (!h) return fail(XFDTD_EINVAL, "null handle");
-    if (tile_x) *tile_x = h->tile_x;
-    if (tile_y) *tile_y = h->tile_y;
-    if (zchunk) *zchunk = h->zchunk;
-    if (workgroups) {
-        const int64_t ntx = (h->g.nx + h->tile_x - 1) / h->tile_x, nty = (h->g.ny + h->tile_y - 1) / h->tile_y;
-        const int64_t nzc = (h->g.nz + h->zchunk - 1) / h->zchunk;
-        *workgroups = (int)(ntx * nty * nzc);
-    }
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        if (tile_x) *tile_x = h->tile_x;
+        if (tile_y) *tile_y = h->tile_y;
+        if (zchunk) *zchunk = h->zchunk;
+        if (workgroups) {
+            const int64_t ntx = (h->g.nx + h->tile_x - 1) / h->tile_x, nty = (h->g.ny + h->tile_y - 1) / h->tile_y;
+            const int64_t nzc = (h->g.nz + h->zchunk - 1) / h->zchunk;
+            *workgroups = (int)(ntx * nty * nzc);
+        }
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw)
 {
-    if (!h || !w) return fail(XFDTD_EINVAL, "null argument");
-    memcpy(w, h->w, sizeof h->w);
-    if (nw) *nw = 15;
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!h || !w) return fail(XFDTD_EINVAL, "null argument");
+        memcpy(w, h->w, sizeof h->w);
+        if (nw) *nw = 15;
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_dispersion(const xfdtd_grid *g, double dt, const double coeffs[12], const double *k, int64_t n,
                      double *omega, double *vph, double *vg, void *stream)
 {
-    if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
-    if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
-    if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
-    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
-    if (n == 0) return XFDTD_OK;
-    if (!k || !omega) return fail(XFDTD_EINVAL, "k and omega must be device pointers");
-    if (n > ((int64_t)1 << 38)) return fail(XFDTD_EINVAL, "n too large");
-    hipStream_t s = (hipStream_t)stream;
-    const double sp[3] = {g->dx, g->dy, g->dz};
-    unsigned int *bad = nullptr;
-    HIP_TRY(hipMallocAsync((void **)&bad, sizeof(unsigned int), s), "hipMallocAsync");
-    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s), "hipMemsetAsync");
-    hipError_t e = launch_dispersion(k, n, dt, coeffs, sp, omega, vph, vg, bad, s);
-    unsigned int nbad = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFreeAsync(bad, s);
-    if (e != hipSuccess) return hip_fail(e, "dispersion");
-    if (nbad) return fail(XFDTD_EUNSTABLE, "%u wave vectors have dt^2 F outside [0, 1] (omega = NaN there)", nbad);
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!grid_ok(g)) return fail(XFDTD_EINVAL, "invalid grid");
+        if (!coeffs_ok(coeffs)) return fail(XFDTD_EINVAL, "coeffs must be 12 finite values");
+        if (!(dt > 0) || !isfinite(dt)) return fail(XFDTD_EINVAL, "dt must be finite and > 0");
+        if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+        if (n == 0) return XFDTD_OK;
+        if (!k || !omega) return fail(XFDTD_EINVAL, "k and omega must be device pointers");
+        if (n > ((int64_t)1 << 38)) return fail(XFDTD_EINVAL, "n too large");
+        hipStream_t s = (hipStream_t)stream;
+        const double sp[3] = {g->dx, g->dy, g->dz};
+        unsigned int *bad = nullptr;
+        HIP_TRY(hipMallocAsync((void **)&bad, sizeof(unsigned int), s), "hipMallocAsync");
+        HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), s), "hipMemsetAsync");
+        hipError_t e = launch_dispersion(k, n, dt, coeffs, sp, omega, vph, vg, bad, s);
+        unsigned int nbad = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFreeAsync(bad, s);
+        if (e != hipSuccess) return hip_fail(e, "dispersion");
+        if (nbad) return fail(XFDTD_EUNSTABLE, "%u wave vectors have dt^2 F outside [0, 1] (omega = NaN there)", nbad);
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_divergence(xfdtd_t h, void *div_star_b, void *div_e)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
-    const Dims d = dims_of(h->g);
-    if (h->dtype == XFDTD_F32)
-        HIP_TRY(launch_divergence<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (float *)div_star_b,
-                                         (float *)div_e, h->stream), "divergence launch");
-    else
-        HIP_TRY(launch_divergence<double>(as_fields<double>(h->fields), d, h->coeffs, sp, (double *)div_star_b,
-                                          (double *)div_e, h->stream), "divergence launch");
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
+        const Dims d = dims_of(h->g);
+        if (h->dtype == XFDTD_F32)
+            HIP_TRY(launch_divergence<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (float *)div_star_b,
+                                             (float *)div_e, h->stream), "divergence launch");
+        else
+            HIP_TRY(launch_divergence<double>(as_fields<double>(h->fields), d, h->coeffs, sp, (double *)div_star_b,
+                                              (double *)div_e, h->stream), "divergence launch");
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double out[3])
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    if (!out) return fail(XFDTD_EINVAL, "out is null");
-    const int nblocks = 1024;
-    if (!h->partials) {
-        HIP_TRY(hipMalloc((void **)&h->partials, sizeof(double) * 3 * nblocks), "hipMalloc");
-        h->npartials = nblocks;
-    }
-    const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
-    const Dims d = dims_of(h->g);
-    if (h->dtype == XFDTD_F32)
-        HIP_TRY(launch_divergence_max<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (const float *)ref_b,
-                                             (const float *)ref_e, h->partials, nblocks, h->stream),
-                "divergence_max launch");
-    else
-        HIP_TRY(launch_divergence_max<double>(as_fields<double>(h->fields), d, h->coeffs, sp,
-                                              (const double *)ref_b, (const double *)ref_e, h->partials,
-                                              nblocks, h->stream),
-                "divergence_max launch");
-    double host[3 * 1024];
-    HIP_TRY(hipMemcpyAsync(host, h->partials, sizeof(double) * 3 * nblocks, hipMemcpyDeviceToHost, h->stream),
-            "hipMemcpyAsync");
-    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    out[0] = out[1] = out[2] = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        out[0] = fmax(out[0], host[3 * b]);
-        out[1] = fmax(out[1], host[3 * b + 1]);
-        out[2] += host[3 * b + 2];
-    }
-    if (out[2] > 0) return fail(XFDTD_ENONFINITE, "%.0f non-finite field values", out[2]);
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        if (!out) return fail(XFDTD_EINVAL, "out is null");
+        const int nblocks = 1024;
+        if (!h->partials) {
+            HIP_TRY(hipMalloc((void **)&h->partials, sizeof(double) * 3 * nblocks), "hipMalloc");
+            h->npartials = nblocks;
+        }
+        const double sp[3] = {h->g.dx, h->g.dy, h->g.dz};
+        const Dims d = dims_of(h->g);
+        if (h->dtype == XFDTD_F32)
+            HIP_TRY(launch_divergence_max<float>(as_fields<float>(h->fields), d, h->coeffs, sp, (const float *)ref_b,
+                                                 (const float *)ref_e, h->partials, nblocks, h->stream),
+                    "divergence_max launch");
+        else
+            HIP_TRY(launch_divergence_max<double>(as_fields<double>(h->fields), d, h->coeffs, sp,
+                                                  (const double *)ref_b, (const double *)ref_e, h->partials,
+                                                  nblocks, h->stream),
+                    "divergence_max launch");
+        double host[3 * 1024];
+        HIP_TRY(hipMemcpyAsync(host, h->partials, sizeof(double) * 3 * nblocks, hipMemcpyDeviceToHost, h->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        out[0] = out[1] = out[2] = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            out[0] = fmax(out[0], host[3 * b]);
+            out[1] = fmax(out[1], host[3 * b + 1]);
+            out[2] += host[3 * b + 2];
+        }
+        if (out[2] > 0) return fail(XFDTD_ENONFINITE, "%.0f non-finite field values", out[2]);
+        return XFDTD_OK;
+    });
 }
 
 }  // extern "C"
@@ -1110,7 +1136,10 @@ void drop_tapes(xfdtd_t h, const void *ws, uint64_t bytes)
 
 int check_ws(xfdtd_t h, int64_t n, int64_t seg, const void *ws, uint64_t ws_bytes)
 {
-    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(XFDTD_EINVAL, "n must be in [0, 2^40]");
+    if (seg > ((int64_t)1 << 40)) return fail(XFDTD_EINVAL, "seg must be <= 2^40");
+    if ((double)ws_arrays(n, seg) * (double)field_bytes(h) >= 0x1p63)
+        return fail(XFDTD_EINVAL, "workspace size exceeds 2^63 bytes");
     if (!ws) return fail(XFDTD_EINVAL, "workspace is null");
     if ((uintptr_t)ws % 256) return fail(XFDTD_EINVAL, "workspace must be 256-byte aligned");
     const uint64_t need = ws_arrays(n, seg) * field_bytes(h);
@@ -1126,90 +1155,103 @@ extern "C" {
 int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6], const void *const e_n[3],
                        double *grad)
 {
-    if (!h) return fail(XFDTD_EINVAL, "null handle");
-    if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
-    for (int c = 0; c < 6; ++c)
-        if (!lam_in[c] || !lam_out[c]) return fail(XFDTD_EINVAL, "lambda array %d is null", c);
-    for (int c = 0; c < 3; ++c)
-        if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
-    // every output array must be disjoint from all inputs and the other outputs
-    const uint64_t bytes = raw_field_bytes(h);
-    auto overlap = [bytes](const void *a, const void *b) { return ranges_overlap(a, bytes, b, bytes); };
-    for (int c = 0; c < 6; ++c) {
-        for (int q = 0; q < 6; ++q)
-            if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
-                return fail(XFDTD_EINVAL, "lam_out[%d] overlaps another lambda array", c);
-        for (int q = 0; q < 3; ++q)
-            if (overlap(lam_out[c], e_n[q])) return fail(XFDTD_EINVAL, "lam_out[%d] overlaps e_n[%d]", c, q);
-    }
-    int rc = check_bound(h);
-    if (rc) return rc;
-    rc = ensure_adjoint_buffers(h);
-    if (rc) return rc;
-    if (h->dtype == XFDTD_F32) {
-        const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
-        return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1);
-    }
-    const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
-    return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
+        for (int c = 0; c < 6; ++c)
+            if (!lam_in[c] || !lam_out[c]) return fail(XFDTD_EINVAL, "lambda array %d is null", c);
+        for (int c = 0; c < 3; ++c)
+            if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
+        // every output array must be disjoint from all inputs and the other outputs
+        const uint64_t bytes = raw_field_bytes(h);
+        auto overlap = [bytes](const void *a, const void *b) { return ranges_overlap(a, bytes, b, bytes); };
+        for (int c = 0; c < 6; ++c) {
+            for (int q = 0; q < 6; ++q)
+                if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
+                    return fail(XFDTD_EINVAL, "lam_out[%d] overlaps another lambda array", c);
+            for (int q = 0; q < 3; ++q)
+                if (overlap(lam_out[c], e_n[q])) return fail(XFDTD_EINVAL, "lam_out[%d] overlaps e_n[%d]", c, q);
+        }
+        int rc = check_bound(h);
+        if (rc) return rc;
+        rc = ensure_adjoint_buffers(h);
+        if (rc) return rc;
+        if (h->dtype == XFDTD_F32) {
+            const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
+            return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1);
+        }
+        const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
+        return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
+    });
 }
 
 int xfdtd_grad_workspace(xfdtd_t h, int64_t n, int64_t seg, uint64_t *bytes)
 {
-    if (!h || !bytes) return fail(XFDTD_EINVAL, "null argument");
-    if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
-    seg = default_seg(n, seg);
-    *bytes = ws_arrays(n, seg) * field_bytes(h);
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!h || !bytes) return fail(XFDTD_EINVAL, "null argument");
+        if (n < 0 || n > ((int64_t)1 << 40)) return fail(XFDTD_EINVAL, "n must be in [0, 2^40]");
+        if (seg > ((int64_t)1 << 40)) return fail(XFDTD_EINVAL, "seg must be <= 2^40");
+        seg = default_seg(n, seg);
+        // 2^40 steps of a 2^35-byte field would overflow 64 bits
+        if ((double)ws_arrays(n, seg) * (double)field_bytes(h) >= 0x1p63)
+            return fail(XFDTD_EINVAL, "workspace size of n = %lld, seg = %lld exceeds 2^63 bytes", (long long)n,
+                        (long long)seg);
+        *bytes = ws_arrays(n, seg) * field_bytes(h);
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes)
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    seg = default_seg(n, seg);
-    rc = check_ws(h, n, seg, ws, ws_bytes);
-    if (rc) return rc;
-    const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h);
-    for (int c = 0; c < 6; ++c)
-        if (ranges_overlap(ws, wsb, h->fields[c], raw_field_bytes(h)))
-            return fail(XFDTD_EINVAL, "the workspace overlaps bound field %d", c);
-    drop_tapes(h, ws, wsb);
-    rc = h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
-                               : grad_forward_t<double>(h, n, seg, (char *)ws);
-    if (rc) return rc;
-    if (h->tapes.size() >= kMaxTapes) h->tapes.erase(h->tapes.begin());
-    h->tapes.push_back({(uintptr_t)ws, (uintptr_t)wsb, n, seg});
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        seg = default_seg(n, seg);
+        rc = check_ws(h, n, seg, ws, ws_bytes);
+        if (rc) return rc;
+        const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h);
+        for (int c = 0; c < 6; ++c)
+            if (ranges_overlap(ws, wsb, h->fields[c], raw_field_bytes(h)))
+                return fail(XFDTD_EINVAL, "the workspace overlaps bound field %d", c);
+        drop_tapes(h, ws, wsb);
+        rc = h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
+                                   : grad_forward_t<double>(h, n, seg, (char *)ws);
+        if (rc) return rc;
+        if (h->tapes.size() >= kMaxTapes) h->tapes.erase(h->tapes.begin());
+        h->tapes.push_back({(uintptr_t)ws, (uintptr_t)wsb, n, seg});
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_bytes, void *const lam[6],
                         double grad[12])
 {
-    int rc = check_bound(h);
-    if (rc) return rc;
-    if (!lam || !grad) return fail(XFDTD_EINVAL, "null argument");
-    for (int c = 0; c < 6; ++c)
-        if (!lam[c]) return fail(XFDTD_EINVAL, "lam[%d] is null", c);
-    seg = default_seg(n, seg);
-    rc = check_ws(h, n, seg, ws, ws_bytes);
-    if (rc) return rc;
-    const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h), fb = raw_field_bytes(h);
-    for (int c = 0; c < 6; ++c) {
-        if (ranges_overlap(ws, wsb, lam[c], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps the workspace", c);
-        for (int q = c + 1; q < 6; ++q)
-            if (ranges_overlap(lam[c], fb, lam[q], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps lam[%d]", c, q);
-    }
-    auto it = std::find_if(h->tapes.begin(), h->tapes.end(), [&](const xfdtd_s::Tape &e) {
-        return e.ws == (uintptr_t)ws && e.n == n && e.seg == seg;
+    return guarded([&]() -> int {
+        int rc = check_bound(h);
+        if (rc) return rc;
+        if (!lam || !grad) return fail(XFDTD_EINVAL, "null argument");
+        for (int c = 0; c < 6; ++c)
+            if (!lam[c]) return fail(XFDTD_EINVAL, "lam[%d] is null", c);
+        seg = default_seg(n, seg);
+        rc = check_ws(h, n, seg, ws, ws_bytes);
+        if (rc) return rc;
+        const uint64_t wsb = ws_arrays(n, seg) * field_bytes(h), fb = raw_field_bytes(h);
+        for (int c = 0; c < 6; ++c) {
+            if (ranges_overlap(ws, wsb, lam[c], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps the workspace", c);
+            for (int q = c + 1; q < 6; ++q)
+                if (ranges_overlap(lam[c], fb, lam[q], fb)) return fail(XFDTD_EINVAL, "lam[%d] overlaps lam[%d]", c, q);
+        }
+        auto it = std::find_if(h->tapes.begin(), h->tapes.end(), [&](const xfdtd_s::Tape &e) {
+            return e.ws == (uintptr_t)ws && e.n == n && e.seg == seg;
+        });
+        if (it == h->tapes.end())
+            return fail(XFDTD_EINVAL, "the workspace holds no forward pass of n = %lld, seg = %lld on this handle "
+                                      "(a backward pass consumes it; run xfdtd_grad_forward again)",
+                        (long long)n, (long long)seg);
+        h->tapes.erase(it);
+        return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
+                                     : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
     });
-    if (it == h->tapes.end())
-        return fail(XFDTD_EINVAL, "the workspace holds no forward pass of n = %lld, seg = %lld on this handle "
-                                  "(a backward pass consumes it; run xfdtd_grad_forward again)",
-                    (long long)n, (long long)seg);
-    h->tapes.erase(it);
-    return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
-                                 : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
 }
 
 }  // extern "C"

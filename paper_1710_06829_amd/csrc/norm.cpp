@@ -416,74 +416,78 @@ extern "C" {
 int xfdtd_dispersion_norm(const xfdtd_grid *g, double dt, const double coeffs[12], int dims, int64_t n,
                           int weight, double width, double *f, double grad[13], void *stream)
 {
-    if (!spacing_ok(g)) return set_error(XFDTD_EINVAL, "spacings must be finite and > 0");
-    if (!coeffs) return set_error(XFDTD_EINVAL, "coeffs is null");
-    for (int i = 0; i < 12; ++i)
-        if (!isfinite(coeffs[i])) return set_error(XFDTD_EINVAL, "coeffs must be 12 finite values");
-    if (!(dt > 0) || !isfinite(dt)) return set_error(XFDTD_EINVAL, "dt must be finite and > 0");
-    if (!f) return set_error(XFDTD_EINVAL, "f is null");
-    int rc = check_norm_args(dims, n, weight, width);
-    if (rc) return rc;
-    const int64_t total = dims == 2 ? n * n : n * n * n;
-    NormDev dev;
-    rc = dev.init(total, (hipStream_t)stream);
-    if (rc) return rc;
-    double o[14];
-    unsigned int nbad = 0;
-    rc = dev.eval(norm_args(g, dt, coeffs, dims, n, weight, width), o, &nbad);
-    if (rc) return rc;
-    if (nbad) {
-        *f = NAN;
-        return set_error(XFDTD_EUNSTABLE, "%u samples have dt^2 F outside (0, 1): omega undefined", nbad);
-    }
-    *f = o[0];
-    if (grad)
-        for (int i = 0; i < 13; ++i) grad[i] = o[1 + i];
-    return XFDTD_OK;
+    return guarded([&]() -> int {
+        if (!spacing_ok(g)) return set_error(XFDTD_EINVAL, "spacings must be finite and > 0");
+        if (!coeffs) return set_error(XFDTD_EINVAL, "coeffs is null");
+        for (int i = 0; i < 12; ++i)
+            if (!isfinite(coeffs[i])) return set_error(XFDTD_EINVAL, "coeffs must be 12 finite values");
+        if (!(dt > 0) || !isfinite(dt)) return set_error(XFDTD_EINVAL, "dt must be finite and > 0");
+        if (!f) return set_error(XFDTD_EINVAL, "f is null");
+        int rc = check_norm_args(dims, n, weight, width);
+        if (rc) return rc;
+        const int64_t total = dims == 2 ? n * n : n * n * n;
+        NormDev dev;
+        rc = dev.init(total, (hipStream_t)stream);
+        if (rc) return rc;
+        double o[14];
+        unsigned int nbad = 0;
+        rc = dev.eval(norm_args(g, dt, coeffs, dims, n, weight, width), o, &nbad);
+        if (rc) return rc;
+        if (nbad) {
+            *f = NAN;
+            return set_error(XFDTD_EUNSTABLE, "%u samples have dt^2 F outside (0, 1): omega undefined", nbad);
+        }
+        *f = o[0];
+        if (grad)
+            for (int i = 0; i < 13; ++i) grad[i] = o[1 + i];
+        return XFDTD_OK;
+    });
 }
 
 int xfdtd_optimize_stencil(const xfdtd_grid *g, const xfdtd_stencil_problem *p, double x_out[8],
                            double coeffs_out[12], double *dt_out, double *f_out, int *evals_out, void *stream)
 {
-    if (!spacing_ok(g)) return set_error(XFDTD_EINVAL, "spacings must be finite and > 0");
-    int rc = check_problem(p);
-    if (rc) return rc;
-    if (!x_out || !coeffs_out || !dt_out || !f_out) return set_error(XFDTD_EINVAL, "null output");
-    const int m = p->nparam;
-    const int64_t total = p->dims == 2 ? p->n * p->n : p->n * p->n * p->n;
-    NormDev dev;
-    rc = dev.init(total, (hipStream_t)stream);
-    if (rc) return rc;
-    Problem pr{g, p, &dev, m};
-    Eval best;
-    double zbest[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int nstart = 1;
-    for (int j = 0; j < m; ++j) nstart *= p->starts;
-    for (int s = 0; s < nstart; ++s) {
-        double z[8];
-        int r = s;
-        for (int j = 0; j < m; ++j) {
-            z[j] = (r % p->starts + 0.5) / p->starts;
-            r /= p->starts;
-        }
-        Eval cur;
-        rc = pr.evaluate(z, cur);
+    return guarded([&]() -> int {
+        if (!spacing_ok(g)) return set_error(XFDTD_EINVAL, "spacings must be finite and > 0");
+        int rc = check_problem(p);
         if (rc) return rc;
-        if (!cur.feasible) continue;
-        rc = pr.local(z, cur);
+        if (!x_out || !coeffs_out || !dt_out || !f_out) return set_error(XFDTD_EINVAL, "null output");
+        const int m = p->nparam;
+        const int64_t total = p->dims == 2 ? p->n * p->n : p->n * p->n * p->n;
+        NormDev dev;
+        rc = dev.init(total, (hipStream_t)stream);
         if (rc) return rc;
-        if (cur.f < best.f) {
-            best = cur;
-            for (int j = 0; j < m; ++j) zbest[j] = z[j];
+        Problem pr{g, p, &dev, m};
+        Eval best;
+        double zbest[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int nstart = 1;
+        for (int j = 0; j < m; ++j) nstart *= p->starts;
+        for (int s = 0; s < nstart; ++s) {
+            double z[8];
+            int r = s;
+            for (int j = 0; j < m; ++j) {
+                z[j] = (r % p->starts + 0.5) / p->starts;
+                r /= p->starts;
+            }
+            Eval cur;
+            rc = pr.evaluate(z, cur);
+            if (rc) return rc;
+            if (!cur.feasible) continue;
+            rc = pr.local(z, cur);
+            if (rc) return rc;
+            if (cur.f < best.f) {
+                best = cur;
+                for (int j = 0; j < m; ++j) zbest[j] = z[j];
+            }
         }
-    }
-    if (evals_out) *evals_out = pr.evals;
-    if (!best.feasible) return set_error(XFDTD_EUNSTABLE, "no stable starting point in the search box");
-    for (int j = 0; j < m; ++j) x_out[j] = p->lo[j] + zbest[j] * (p->hi[j] - p->lo[j]);
-    for (int i = 0; i < 12; ++i) coeffs_out[i] = best.c[i];
-    *dt_out = best.dt;
-    *f_out = best.f;
-    return XFDTD_OK;
+        if (evals_out) *evals_out = pr.evals;
+        if (!best.feasible) return set_error(XFDTD_EUNSTABLE, "no stable starting point in the search box");
+        for (int j = 0; j < m; ++j) x_out[j] = p->lo[j] + zbest[j] * (p->hi[j] - p->lo[j]);
+        for (int i = 0; i < 12; ++i) coeffs_out[i] = best.c[i];
+        *dt_out = best.dt;
+        *f_out = best.f;
+        return XFDTD_OK;
+    });
 }
 
 }  // extern "C"

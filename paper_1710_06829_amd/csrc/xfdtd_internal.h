@@ -5,6 +5,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <exception>
+#include <new>
+
+#include "../../include/xfdtd.h"
+
 namespace xfdtd {
 
 // Folded weights of one step, in the arithmetic type T.
@@ -181,7 +186,25 @@ Weights<T> fold_weights(double dt, const double *coeffs, const double sp[3], dou
     }
     return w;
 }
-// Record an error message (thread-local) and return code.
+// Record an error message (thread-local, in a fixed buffer: recording never
+// allocates or throws) and return code.
 int set_error(int code, const char *fmt, ...);
+
+// Runs the body of a C entry point: a C++ exception (a failed host
+// allocation in a std::vector or std::map, a std::system_error from a
+// mutex) becomes an error code instead of unwinding into the C caller.
+template <typename F>
+int guarded(F &&f) noexcept
+{
+    try {
+        return f();
+    } catch (const std::bad_alloc &) {
+        return set_error(XFDTD_EINVAL, "out of host memory");
+    } catch (const std::exception &e) {
+        return set_error(XFDTD_EINVAL, "%s", e.what());
+    } catch (...) {
+        return set_error(XFDTD_EINVAL, "unexpected C++ exception");
+    }
+}
 
 }  // namespace xfdtd

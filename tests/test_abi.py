@@ -361,3 +361,59 @@ def test_stencil_family_builds_the_affine_problem():
     assert p2.dt_mode == 1 and p2.dt_param == 1
     with pytest.raises(ValueError):
         fam2.dt_fraction(0.1, 1.0)
+
+
+def test_absurd_workspace_sizes_are_argument_errors():
+    # no 64-bit overflow of the workspace size and no exception: a plain
+    # XFDTD_EINVAL before any device call
+    rc, h = _create(shape=(1024, 1024, 256))
+    assert rc == 0
+    L = B.lib()
+    out = ctypes.c_uint64()
+    try:
+        for n, seg in [(1 << 62, 0), ((1 << 40) + 1, 0), (100, 1 << 50), (1 << 40, 1)]:
+            rc = L.xfdtd_grad_workspace(h, n, seg, ctypes.byref(out))
+            assert rc == -1, (n, seg, rc)
+            assert L.xfdtd_last_error()
+        assert L.xfdtd_grad_workspace(h, 200, 0, ctypes.byref(out)) == 0 and out.value > 0
+    finally:
+        L.xfdtd_destroy(h)
+
+
+_ALLOC_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_1710_06829_amd import _binding as B
+L = B.lib()
+m = 1 << 20
+grids = (B.Grid * m)()
+for i in range(0, m, 4096):
+    grids[i] = B.make_grid((4, 4, 4), (1, 1, 1))
+for i in range(m):
+    if i % 4096:
+        ctypes.memmove(ctypes.byref(grids, i * ctypes.sizeof(B.Grid)), ctypes.byref(grids, 0),
+                       ctypes.sizeof(B.Grid))
+dts = np.full(m, 0.3)
+coeffs = np.tile(np.array([1.0, 0, 0, 0] * 3), m)
+out = ctypes.c_void_p()
+# leave ~32 MB of address space: the batch's host vectors (~160 MB) cannot fit
+used = int(open("/proc/self/statm").read().split()[0]) * resource.getpagesize()
+resource.setrlimit(resource.RLIMIT_AS, (used + (32 << 20), resource.RLIM_INFINITY))
+rc = L.xfdtd_batch_create(grids, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m, B.XFDTD_F64, 1,
+                          ctypes.byref(out))
+print("rc", rc, L.xfdtd_last_error().decode())
+"""
+
+
+def test_host_allocation_failure_is_an_error_code_not_an_exception():
+    # A failed host allocation inside an entry point (here the per-box vectors
+    # of a 2^20-box batch under an address-space limit) must come back as
+    # XFDTD_EINVAL with a message; a C++ exception crossing the C interface
+    # would terminate the process instead.
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _ALLOC_CHILD, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "rc -1 out of host memory" in r.stdout, r.stdout + r.stderr[-2000:]
