@@ -72,6 +72,15 @@ def make_inputs(shape, dtype):
     return t, coeffs, dt, f
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count, from /proc/cpuinfo."""
+    try:
+        names = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")]
+    except OSError:
+        return "unknown"
+    return f"{names[0]} ({len(names)} logical CPUs visible)" if names else "unknown"
+
+
 def cpu_baseline(f64_fields, coeffs, dt, steps):
     """The FP64 C oracle, as it stands, on the full grid for `steps` steps."""
     import oracle
@@ -85,6 +94,7 @@ def cpu_baseline(f64_fields, coeffs, dt, steps):
         "value": cells * steps / el / 1e9,
         "unit": "Gcell-updates/s",
         "cores": threads,
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": f"{steps} FP64 steps of the full 512x256x256 pulse workload "
                   f"(plain C oracle, OpenMP, {el:.1f} s)",

@@ -150,8 +150,33 @@ int xfdtd_step_ampere(xfdtd_t h);
 int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3]);
 
 /* n >= 0 full steps (Faraday then Ampere each); the result is in the bound
- * fields when the queued work completes. */
+ * fields when the queued work completes.  With scratch arrays bound, FP32
+ * handles advance two steps per pass over the fields by default (see
+ * xfdtd_set_steps_per_pass). */
 int xfdtd_run(xfdtd_t h, int64_t n);
+
+/*
+ * Steps per pass of xfdtd_run (FP32 with scratch arrays bound):
+ *   1: one fused step per launch (reads and writes the state once per step:
+ *      48 B per cell-update in FP32);
+ *   2: two chained steps per launch (the leapfrog of App. A eq. update1-6
+ *      applied twice in one z-march: the state is read and written once per
+ *      two steps, 24 B per cell-update).  The second step's inputs are formed
+ *      on chip, redundantly on a 4-cell halo of each tile; every cell's
+ *      arithmetic is the one-step kernel's, so the results are bitwise the
+ *      same as with 1.
+ * Default 2 for FP32 (override with XFDTD_STEPS_PER_PASS=1 at xfdtd_create),
+ * 1 for FP64; xfdtd_tune chooses between them.  XFDTD_EINVAL for other values
+ * and for 2 on an FP64 handle.  Host only.
+ */
+int xfdtd_set_steps_per_pass(xfdtd_t h, int steps);
+
+/* Launch configuration of the two-step kernel for this handle, and the steps
+ * per pass xfdtd_run uses (1 or 2): tile width and height of its output tiles
+ * (32 x 8 or 32 x 16), z-planes per workgroup, workgroups per launch.  Any
+ * pointer may be NULL.  Host only. */
+int xfdtd_launch_config2(xfdtd_t h, int *steps_per_pass, int *tile_x, int *tile_y, int *zchunk,
+                         int *workgroups);
 
 /*
  * Folded weights actually used, as doubles exactly equal to the dtype values.
@@ -178,15 +203,17 @@ int xfdtd_get_weights(xfdtd_t h, double w[15], int *nw);
  * for every configuration. */
 int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *workgroups);
 
-/* Autotunes the fused step's launch configuration for this handle: times
- * tile widths 64 and 32, tile heights 8 and 16 (FP32; 4 and 8 for FP64) and a
- * few z-chunk lengths with steps that read the bound fields and write only the
- * scratch arrays (the state is unchanged), keeps the fastest and caches it
- * per (grid size, dtype, device); force = 1 re-times, otherwise a cached
- * choice is taken.  best_ms (nullable) receives the best time per step (-1
- * when taken from the cache).  Requires bound fields and scratch arrays
- * (XFDTD_ESTATE otherwise); synchronises the stream.  Results are bitwise
- * the same for every configuration. */
+/* Autotunes the launch configuration of xfdtd_run for this handle: times
+ * the fused step's tile widths 64 and 32, tile heights 8 and 16 (FP32; 4 and
+ * 8 for FP64) and, for FP32, the two-step kernel's 32 x 8 and 32 x 16 tiles,
+ * each with a few z-chunk lengths, with launches that read the bound fields
+ * and write only the scratch arrays (the state is unchanged); keeps the
+ * fastest per step (setting the steps per pass) and caches it per (grid size,
+ * dtype, device); force = 1 re-times, otherwise a cached choice is taken.
+ * best_ms (nullable) receives the best time per step (-1 when taken from the
+ * cache).  Requires bound fields and scratch arrays (XFDTD_ESTATE
+ * otherwise); synchronises the stream.  Results are bitwise the same for
+ * every configuration. */
 int xfdtd_tune(xfdtd_t h, int force, double *best_ms);
 
 /*

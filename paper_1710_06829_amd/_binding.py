@@ -64,6 +64,9 @@ SIGNATURES = {
     "xfdtd_tune": ([_vp, _int, _dp], _int),
     "xfdtd_launch_config": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                              ctypes.POINTER(_int)], _int),
+    "xfdtd_set_steps_per_pass": ([_vp, _int], _int),
+    "xfdtd_launch_config2": ([_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                              ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "xfdtd_dispersion": ([_GP, ctypes.c_double, _dp, _vp, _i64, _vp, _vp, _vp, _vp], _int),
     "xfdtd_dispersion_norm": ([_GP, ctypes.c_double, _dp, _int, _i64, _int, ctypes.c_double, _dp, _dp, _vp],
                               _int),

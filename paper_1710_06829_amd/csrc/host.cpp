@@ -224,7 +224,7 @@ int64_t adjoint_slots(int dtype, int tile_x, int tile_y)
 // 9 planes, 44.8 us per step, against 216 of 11 planes, 28.1 us).  Measured
 // on 512x256x256 with 64x16 tiles, one workgroup per CU: 128-plane chunks
 // (256 workgroups) beat 2048 chunks of 32 planes by 7 %.
-int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int64_t slots)
+int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int64_t slots, int warm = 3)
 {
     const int64_t ntx = (g.nx + tile_x - 1) / tile_x, nty = (g.ny + tile_y - 1) / tile_y;
     const int64_t tiles = ntx * nty, nz = g.nz;
@@ -238,7 +238,7 @@ int auto_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int64_t slots)
         if (z < 4 && z < nz) break;
         const int64_t chunks = (nz + z - 1) / z;
         const int64_t rounds = (tiles * chunks + slots - 1) / slots;
-        const double cost = (double)rounds * (double)(z + 3);
+        const double cost = (double)rounds * (double)(z + warm);
         if (cost < best) {
             best = cost;
             best_z = z;
@@ -279,6 +279,26 @@ int pick_tile_x(const xfdtd_grid &g)
     return c32 < c64 && g.nx <= 96 ? 32 : 64;
 }
 
+// Two-step kernel: workgroups resident per CU, and the default tiling.  Its
+// z-march needs 10 warm-up planes per chunk (each stage's 3 plus stage 2's lag
+// of 3 and one more plane of E^{n+1}).
+int64_t blocked2_slots(int tile_x, int tile_y)
+{
+    const int per = blocked2_occupancy<float>(tile_x, tile_y);
+    return (int64_t)device_cus() * (per > 0 ? per : 1);
+}
+
+int blocked2_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
+{
+    return auto_zchunk(g, tile_x, tile_y, blocked2_slots(tile_x, tile_y), 10);
+}
+
+// 32x16 tiles while their z-chunks stay long (>= 64 planes), 32x8 otherwise
+int pick_blocked2_tile_y(const xfdtd_grid &g)
+{
+    return blocked2_zchunk(g, 32, 16) >= 64 ? 16 : 8;
+}
+
 }  // namespace
 
 struct xfdtd_s {
@@ -296,6 +316,8 @@ struct xfdtd_s {
     bool have_scratch;
     hipStream_t stream;
     int tile_x, tile_y, zchunk;  // fused step
+    int spp;                     // steps per pass of xfdtd_run: 1 (fused step) or 2 (two-step kernel)
+    int btile_x, btile_y, bzchunk;  // two-step kernel
     int atile_x, atile_y, azchunk;  // adjoint step
     int device;
     double *partials;  // device, for reductions
@@ -372,6 +394,39 @@ int run_t(xfdtd_t h, int64_t n)
         return XFDTD_OK;
     }
     Fields<T> s = as_fields<T>(h->scratch);
+    if (h->spp == 2) {
+        // Two steps per launch.  Out-of-place launches alternate between the
+        // bound fields and the scratch arrays; their count is made even so
+        // that the result ends in the bound fields: an odd n starts with one
+        // in-place step (even number of two-step launches) or one fused step
+        // (odd number); an even n with an odd number of two-step launches
+        // does one of them as two fused steps.
+        Fields<T> a = f, b = s;
+        int64_t pairs = n / 2;
+        auto fused = [&]() -> int {
+            HIP_TRY(launch_fused<T>(a, b, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
+            std::swap(a, b);
+            return XFDTD_OK;
+        };
+        int rc = XFDTD_OK;
+        if ((n & 1) && pairs % 2 == 0) {
+            HIP_TRY(launch_faraday<T>(a, d, w, h->stream), "faraday launch");
+            HIP_TRY(launch_ampere<T>(a, d, w, h->stream), "ampere launch");
+        } else if (n & 1) {
+            rc = fused();
+        } else if (pairs % 2 == 1) {
+            rc = fused();
+            if (!rc) rc = fused();
+            --pairs;
+        }
+        if (rc) return rc;
+        for (int64_t i = 0; i < pairs; ++i) {
+            HIP_TRY(launch_blocked2<T>(a, b, d, w, h->btile_x, h->btile_y, h->bzchunk, h->stream),
+                    "two-step launch");
+            std::swap(a, b);
+        }
+        return XFDTD_OK;
+    }
     int64_t left = n;
     if (left & 1) {  // odd count: one in-place step keeps the result in `fields`
         HIP_TRY(launch_faraday<T>(f, d, w, h->stream), "faraday launch");
@@ -389,42 +444,53 @@ int run_t(xfdtd_t h, int64_t n)
 
 namespace {
 
-// Fused-step tilings chosen by xfdtd_tune, per (nx, ny, nz, dtype, device).
+// Tilings chosen by xfdtd_tune, per (nx, ny, nz, dtype, device): steps per
+// pass, then (tile_x, tile_y, zchunk) of the kernel that won.
 std::mutex g_tune_mu;
-std::map<std::array<int64_t, 5>, std::array<int, 3>> g_tune;
+std::map<std::array<int64_t, 5>, std::array<int, 4>> g_tune;
 
 std::array<int64_t, 5> tune_key(const xfdtd_s *h)
 {
     return {h->g.nx, h->g.ny, h->g.nz, (int64_t)h->dtype, (int64_t)h->device};
 }
 
-// Times each candidate tiling with fused steps fields -> scratch (the bound
-// state is only read) and keeps the fastest.
+// z-chunk lengths worth timing for a kernel whose chunks start with `warm`
+// warm-up planes: the cost model's choice, the whole depth and a few splits
+std::vector<int> zchunk_candidates(const xfdtd_grid &g, int model)
+{
+    const int64_t nz = g.nz;
+    const int64_t zs[7] = {model, nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
+    std::vector<int> out;
+    for (int64_t z : zs) {
+        if (z > nz) z = nz;
+        if (z < 1 || (z < 4 && z < nz)) continue;
+        if (std::find(out.begin(), out.end(), (int)z) == out.end()) out.push_back((int)z);
+    }
+    return out;
+}
+
+// Times each candidate with launches fields -> scratch (the bound state is
+// only read) and keeps the fastest per step: one-step tilings, and for FP32
+// the two-step kernel's tilings (two steps per launch).
 template <typename T>
 int tune_t(xfdtd_t h, double *best_ms)
 {
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
     const Fields<T> f = as_fields<T>(h->fields), s = as_fields<T>(h->scratch);
-    std::vector<std::array<int, 3>> cands;
+    std::vector<std::array<int, 4>> cands;  // steps per launch, tile_x, tile_y, zchunk
+    auto fits = [&](int tx, int ty, int z) {
+        return ((d.nx + tx - 1) / tx) * (int64_t)((d.ny + ty - 1) / ty) * ((h->g.nz + z - 1) / z) <= 0x7fffffff;
+    };
     const int tys[2] = {sizeof(T) == 4 ? 8 : 4, sizeof(T) == 4 ? 16 : 8};
     for (int tx : {64, 32})
-        for (int ty : tys) {
-            const int64_t nz = h->g.nz;
-            const int64_t zs[7] = {auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty)),
-                                   nz, (nz + 1) / 2, (nz + 3) / 4, (nz + 7) / 8, 16, 32};
-            std::vector<int> seen;
-            for (int64_t z : zs) {
-                if (z > nz) z = nz;
-                if (z < 1 || (z < 4 && z < nz)) continue;
-                bool dup = false;
-                for (int q : seen) dup = dup || q == (int)z;
-                if (dup) continue;
-                seen.push_back((int)z);
-                const int64_t nb = ((d.nx + tx - 1) / tx) * (int64_t)((d.ny + ty - 1) / ty) * ((nz + z - 1) / z);
-                if (nb <= 0x7fffffff) cands.push_back({tx, ty, (int)z});
-            }
-        }
+        for (int ty : tys)
+            for (int z : zchunk_candidates(h->g, auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty))))
+                if (fits(tx, ty, z)) cands.push_back({1, tx, ty, z});
+    if (sizeof(T) == 4)
+        for (int ty : {8, 16})
+            for (int z : zchunk_candidates(h->g, blocked2_zchunk(h->g, 32, ty)))
+                if (fits(32, ty, z)) cands.push_back({2, 32, ty, z});
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     hipError_t he = hipEventCreate(&e1);
@@ -443,7 +509,8 @@ int tune_t(xfdtd_t h, double *best_ms)
             auto timed = [&](int r, float *ms) {
                 hipError_t e = hipEventRecord(e0, h->stream);
                 for (int q = 0; q < r && e == hipSuccess; ++q)
-                    e = launch_fused<T>(f, s, d, w, c[0], c[1], c[2], h->stream);
+                    e = c[0] == 2 ? launch_blocked2<T>(f, s, d, w, c[1], c[2], c[3], h->stream)
+                                  : launch_fused<T>(f, s, d, w, c[1], c[2], c[3], h->stream);
                 if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -455,21 +522,29 @@ int tune_t(xfdtd_t h, double *best_ms)
                 reps[i] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
             }
             if (he == hipSuccess) he = timed(reps[i], &ms);
-            if (he == hipSuccess) per[i] = std::min(per[i], (double)ms / reps[i]);
+            if (he == hipSuccess) per[i] = std::min(per[i], (double)ms / reps[i] / c[0]);
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (he != hipSuccess) return hip_fail(he, "tuning launch");
     double best = INFINITY;
-    std::array<int, 3> bestc = {h->tile_x, h->tile_y, h->zchunk};
+    std::array<int, 4> bestc = {h->spp, 0, 0, 0};
     for (size_t i = 0; i < cands.size(); ++i)
         if (per[i] < best) {
             best = per[i];
             bestc = cands[i];
         }
-    if (he != hipSuccess) return hip_fail(he, "tuning launch");
-    h->tile_x = bestc[0];
-    h->tile_y = bestc[1];
-    h->zchunk = bestc[2];
+    if (bestc[1] == 0) return fail(XFDTD_EHIP, "no tiling could be timed");
+    h->spp = bestc[0];
+    if (bestc[0] == 2) {
+        h->btile_x = bestc[1];
+        h->btile_y = bestc[2];
+        h->bzchunk = bestc[3];
+    } else {
+        h->tile_x = bestc[1];
+        h->tile_y = bestc[2];
+        h->zchunk = bestc[3];
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[tune_key(h)] = bestc;
@@ -560,6 +635,21 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
         const char *ty = getenv("XFDTD_TILE_Y");
         if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
         h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
+    // two-step kernel (FP32): 32-column tiles; the default steps per pass
+    // can be overridden with XFDTD_STEPS_PER_PASS (1 or 2)
+    h->btile_x = 32;
+    h->btile_y = dtype == XFDTD_F32 ? pick_blocked2_tile_y(*g) : 8;
+    h->bzchunk = dtype == XFDTD_F32 ? blocked2_zchunk(*g, h->btile_x, h->btile_y) : 1;
+    h->spp = dtype == XFDTD_F32 ? 2 : 1;
+    const char *spp = getenv("XFDTD_STEPS_PER_PASS");
+    if (spp && atoi(spp) == 1) h->spp = 1;
+    const char *bty = getenv("XFDTD_BLK_TILE_Y");
+    if (dtype == XFDTD_F32 && bty && (atoi(bty) == 8 || atoi(bty) == 16)) {
+        h->btile_y = atoi(bty);
+        h->bzchunk = blocked2_zchunk(*g, h->btile_x, h->btile_y);
+    }
+    const char *bzc = getenv("XFDTD_BLK_ZCHUNK");
+    if (dtype == XFDTD_F32 && bzc && atoi(bzc) > 0) h->bzchunk = atoi(bzc);
         // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
         // fit in LDS), its own z-chunk for that tile height
         h->atile_x = pick_tile_x(*g);
@@ -718,9 +808,11 @@ int xfdtd_tune(xfdtd_t h, int force, double *best_ms)
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(tune_key(h));
             if (it != g_tune.end()) {
-                h->tile_x = it->second[0];
-                h->tile_y = it->second[1];
-                h->zchunk = it->second[2];
+                const std::array<int, 4> &c = it->second;
+                h->spp = c[0];
+                (c[0] == 2 ? h->btile_x : h->tile_x) = c[1];
+                (c[0] == 2 ? h->btile_y : h->tile_y) = c[2];
+                (c[0] == 2 ? h->bzchunk : h->zchunk) = c[3];
                 if (best_ms) *best_ms = -1.0;
                 return XFDTD_OK;
             }
@@ -740,6 +832,34 @@ int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *w
             const int64_t ntx = (h->g.nx + h->tile_x - 1) / h->tile_x, nty = (h->g.ny + h->tile_y - 1) / h->tile_y;
             const int64_t nzc = (h->g.nz + h->zchunk - 1) / h->zchunk;
             *workgroups = (int)(ntx * nty * nzc);
+        }
+        return XFDTD_OK;
+    });
+}
+
+int xfdtd_set_steps_per_pass(xfdtd_t h, int steps)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        if (steps != 1 && steps != 2) return fail(XFDTD_EINVAL, "steps per pass must be 1 or 2");
+        if (steps == 2 && h->dtype != XFDTD_F32) return fail(XFDTD_EINVAL, "the two-step kernel is FP32 only");
+        h->spp = steps;
+        return XFDTD_OK;
+    });
+}
+
+int xfdtd_launch_config2(xfdtd_t h, int *steps_per_pass, int *tile_x, int *tile_y, int *zchunk, int *workgroups)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        if (steps_per_pass) *steps_per_pass = h->spp;
+        if (tile_x) *tile_x = h->btile_x;
+        if (tile_y) *tile_y = h->btile_y;
+        if (zchunk) *zchunk = h->bzchunk;
+        if (workgroups) {
+            const int64_t ntx = (h->g.nx + h->btile_x - 1) / h->btile_x;
+            const int64_t nty = (h->g.ny + h->btile_y - 1) / h->btile_y;
+            *workgroups = (int)(ntx * nty * ((h->g.nz + h->bzchunk - 1) / h->bzchunk));
         }
         return XFDTD_OK;
     });

@@ -193,6 +193,62 @@ __global__ __launch_bounds__(256) void ampere_kernel(Fields<T> f, Dims d, Weight
 }
 
 // ---------------------------------------------------------------------------
+// per-position pieces of a step, shared by the one-step and two-step z-marches
+// (the same expression trees, so both round every cell's update the same way)
+// ---------------------------------------------------------------------------
+// The six forward differences g of plane k+1 at a position: z-differences
+// from the lane's own E(k+1) (e1) and E(k+2) (e2), x- and y-differences from
+// the staged plane E(k+1) (Ex1, Ey1, Ez1: LDS, row pitch PX, own index lg).
+template <int PX, typename T>
+__device__ __forceinline__ void form_g(T gn[6], const T e1[3], const T e2[3], const T *Ex1, const T *Ey1,
+                                       const T *Ez1, int lg)
+{
+    gn[0] = e2[1] - e1[1];          // g_z[Ey] -> Bx (+S_z)
+    gn[1] = Ez1[lg + PX] - e1[2];   // g_y[Ez] -> Bx (-S_y)
+    gn[2] = Ez1[lg + 1] - e1[2];    // g_x[Ez] -> By (+S_x)
+    gn[3] = e2[0] - e1[0];          // g_z[Ex] -> By (-S_z)
+    gn[4] = Ex1[lg + PX] - e1[0];   // g_y[Ex] -> Bz (+S_y)
+    gn[5] = Ey1[lg + 1] - e1[1];    // g_x[Ey] -> Bz (-S_x)
+}
+
+// Faraday update of a position: bn = bo + (star differences of g(k)); the
+// x/y neighbours of g(k) come from G (six LDS planes, row pitch PX, own index
+// l), its centre gc and z-neighbours gm = g(k-1), gn = g(k+1) from registers.
+template <int PX, int P, typename T>
+__device__ __forceinline__ void faraday_stars(T bn[3], const T bo[3], const T gm[6], const T gc[6],
+                                              const T gn[6], const T (*G)[P], int l, const Weights<T> &w)
+{
+    // star argument order: centre, along-axis pair, t1 pair, t2 pair
+    const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[0], gn[0], gm[0], G[0][l + 1], G[0][l - 1],
+                       G[0][l + PX], G[0][l - PX]);
+    const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[1], G[1][l + PX], G[1][l - PX], G[1][l + 1],
+                       G[1][l - 1], gn[1], gm[1]);
+    const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[2], G[2][l + 1], G[2][l - 1], G[2][l + PX],
+                       G[2][l - PX], gn[2], gm[2]);
+    const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[3], gn[3], gm[3], G[3][l + 1], G[3][l - 1],
+                       G[3][l + PX], G[3][l - PX]);
+    const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[4], G[4][l + PX], G[4][l - PX], G[4][l + 1],
+                       G[4][l - 1], gn[4], gm[4]);
+    const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[5], G[5][l + 1], G[5][l - 1], G[5][l + PX],
+                       G[5][l - PX], gn[5], gm[5]);
+    bn[0] = bo[0] + (sz0 - sy1);
+    bn[1] = bo[1] + (sx2 - sz3);
+    bn[2] = bo[2] + (sy4 - sx5);
+}
+
+// Ampere update of a position: E^{n+1}(k-1) from E^n(k-1) (ea), B^{n+1/2}(k-1)
+// (own value b1, x-1 / y-1 neighbours from Bp: three LDS planes, row pitch
+// PX) and the x, y components of B^{n+1/2}(k-2) (b2).
+template <int PX, int P, typename T>
+__device__ __forceinline__ void ampere3(T en[3], const T ea[3], const T b1[3], const T b2[2], const T (*Bp)[P],
+                                        int l, const Weights<T> &w)
+{
+    en[0] = ampere_eval(ea[0], w.wa[1], b1[2], Bp[2][l - PX], w.wa[2], b1[1], b2[1]);
+    en[1] = ampere_eval(ea[1], w.wa[2], b1[0], b2[0], w.wa[0], b1[2], Bp[2][l - 1]);
+    en[2] = ampere_eval(ea[2], w.wa[0], b1[1], Bp[1][l - 1], w.wa[1], b1[0], Bp[0][l - PX]);
+}
+
+// ---------------------------------------------------------------------------
 // fused step, z-march (see the file header)
 // ---------------------------------------------------------------------------
 // Tiling of the fused step: a workgroup of NW row waves plus one halo wave
@@ -372,14 +428,8 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
         T gn[R][6];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const T *Ex1 = Ebuf[eb][0], *Ey1 = Ebuf[eb][1], *Ez1 = Ebuf[eb][2];
             const int lg = isG[r] ? li[r] : 0;
-            gn[r][0] = e2[r][1] - e1[r][1];          // g_z[Ey] -> Bx (+S_z)
-            gn[r][1] = Ez1[lg + PX] - e1[r][2];      // g_y[Ez] -> Bx (-S_y)
-            gn[r][2] = Ez1[lg + 1] - e1[r][2];       // g_x[Ez] -> By (+S_x)
-            gn[r][3] = e2[r][0] - e1[r][0];          // g_z[Ex] -> By (-S_z)
-            gn[r][4] = Ex1[lg + PX] - e1[r][0];      // g_y[Ex] -> Bz (+S_y)
-            gn[r][5] = Ey1[lg + 1] - e1[r][1];       // g_x[Ey] -> Bz (-S_x)
+            form_g<PX>(gn[r], e1[r], e2[r], Ebuf[eb][0], Ebuf[eb][1], Ebuf[eb][2], lg);
             if (isG[r]) {
 #pragma unroll
                 for (int m = 0; m < 6; ++m) Gbuf[gb ^ 1][m][li[r]] = gn[r][m];
@@ -393,24 +443,8 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
         for (int r = 0; r < R; ++r) {
             bn[r][0] = bn[r][1] = bn[r][2] = T(0);
             if (isB[r] && doStar) {
-                const T(*G)[P] = Gbuf[gb];
                 const int l = li[r];
-                // star argument order: centre, along-axis pair, t1 pair, t2 pair
-                const T sz0 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[r][0], gn[r][0], gm[r][0],
-                                   G[0][l + 1], G[0][l - 1], G[0][l + PX], G[0][l - PX]);
-                const T sy1 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[r][1], G[1][l + PX],
-                                   G[1][l - PX], G[1][l + 1], G[1][l - 1], gn[r][1], gm[r][1]);
-                const T sx2 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[r][2], G[2][l + 1],
-                                   G[2][l - 1], G[2][l + PX], G[2][l - PX], gn[r][2], gm[r][2]);
-                const T sz3 = star(w.wc[2], w.wd[2], w.wb[2][0], w.wb[2][1], gc[r][3], gn[r][3], gm[r][3],
-                                   G[3][l + 1], G[3][l - 1], G[3][l + PX], G[3][l - PX]);
-                const T sy4 = star(w.wc[1], w.wd[1], w.wb[1][0], w.wb[1][1], gc[r][4], G[4][l + PX],
-                                   G[4][l - PX], G[4][l + 1], G[4][l - 1], gn[r][4], gm[r][4]);
-                const T sx5 = star(w.wc[0], w.wd[0], w.wb[0][0], w.wb[0][1], gc[r][5], G[5][l + 1],
-                                   G[5][l - 1], G[5][l + PX], G[5][l - PX], gn[r][5], gm[r][5]);
-                bn[r][0] = bo[r][0] + (sz0 - sy1);
-                bn[r][1] = bo[r][1] + (sx2 - sz3);
-                bn[r][2] = bo[r][2] + (sy4 - sx5);
+                faraday_stars<PX, P>(bn[r], bo[r], gm[r], gc[r], gn[r], Gbuf[gb], l, w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Bbuf[bb][c][l] = bn[r][c];
             }
@@ -423,14 +457,12 @@ __device__ __forceinline__ void fused_tile(const Fields<T> &in, const Fields<T> 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (!isO[r]) continue;
-                const int l = li[r];
-                const T ex = ampere_eval(ea[r][0], w.wa[1], b1[r][2], Bp[2][l - PX], w.wa[2], b1[r][1], b2[r][1]);
-                const T ey = ampere_eval(ea[r][1], w.wa[2], b1[r][0], b2[r][0], w.wa[0], b1[r][2], Bp[2][l - 1]);
-                const T ez = ampere_eval(ea[r][2], w.wa[0], b1[r][1], Bp[1][l - 1], w.wa[1], b1[r][0], Bp[0][l - PX]);
+                T en[3];
+                ampere3<PX, P>(en, ea[r], b1[r], b2[r], Bp, li[r], w);
                 const uint64_t pm = (uint64_t)(uint32_t)wm * nxy;
-                st_plane(dst[0] + pm, oc[r], ex);
-                st_plane(dst[1] + pm, oc[r], ey);
-                st_plane(dst[2] + pm, oc[r], ez);
+                st_plane(dst[0] + pm, oc[r], en[0]);
+                st_plane(dst[1] + pm, oc[r], en[1]);
+                st_plane(dst[2] + pm, oc[r], en[2]);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) st_plane(dst[3 + c] + pm, oc[r], b1[r][c]);
             }
@@ -508,6 +540,302 @@ __global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<
     }
 }
 
+// ---------------------------------------------------------------------------
+// two steps per pass: the fused z-march applied twice in one sweep
+// ---------------------------------------------------------------------------
+// (E^n, B^{n-1/2}) -> (E^{n+2}, B^{n+3/2}) with one read and one write of the
+// state per two steps (24 B FP32 per cell-update, half of the one-step
+// kernel's 48 B).  Stage 1 is the one-step march (iteration k forms g1(k+1),
+// B^{n+1/2}(k) and E^{n+1}(k-1)); stage 2 runs the same march on stage 1's
+// results three planes behind it (its iteration j = k - 3 forms g2(j+1) from
+// the E^{n+1}(k-1) stage 1 has just produced, B^{n+3/2}(j) from the
+// B^{n+1/2}(j) stage 1 produced three iterations earlier, and E^{n+2}(j-1)),
+// so stage 2 never waits for anything but registers and LDS.
+//
+// A workgroup owns a TX x TY output tile.  Two chained steps reach four cells
+// into the neighbouring tiles (each step two: the extended difference one cell
+// below and two above, Ampere one more below), so the workgroup covers the
+// (TX + 8) x (TY + 8) positions x, y in [-4, T + 4), laid out linearly (slot
+// s = threadIdx.x + r * THREADS is position (s mod PX, s / PX), LDS index s),
+// and evaluates each stage redundantly on the part of the halo the next stage
+// needs (regions below).  Every position computes the same per-cell
+// expressions as the one-step kernel, so the result is bitwise that of two
+// one-step launches.  LDS holds one plane of each staged quantity per stage
+// (E, the six g, B).  A plane iteration has two barriers: stage 1 reads its
+// planes while stage 2's planes of the previous iteration are written, and
+// after the first barrier stage 2 reads while stage 1's new planes are
+// written, so every LDS write overlaps the other stage's arithmetic.
+template <int TX_, int TY_, int R_, int NW_>
+struct Blk2Cfg {
+    static constexpr int TX = TX_, TY = TY_, R = R_, NW = NW_;
+    static constexpr int PX = TX + 8, PY = TY + 8, P = PX * PY;
+    static constexpr int THREADS = 64 * NW;
+    static_assert(R * THREADS >= P, "every position needs a slot");
+    static_assert(THREADS <= 1024, "workgroup size");
+};
+
+template <typename T, int P>
+struct Blk2Smem {
+    T E0[3][P];  // stage 1: E^n(k+1)
+    T G1[6][P];  // stage 1: g(k) of E^n
+    T B1[3][P];  // stage 1: B^{n+1/2}(k-1)
+    T E1[3][P];  // stage 2: E^{n+1}(j+1)
+    T G2[6][P];  // stage 2: g(j) of E^{n+1}
+    T B2[3][P];  // stage 2: B^{n+3/2}(j-1)
+};
+
+template <typename T, typename C>
+__device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
+                                              const Weights<T> &w, int zchunk, int ntx, int nty, int logical,
+                                              Blk2Smem<T, C::P> &sm)
+{
+    constexpr int R = C::R, PX = C::PX, P = C::P;
+    gptr<const T> src[6];
+    gptr<T> dst[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        src[c] = (gptr<const T>)in.c[c];
+        dst[c] = (gptr<T>)out.c[c];
+    }
+    const int tx = logical % ntx;
+    const int rest = logical / ntx;
+    const int ty = rest % nty;
+    const int zc = rest / nty;
+    const int x0 = tx * C::TX, y0 = ty * C::TY, k0 = zc * zchunk;
+    const int TXe = min(C::TX, d.nx - x0), TYe = min(C::TY, d.ny - y0);
+    const int KZe = min(zchunk, d.nz - k0);
+
+    // Regions (tile coordinates; TXe, TYe the tile's extent inside the box):
+    //   L1 E^n loaded, staged            [-4, T+4)   G1 g of E^n staged  [-4, T+3)
+    //   S1 B^{n+1/2} formed, staged      [-3, T+2)   A1 E^{n+1} formed   [-2, T+2)
+    //   G2 g of E^{n+1} staged           [-2, T+1)   S2 B^{n+3/2}        [-1, T)
+    //   O  E^{n+2} formed, both stored   [0, T)
+    // Each stage reads only inside the region the previous one filled.
+    bool inL1[R], inG1[R], inS1[R], inA1[R], inG2[R], inS2[R], inO[R];
+    bool inner[R];
+    int li[R], col[R], colb[R];
+    const uint32_t nxy = (uint32_t)d.nx * (uint32_t)d.ny;  // <= 2^28 (host check)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int sl = (int)threadIdx.x + r * C::THREADS;
+        const int rx = sl % PX - 4, ry = sl / PX - 4;
+        const bool v = sl < P && rx < TXe + 4 && ry < TYe + 4;
+        auto in_box = [&](int lo, int hx, int hy) { return v && rx >= lo && ry >= lo && rx < hx && ry < hy; };
+        inL1[r] = v;
+        inG1[r] = in_box(-4, TXe + 3, TYe + 3);
+        inS1[r] = in_box(-3, TXe + 2, TYe + 2);
+        inA1[r] = in_box(-2, TXe + 2, TYe + 2);
+        inG2[r] = in_box(-2, TXe + 1, TYe + 1);
+        inS2[r] = in_box(-1, TXe, TYe);
+        inO[r] = in_box(0, TXe, TYe);
+        // idle slots sit on an interior index, so that every neighbour index
+        // they form stays inside the planes (their values are never used)
+        li[r] = v ? sl : PX + 1;
+        // Phase A evaluates every stage at every position without branches
+        // (results outside a stage's region are never read), so the
+        // neighbour indices of the reads are clamped into the planes: g reads
+        // +1 and +PX (slot 0 outside the g regions), the stars and the Ampere
+        // update +-1 and +-PX (an interior slot on the outermost ring).
+        inner[r] = sl < P && rx >= -3 && ry >= -3 && rx <= C::TX + 2 && ry <= C::TY + 2;
+        // idle positions load column 0 (in bounds, value unused)
+        col[r] = v ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
+        // B^{n-1/2} is needed only where B^{n+1/2} is formed
+        colb[r] = inS1[r] ? col[r] : 0;
+    }
+    const int nz = d.nz;
+    auto inc = [nz](int v) { return v + 1 == nz ? 0 : v + 1; };
+
+    // Values a position keeps along z live in rings of four register slots:
+    // the value of plane p sits in slot (p - kbeg) & 3, kbeg = k0 - 5 being
+    // the first iteration, and no value is needed more than three planes
+    // after the next one arrives.  The loop is unrolled four times, so every
+    // slot index is a constant and slots keep their roles at the back-edge
+    // (no register moves to rotate queues).
+    //   stage 1: E^n at k-1 .. k+2 (E), g1 at k-1 .. k+1 (G), B^{n+1/2} at
+    //            k-3 .. k (B); prefetched E^n(k+2) and B^{n-1/2}(k) in two
+    //            alternating sets (pe, pb)
+    //   stage 2 (plane j = k - 3): E^{n+1} at j-1 .. j+2 (F), g2 at
+    //            j-1 .. j+1 (H), B^{n+3/2} at j-2 .. j (Cq)
+    T E[4][R][3], G[4][R][6], B[4][R][3], F[4][R][3], H[4][R][6], Cq[4][R][3], pe[2][R][3], pb[2][R][3];
+    // first iteration k = k0 - 5: E^n(k0-4) staged and in slot 1, E^n(k0-3)
+    // and B^{n-1/2}(k0-5) in the first prefetch set
+    int wE = wrap(k0 - 2, nz), wB = wrap(k0 - 5, nz), wm = wrap(k0 - 9, nz);
+    {
+        const uint64_t qa = (uint64_t)(uint32_t)wrap(k0 - 4, nz) * nxy;
+        const uint64_t qb = (uint64_t)(uint32_t)wrap(k0 - 3, nz) * nxy;
+        const uint64_t qc = (uint64_t)(uint32_t)wB * nxy;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) E[q][r][c] = B[q][r][c] = F[q][r][c] = Cq[q][r][c] = T(0);
+#pragma unroll
+                for (int m = 0; m < 6; ++m) G[q][r][m] = H[q][r][m] = T(0);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                E[1][r][c] = ld_plane(src[c] + qa, col[r]);
+                pe[0][r][c] = ld_plane(src[c] + qb, col[r]);
+                pb[0][r][c] = ld_plane(src[3 + c] + qc, colb[r]);
+            }
+            if (inL1[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sm.E0[c][li[r]] = E[1][r][c];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int klast = k0 + KZe - 1;
+    // One plane iteration, i = k - kbeg; I = i & 3 (a constant) picks the ring
+    // slots, I & 1 the prefetch set consumed (the other one is refilled).
+    auto plane = [&](auto slot, int k) {
+        constexpr int I = decltype(slot)::value;
+        constexpr int Q = I & 1;
+        constexpr int m1 = (I + 3) & 3, s0 = I, p1 = (I + 1) & 3, p2 = (I + 2) & 3;
+        // stage 1: E^n(k+2) and B^{n-1/2}(k) arrive
+        T bo[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                E[p2][r][c] = take(pe[Q][r][c]);
+                bo[r][c] = take(pb[Q][r][c]);
+            }
+        // lane offsets opaque to the compiler (scalar plane base + 32-bit
+        // lane offset per access, as in the one-step kernel)
+        uint32_t oc[R], ob[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            oc[r] = col[r];
+            ob[r] = colb[r];
+            asm("" : "+v"(oc[r]), "+v"(ob[r]));
+        }
+        {
+            const uint64_t pE = (uint64_t)(uint32_t)wE * nxy;
+            wB = inc(wB);
+            const uint64_t pB = (uint64_t)(uint32_t)wB * nxy;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pe[Q ^ 1][r][c] = ld_plane(src[c] + pE, oc[r]);
+                    pb[Q ^ 1][r][c] = ld_plane(src[3 + c] + pB, ob[r]);
+                }
+        }
+
+        // ---- phase 1: stage 2's planes of the previous iteration go to LDS;
+        // stage 1 reads its planes ----
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int l = li[r];
+            if (inA1[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sm.E1[c][l] = F[p2][r][c];  // E^{n+1}(j+1) = (k-2)
+            }
+            if (inG2[r]) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) sm.G2[m][l] = H[p1][r][m];  // g2(j) = (k-3)
+            }
+            if (inS2[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sm.B2[c][l] = Cq[s0][r][c];  // B^{n+3/2}(j-1) = (k-4)
+            }
+        }
+        // stage 1: g1(k+1), B^{n+1/2}(k), E^{n+1}(k-1)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int ls = inner[r] ? li[r] : PX + 1;
+            form_g<PX>(G[p1][r], E[p1][r], E[p2][r], sm.E0[0], sm.E0[1], sm.E0[2], inG1[r] ? li[r] : 0);
+            B[s0][r][0] = B[s0][r][1] = B[s0][r][2] = T(0);
+            if (inS1[r] && k >= k0 - 3)
+                faraday_stars<PX, P>(B[s0][r], bo[r], G[m1][r], G[s0][r], G[p1][r], sm.G1, ls, w);
+            ampere3<PX, P>(F[m1][r], E[m1][r], B[m1][r], B[p2][r], sm.B1, ls, w);
+        }
+        __syncthreads();
+
+        // ---- phase 2: stage 1's planes go to LDS; stage 2 reads its planes ----
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int l = li[r];
+            if (inL1[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sm.E0[c][l] = E[p2][r][c];  // E^n(k+2)
+            }
+            if (inG1[r]) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) sm.G1[m][l] = G[p1][r][m];  // g1(k+1)
+            }
+            if (inS1[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sm.B1[c][l] = B[s0][r][c];  // B^{n+1/2}(k)
+            }
+        }
+        // stage 2, plane j = k - 3: g2(j+1) from E^{n+1}(j+1) (staged, and
+        // slot p2) and E^{n+1}(j+2) (slot m1, just formed); B^{n+3/2}(j) from
+        // B^{n+1/2}(j) (slot p1); E^{n+2}(j-1) from E^{n+1}(j-1) (slot s0)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int ls = inner[r] ? li[r] : PX + 1;
+            form_g<PX>(H[p2][r], F[p2][r], F[m1][r], sm.E1[0], sm.E1[1], sm.E1[2], inG2[r] ? li[r] : 0);
+            Cq[p1][r][0] = Cq[p1][r][1] = Cq[p1][r][2] = T(0);
+            if (inS2[r] && k >= k0 + 2)
+                faraday_stars<PX, P>(Cq[p1][r], B[p1][r], H[s0][r], H[p1][r], H[p2][r], sm.G2, ls, w);
+        }
+        // outputs of plane j-1 = k-4: E^{n+2}(j-1) and B^{n+3/2}(j-1)
+        if (k >= k0 + 4 && k <= klast + 4) {
+            const uint64_t pm = (uint64_t)(uint32_t)wm * nxy;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!inO[r]) continue;
+                T ex[3];
+                ampere3<PX, P>(ex, F[s0][r], Cq[s0][r], Cq[m1][r], sm.B2, li[r], w);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) st_plane(dst[c] + pm, oc[r], ex[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) st_plane(dst[3 + c] + pm, oc[r], Cq[s0][r][c]);
+            }
+        }
+        __syncthreads();
+        wE = inc(wE);
+        wm = inc(wm);
+    };
+    // KZe + 10 iterations (k = k0 - 5 .. klast + 4), four per loop trip;
+    // up to three more whose results are unused
+    for (int k = k0 - 5; k <= klast + 4; k += 4) {
+        plane(std::integral_constant<int, 0>{}, k);
+        plane(std::integral_constant<int, 1>{}, k + 1);
+        plane(std::integral_constant<int, 2>{}, k + 2);
+        plane(std::integral_constant<int, 3>{}, k + 3);
+    }
+}
+
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void blocked2_kernel(Fields<T> in, Fields<T> out, Dims d, Weights<T> w,
+                                                              int zchunk, int ntx, int nty)
+{
+    __shared__ Blk2Smem<T, C::P> sm;
+    blocked2_tile<T, C>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
+}
+
+// Two-step tilings (FP32), one position per lane: 32x16 outputs on 40x24
+// positions (15 waves), 32x8 on 40x16 (10 waves, for small boxes).  With two
+// positions per lane (e.g. 32x24 on 40x32 in 10 waves) the two stages' register
+// queues exceed the 168 VGPRs of three waves per SIMD and spill.
+using Blk32x16 = Blk2Cfg<32, 16, 1, 15>;
+using Blk32x8 = Blk2Cfg<32, 8, 1, 10>;
+
+template <typename T, typename F>
+hipError_t with_blk2(int tile_x, int tile_y, F &&f)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (tile_x == 32 && tile_y == 16) return f(Blk32x16{});
+        if (tile_x == 32 && tile_y == 8) return f(Blk32x8{});
+    }
+    return hipErrorInvalidValue;
+}
+
 // 64-wide tiles of height 4 and 8 (one row per lane) and 16 (two rows per
 // lane); 32-wide tiles (two row groups per wave) of the same heights, for
 // boxes whose x extent is 32 modulo 64 or too small to fill the CUs.
@@ -583,6 +911,39 @@ hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const
 }
 
 template <typename T>
+hipError_t launch_blocked2(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
+                           int tile_y, int zchunk, hipStream_t s)
+{
+    if (tile_x <= 0 || tile_y <= 0 || zchunk <= 0) return hipErrorInvalidValue;
+    const int ntx = (d.nx + tile_x - 1) / tile_x;
+    const int nty = (d.ny + tile_y - 1) / tile_y;
+    const int nzc = (d.nz + zchunk - 1) / zchunk;
+    const int64_t nb = (int64_t)ntx * nty * nzc;
+    if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    return with_blk2<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((blocked2_kernel<T, C>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, in, out, d, w,
+                           zchunk, ntx, nty);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+int blocked2_occupancy(int tile_x, int tile_y)
+{
+    int n = 0;
+    const hipError_t e = with_blk2<T>(tile_x, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, blocked2_kernel<T, C>, C::THREADS, 0);
+    });
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+template <typename T>
 hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_x,
                           int tile_y, int grid, hipStream_t s)
 {
@@ -611,6 +972,12 @@ int fused_occupancy(int tile_x, int tile_y)
     return n;
 }
 
+template int blocked2_occupancy<float>(int, int);
+template int blocked2_occupancy<double>(int, int);
+template hipError_t launch_blocked2<float>(const Fields<float> &, const Fields<float> &, Dims,
+                                           const Weights<float> &, int, int, int, hipStream_t);
+template hipError_t launch_blocked2<double>(const Fields<double> &, const Fields<double> &, Dims,
+                                            const Weights<double> &, int, int, int, hipStream_t);
 template int fused_occupancy<float>(int, int);
 template int fused_occupancy<double>(int, int);
 template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, int, int, int, int, int,

@@ -71,6 +71,16 @@ template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
                         int tile_y, int zchunk, hipStream_t s);
 
+// Two fused steps in one launch from `in` to `out` (distinct buffers): the
+// same per-cell arithmetic, one pass over HBM.  FP32; tile_x x tile_y output
+// tiles 32x8 or 32x16, zchunk planes per workgroup (>= 1).
+// hipErrorInvalidValue for any other tiling or dtype.
+template <typename T>
+hipError_t launch_blocked2(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
+                           int tile_y, int zchunk, hipStream_t s);
+template <typename T>
+int blocked2_occupancy(int tile_x, int tile_y);
+
 // Workgroups of the fused step (tile_x x tile_y tiles) resident per CU on
 // the current device, from the HIP occupancy calculator; 0 if unknown (no
 // device, unsupported tile).

@@ -137,8 +137,13 @@ class Solver:
         self._bind()
         B.check(B.lib().xfdtd_run(self._h, int(n)))
 
+    def set_steps_per_pass(self, steps: int):
+        """1: one fused step per launch; 2: the two-step kernel (FP32).  The
+        results are bitwise the same."""
+        B.check(B.lib().xfdtd_set_steps_per_pass(self._h, int(steps)))
+
     def tune(self, force=False):
-        """Autotune the fused step's tiling for this box (needs scratch); the
+        """Autotune run()'s kernel and tiling for this box (needs scratch); the
         fields are left unchanged.  Returns the chosen launch_config()."""
         if self.scratch is None:
             raise ValueError("tuning needs scratch=True")
@@ -149,10 +154,17 @@ class Solver:
         return self.launch_config()
 
     def launch_config(self):
-        """{'tile_x', 'tile_y', 'zchunk', 'workgroups'} of the fused step for this box."""
+        """{'tile_x', 'tile_y', 'zchunk', 'workgroups'} of the fused step for
+        this box, 'steps_per_pass' of run() and 'two_step': the same keys for
+        the two-step kernel."""
         v = [ctypes.c_int() for _ in range(4)]
         B.check(B.lib().xfdtd_launch_config(self._h, *[ctypes.byref(x) for x in v]))
-        return {"tile_x": v[0].value, "tile_y": v[1].value, "zchunk": v[2].value, "workgroups": v[3].value}
+        u = [ctypes.c_int() for _ in range(5)]
+        B.check(B.lib().xfdtd_launch_config2(self._h, *[ctypes.byref(x) for x in u]))
+        return {"tile_x": v[0].value, "tile_y": v[1].value, "zchunk": v[2].value, "workgroups": v[3].value,
+                "steps_per_pass": u[0].value,
+                "two_step": {"tile_x": u[1].value, "tile_y": u[2].value, "zchunk": u[3].value,
+                             "workgroups": u[4].value}}
 
     def weights(self):
         w = (ctypes.c_double * 15)()

@@ -167,8 +167,9 @@ def test_autograd_propagate_fp64_24cube_pulse():
 
 def test_c4_fp32_gradients_vs_fp64_finite_differences():
     """128^3 FP32, 200 steps, sqrt(N) checkpoints: gradients w.r.t. the 12
-    coefficients and the initial E within 1e-4 of FP64 central differences
-    of the oracle (stored by tests/golden/make_c4_fd.py)."""
+    coefficients and the initial E (a seeded direction and 16 sampled
+    entries) within 1e-4 of FP64 central differences of the oracle (stored
+    by tests/golden/make_c4_fd.py)."""
     path = os.path.join(GOLD, "c4_fd.npz")
     if not os.path.exists(path):
         pytest.skip("c4_fd.npz not generated")
@@ -190,6 +191,14 @@ def test_c4_fp32_gradients_vs_fp64_finite_differences():
     gE = to_host([f.grad for f in fields[:3]])
     dE = sum(float(np.sum(gE[a] * u[a])) for a in range(3))
     assert abs(dE - float(ref["dir_e0"])) < 1e-4 * abs(float(ref["dir_e0"]))
+    # 16 sampled entries of dL/dE0 (8 in the pulse core, 8 uniform), relative
+    # to max(|fd|, 1e-3 max |fd|) over the sample
+    if "e0_grad" in ref:
+        fd_e = ref["e0_grad"]
+        got_e = np.array([gE[int(a)].reshape(-1)[int(i)] for a, i in zip(ref["e0_comp"], ref["e0_site"])])
+        rel_e = np.abs(got_e - fd_e) / np.maximum(np.abs(fd_e), 1e-3 * np.abs(fd_e).max())
+        print(f"c4 sampled dL/dE0: max rel err {rel_e.max():.2e}")
+        assert rel_e.max() < 1e-4, (rel_e, got_e, fd_e)
 
 
 def test_largest_plane_adjoint_identities_fp64():

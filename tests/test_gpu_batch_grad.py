@@ -31,7 +31,7 @@ def _boxes(seed):
     return out
 
 
-@pytest.mark.parametrize("n,seg", [(7, 0), (7, 3), (10, 2), (5, 1), (9, 9), (1, 0), (0, 0)])
+@pytest.mark.parametrize("n,seg", [(7, 0), (7, 3), (10, 2), (5, 1), (9, 9), (1, 0), (0, 0), (13, 1), (13, 2)])
 @pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 3), (4, 1, 0, 32)])
 def test_batch_grad_matches_oracle_fp64(n, seg, cfg):
     boxes = _boxes(900)
@@ -101,9 +101,9 @@ def test_batch_grad_rejects_bad_workspaces():
 
 def test_config5_16_boxes_96cube_300_steps_vs_finite_differences():
     """16 coefficient sets on 96^3 FP32 boxes, 300 steps, forward and adjoint
-    batched: each box's gradient along a seeded direction in coefficient space
-    within 1e-4 of FP64 central differences of the oracle (stored by
-    tests/golden/make_c5_fd.py)."""
+    batched: each box's gradient along two seeded directions in coefficient
+    space, and all 12 coefficients of four boxes, within 1e-4 of FP64 central
+    differences of the oracle (stored by tests/golden/make_c5_fd.py)."""
     path = os.path.join(GOLD, "c5_fd.npz")
     if not os.path.exists(path):
         pytest.skip("c5_fd.npz not generated")
@@ -122,11 +122,30 @@ def test_config5_16_boxes_96cube_300_steps_vs_finite_differences():
             lam[a][:, :, xp] = t[i][a][:, :, xp] - torch.from_numpy(tgt[a]).to(DEV, torch.float32)
         lams.append(lam)
     g = bt.grad_backward(n, ws, lams)
-    dd = ref["dir_deriv"]
-    scale = np.abs(dd).max()
-    for i in range(len(boxes)):
-        got = float(np.dot(g[i], ref["dirs"][i]))
-        assert abs(got - dd[i]) < 1e-4 * max(abs(dd[i]), 1e-2 * scale), (i, got, dd[i])
+    # Directional derivatives along two seeded unit directions per box.  A
+    # projection can cancel far below the size of the gradient, so the bar is
+    # 1e-4 relative to max(|fd|, 1e-3 |g|_2) (the per-entry floor of the
+    # gradient checks, applied to the projection's natural scale |g|_2).
+    worst = 0.0
+    for key_v, key_d in (("dirs", "dir_deriv"), ("dirs2", "dir_deriv2")):
+        if key_d not in ref:
+            continue
+        for i in range(len(boxes)):
+            gi = np.asarray(g[i])
+            got = float(np.dot(gi, ref[key_v][i]))
+            fd = float(ref[key_d][i])
+            rel = abs(got - fd) / max(abs(fd), 1e-3 * np.linalg.norm(gi))
+            worst = max(worst, rel)
+            assert rel < 1e-4, (key_d, i, got, fd, rel)
+    # every coefficient of four boxes, per entry against
+    # max(|fd|, 1e-3 max |fd|) of that box
+    if "full_grad" in ref:
+        for row, i in enumerate(ref["full_boxes"]):
+            fd = ref["full_grad"][row]
+            rel = np.abs(np.asarray(g[int(i)]) - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+            worst = max(worst, float(rel.max()))
+            assert rel.max() < 1e-4, (int(i), rel, np.asarray(g[int(i)]), fd)
+    print(f"c5 batched gradients: worst relative error {worst:.2e}")
 
 
 def test_batch_grad_rejects_aliased_lambda():

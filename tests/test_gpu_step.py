@@ -242,7 +242,7 @@ def test_fp32_tilings_agree_bitwise_and_match_oracle(env, shape):
     for tx in (64, 32):
         for ty in (4, 8, 16):
             for zc in (2, 7, 64):
-                env(XFDTD_TILE_X=tx, XFDTD_TILE_Y=ty, XFDTD_ZCHUNK=zc)
+                env(XFDTD_TILE_X=tx, XFDTD_TILE_Y=ty, XFDTD_ZCHUNK=zc, XFDTD_STEPS_PER_PASS=1)
                 t = to_dev(f0, torch.float32)
                 s = pkg.Solver(t, dt, c, spacing=sp)
                 assert s.launch_config()["tile_x"] == tx
@@ -253,6 +253,62 @@ def test_fp32_tilings_agree_bitwise_and_match_oracle(env, shape):
     ce, spe = _fp32.effective(c, dt, sp)
     exp = oracle.c_run(_fp32.round_fields(f0), 6, ce, dt, spe)
     assert rel_l2(outs[0], exp) < 1e-6
+
+
+TWO_STEP_SHAPES = [(37, 45, 150), (16, 33, 64), (3, 17, 5), (1, 1, 5), (2, 40, 33), (9, 1, 70), (1, 8, 1),
+                   (5, 16, 32), (64, 7, 2)]
+
+
+@pytest.mark.parametrize("shape", TWO_STEP_SHAPES)
+def test_two_step_kernel_bitwise_equals_one_step(env, shape):
+    """Two steps per launch (FP32): every tile height and z-chunking, and run
+    lengths that take each of the paths that keep the result in the bound
+    fields (odd and even counts of two-step launches, odd n), give bitwise
+    the result of one fused step per launch; that result matches the oracle
+    under the FP32 convention."""
+    c = _coeffs(481)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 482)
+    for n in (1, 2, 3, 4, 7, 8):
+        env(XFDTD_STEPS_PER_PASS=1)
+        ref = to_dev(f0, torch.float32)
+        s1 = pkg.Solver(ref, dt, c, spacing=sp)
+        assert s1.launch_config()["steps_per_pass"] == 1
+        s1.run(n)
+        ref = to_host(ref)
+        env(XFDTD_STEPS_PER_PASS=2)
+        for ty in (8, 16):
+            for zc in (1, 3, 7, 64) if n in (4, 7) else (64,):
+                env(XFDTD_BLK_TILE_Y=ty, XFDTD_BLK_ZCHUNK=zc)
+                t = to_dev(f0, torch.float32)
+                s = pkg.Solver(t, dt, c, spacing=sp)
+                lc = s.launch_config()
+                assert lc["steps_per_pass"] == 2 and lc["two_step"]["tile_y"] == ty
+                assert lc["two_step"]["zchunk"] == zc
+                s.run(n)
+                got = to_host(t)
+                assert all(np.array_equal(a, b) for a, b in zip(got, ref)), (n, ty, zc)
+        if n == 8:
+            ce, spe = _fp32.effective(c, dt, sp)
+            exp = oracle.c_run(_fp32.round_fields(f0), n, ce, dt, spe)
+            assert rel_l2(got, exp) < 1e-6
+
+
+def test_two_step_kernel_rejects_fp64_and_bad_counts():
+    shape = (6, 5, 7)
+    c = _coeffs(485)
+    dt = 0.9 * O.cfl_dt(c)
+    s = pkg.Solver(to_dev(S.uniform_fields(shape, 486)), dt, c)
+    assert s.launch_config()["steps_per_pass"] == 1
+    with pytest.raises(pkg.XfdtdError):
+        s.set_steps_per_pass(2)
+    s32 = pkg.Solver(to_dev(S.uniform_fields(shape, 486), torch.float32), dt, c)
+    for bad in (0, 3, -1):
+        with pytest.raises(pkg.XfdtdError):
+            s32.set_steps_per_pass(bad)
+    s32.set_steps_per_pass(1)
+    assert s32.launch_config()["steps_per_pass"] == 1
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
