@@ -570,7 +570,7 @@ struct Blk2Cfg {
     static constexpr int TX = TX_, TY = TY_, R = R_, NW = NW_;
     static constexpr int PX = TX + 8, PY = TY + 8, P = PX * PY;
     static constexpr int THREADS = 64 * NW;
-    static_assert(R * THREADS >= P, "every position needs a slot");
+    static_assert(R * THREADS == P, "one slot per position (every slot writes its own LDS index)");
     static_assert(THREADS <= 1024, "workgroup size");
 };
 
@@ -628,9 +628,10 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
         inG2[r] = in_box(-2, TXe + 1, TYe + 1);
         inS2[r] = in_box(-1, TXe, TYe);
         inO[r] = in_box(0, TXe, TYe);
-        // idle slots sit on an interior index, so that every neighbour index
-        // they form stays inside the planes (their values are never used)
-        li[r] = v ? sl : PX + 1;
+        // every slot is a position of the grid (static_assert in Blk2Cfg);
+        // positions past the tile's extent (ragged tiles) keep their own
+        // slots, which no position of the tile reads
+        li[r] = sl;
         // Phase A evaluates every stage at every position without branches
         // (results outside a stage's region are never read), so the
         // neighbour indices of the reads are clamped into the planes: g reads
@@ -726,22 +727,18 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
         }
 
         // ---- phase 1: stage 2's planes of the previous iteration go to LDS;
-        // stage 1 reads its planes ----
+        // stage 1 reads its planes.  Every position writes its own slot of
+        // every plane (slots outside a stage's region hold values nothing
+        // reads), so the writes need no branches. ----
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int l = li[r];
-            if (inA1[r]) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sm.E1[c][l] = F[p2][r][c];  // E^{n+1}(j+1) = (k-2)
-            }
-            if (inG2[r]) {
+            for (int c = 0; c < 3; ++c) sm.E1[c][l] = F[p2][r][c];  // E^{n+1}(j+1) = (k-2)
 #pragma unroll
-                for (int m = 0; m < 6; ++m) sm.G2[m][l] = H[p1][r][m];  // g2(j) = (k-3)
-            }
-            if (inS2[r]) {
+            for (int m = 0; m < 6; ++m) sm.G2[m][l] = H[p1][r][m];  // g2(j) = (k-3)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sm.B2[c][l] = Cq[s0][r][c];  // B^{n+3/2}(j-1) = (k-4)
-            }
+            for (int c = 0; c < 3; ++c) sm.B2[c][l] = Cq[s0][r][c];  // B^{n+3/2}(j-1) = (k-4)
         }
         // stage 1: g1(k+1), B^{n+1/2}(k), E^{n+1}(k-1)
 #pragma unroll
@@ -759,18 +756,12 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int l = li[r];
-            if (inL1[r]) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sm.E0[c][l] = E[p2][r][c];  // E^n(k+2)
-            }
-            if (inG1[r]) {
+            for (int c = 0; c < 3; ++c) sm.E0[c][l] = E[p2][r][c];  // E^n(k+2)
 #pragma unroll
-                for (int m = 0; m < 6; ++m) sm.G1[m][l] = G[p1][r][m];  // g1(k+1)
-            }
-            if (inS1[r]) {
+            for (int m = 0; m < 6; ++m) sm.G1[m][l] = G[p1][r][m];  // g1(k+1)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sm.B1[c][l] = B[s0][r][c];  // B^{n+1/2}(k)
-            }
+            for (int c = 0; c < 3; ++c) sm.B1[c][l] = B[s0][r][c];  // B^{n+1/2}(k)
         }
         // stage 2, plane j = k - 3: g2(j+1) from E^{n+1}(j+1) (staged, and
         // slot p2) and E^{n+1}(j+2) (slot m1, just formed); B^{n+3/2}(j) from
