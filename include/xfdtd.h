@@ -333,6 +333,24 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
                        const void *const e_n[3], double *grad);
 
 /*
+ * The adjoint step of xfdtd_adjoint_step for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc.  Same arguments, operation and
+ * results (bitwise) as xfdtd_adjoint_step; the per-workgroup FP64 gradient
+ * sums of the launch go to a static device array of the library (16384
+ * workgroups x 12 doubles = 1.5 MiB, one copy per GPU, held until the process
+ * ends) instead of a buffer the handle allocates on first use.  Each call
+ * overwrites the slots it uses, so nothing needs clearing between calls, but
+ * calls that overlap on one GPU (other streams, other threads, other
+ * handles) share that array and race: serialise them.  XFDTD_EINVAL when the
+ * handle's adjoint launch has more than 16384 workgroups or the current
+ * device is not the handle's.  Calls no hipMalloc or hipFree; the first call
+ * on a device looks up the array's device address.
+ */
+int xfdtd_adjoint_step_noalloc(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
+                               const void *const e_n[3], double *grad);
+
+/*
  * Checkpointed gradient of n steps.  The forward pass stores the state every
  * `seg` steps (seg <= 0 selects ceil(sqrt(2 n))) and the E fields of the last
  * two segments; the backward pass recomputes every earlier segment from its

@@ -75,6 +75,8 @@ SIGNATURES = {
     "xfdtd_divergence": ([_vp, _vp, _vp], _int),
     "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),
     "xfdtd_adjoint_step": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
+    "xfdtd_adjoint_step_noalloc": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+                                   _int),
     "xfdtd_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),
     "xfdtd_grad_forward": ([_vp, _i64, _i64, _vp, ctypes.c_uint64], _int),
     "xfdtd_grad_backward": ([_vp, _i64, _i64, _vp, ctypes.c_uint64, ctypes.POINTER(_vp), _dp], _int),

@@ -992,21 +992,69 @@ Scale12 grad_scale(const xfdtd_s *h)
 
 // One adjoint launch.  accumulate = 0 overwrites the per-workgroup gradient
 // sums, 1 adds to them; reduce != 0 then adds their scaled total to grad.
+// partials: the per-workgroup sums (default: the handle's buffer).
 template <typename T>
 int adjoint_one(xfdtd_t h, const Fields<T> &lin, const Fields<T> &lout, const T *const en[3], double *grad,
-                int accumulate, int reduce)
+                int accumulate, int reduce, double *partials = nullptr)
 {
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
     const int ty = adjoint_tile_y(h);
-    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, h->atile_x, ty, h->azchunk, h->apartials, accumulate,
-                              h->stream),
+    if (!partials) partials = h->apartials;
+    HIP_TRY(launch_adjoint<T>(lin, lout, en, d, w, h->atile_x, ty, h->azchunk, partials, accumulate, h->stream),
             "adjoint launch");
     if (reduce)
-        HIP_TRY(launch_reduce_partials(h->apartials, adjoint_blocks(d, h->atile_x, ty, h->azchunk), grad_scale(h),
-                                       grad, h->stream),
+        HIP_TRY(launch_reduce_partials(partials, adjoint_blocks(d, h->atile_x, ty, h->azchunk), grad_scale(h), grad,
+                                       h->stream),
                 "reduce launch");
     return XFDTD_OK;
+}
+
+// Static scratch of the allocation-free adjoint step: the per-workgroup FP64
+// gradient sums of one adjoint launch (at most kNoallocBlocks workgroups).
+// Each GPU holds its own copy until the process ends; its device address is
+// looked up once per device (with that device current) and kept in
+// g_scratch_ptr.  In host code the array's name is not a device address.
+constexpr int kNoallocBlocks = 16384;
+static __device__ __align__(256) double adj_scratch[kNoallocBlocks * 12];
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64];
+
+int noalloc_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= 64) return fail(XFDTD_EINVAL, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(adj_scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress of the static scratch");
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return XFDTD_OK;
+}
+
+// Argument checks shared by the adjoint step entry points (before any device work).
+int check_adjoint_args(xfdtd_t h, void *const lam_in[6], void *const lam_out[6], const void *const e_n[3],
+                       const double *grad)
+{
+    if (!h) return fail(XFDTD_EINVAL, "null handle");
+    if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
+    for (int c = 0; c < 6; ++c)
+        if (!lam_in[c] || !lam_out[c]) return fail(XFDTD_EINVAL, "lambda array %d is null", c);
+    for (int c = 0; c < 3; ++c)
+        if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
+    // every output array must be disjoint from all inputs and the other outputs
+    const uint64_t bytes = raw_field_bytes(h);
+    auto overlap = [bytes](const void *a, const void *b) { return ranges_overlap(a, bytes, b, bytes); };
+    for (int c = 0; c < 6; ++c) {
+        for (int q = 0; q < 6; ++q)
+            if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
+                return fail(XFDTD_EINVAL, "lam_out[%d] overlaps another lambda array", c);
+        for (int q = 0; q < 3; ++q)
+            if (overlap(lam_out[c], e_n[q])) return fail(XFDTD_EINVAL, "lam_out[%d] overlaps e_n[%d]", c, q);
+    }
+    return check_bound(h);
 }
 
 size_t field_bytes(const xfdtd_s *h)
@@ -1276,23 +1324,7 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
                        double *grad)
 {
     return guarded([&]() -> int {
-        if (!h) return fail(XFDTD_EINVAL, "null handle");
-        if (!lam_in || !lam_out || !e_n || !grad) return fail(XFDTD_EINVAL, "null argument");
-        for (int c = 0; c < 6; ++c)
-            if (!lam_in[c] || !lam_out[c]) return fail(XFDTD_EINVAL, "lambda array %d is null", c);
-        for (int c = 0; c < 3; ++c)
-            if (!e_n[c]) return fail(XFDTD_EINVAL, "e_n[%d] is null", c);
-        // every output array must be disjoint from all inputs and the other outputs
-        const uint64_t bytes = raw_field_bytes(h);
-        auto overlap = [bytes](const void *a, const void *b) { return ranges_overlap(a, bytes, b, bytes); };
-        for (int c = 0; c < 6; ++c) {
-            for (int q = 0; q < 6; ++q)
-                if (overlap(lam_out[c], lam_in[q]) || (q != c && overlap(lam_out[c], lam_out[q])))
-                    return fail(XFDTD_EINVAL, "lam_out[%d] overlaps another lambda array", c);
-            for (int q = 0; q < 3; ++q)
-                if (overlap(lam_out[c], e_n[q])) return fail(XFDTD_EINVAL, "lam_out[%d] overlaps e_n[%d]", c, q);
-        }
-        int rc = check_bound(h);
+        int rc = check_adjoint_args(h, lam_in, lam_out, e_n, grad);
         if (rc) return rc;
         rc = ensure_adjoint_buffers(h);
         if (rc) return rc;
@@ -1302,6 +1334,35 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
         }
         const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
         return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
+    });
+}
+
+int xfdtd_adjoint_step_noalloc(xfdtd_t h, void *const lam_in[6], void *const lam_out[6], const void *const e_n[3],
+                               double *grad)
+{
+    return guarded([&]() -> int {
+        int rc = check_adjoint_args(h, lam_in, lam_out, e_n, grad);
+        if (rc) return rc;
+        const int nb = adjoint_blocks(dims_of(h->g), h->atile_x, adjoint_tile_y(h), h->azchunk);
+        if (nb > kNoallocBlocks)
+            return fail(XFDTD_EINVAL,
+                        "the adjoint launch of this grid has %d workgroups; the allocation-free step holds "
+                        "the sums of at most %d (use xfdtd_adjoint_step)", nb, kNoallocBlocks);
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        if (dev != h->device)
+            return fail(XFDTD_EINVAL, "the current device (%d) is not the handle's (%d)", dev, h->device);
+        double *ws = nullptr;
+        rc = noalloc_scratch(dev, &ws);
+        if (rc) return rc;
+        // the adjoint kernel overwrites the slot of every workgroup it runs
+        // (nothing in the scratch needs to start at zero)
+        if (h->dtype == XFDTD_F32) {
+            const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
+            return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1, ws);
+        }
+        const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
+        return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1, ws);
     });
 }
 
