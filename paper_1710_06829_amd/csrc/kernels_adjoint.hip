@@ -159,19 +159,28 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         dst[c] = (gptr_a<T>)lout.c[c];
     }
 
-    // own-column queues: la = lE'(k-1), l0 = lE'(k), l1 = lE'(k+1);
-    // mm, mc = mu(k-1), mu(k); sp0/sp3 and sq0/sq3 = stars 0 and 3 at k-1 and
-    // k-2; n0 = E(k), staged in LDS for the x+1 and y+1 neighbours that the
-    // gradient needs.  Prefetched values (lE'(k+2), lB'(k+1), E(k+1))
-    // alternate between two register sets, so a load issued in one iteration
-    // is first waited for in the next (a single rotating set would make the
-    // compiler wait for it at the loop back-edge, with the iteration's stores).
-    T la[3], l0[3], l1[3], n0[3];
+    // Values a lane keeps along z live in rings of four register slots: the
+    // value of plane p sits in slot (p - kbeg) & 3, kbeg = k0 - 3 being the
+    // first iteration; the loop is unrolled four times so that every slot
+    // index is a constant and slots keep their roles from one loop trip to
+    // the next (no register moves to rotate queues).
+    //   LE: lE' at k-1 .. k+2;  MU: mu at k-1 .. k+1;  EN: primal E at k, k+1
+    //   (staged in LDS for the x+1 and y+1 neighbours the gradient needs);
+    //   S0, S3: stars 0 and 3 of mu at k-2 .. k.
+    // Prefetched values (lE'(k+2), lB'(k+1), E(k+1)) alternate between two
+    // register sets, so a load issued in one iteration is first waited for in
+    // the next.
+    T LE[4][3], MU[4][3], EN[4][3], S0[4], S3[4];
     T pe[2][3], pb[2][3], pn[2][3];
-    T mm[3], mc[3], sp0 = T(0), sp3 = T(0), sq0 = T(0), sq3 = T(0);
     double acc[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) LE[q][c] = MU[q][c] = EN[q][c] = T(0);
+        S0[q] = S3[q] = T(0);
+    }
 
     // plane trackers (k starts at k0 - 3): w3 = k+3 (lE' prefetch),
     // wb = k+1 -> k+2 (lB' prefetch), wn = k+1 -> k+2 (primal E prefetch),
@@ -182,36 +191,37 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         const uint64_t pm = (uint64_t)(uint32_t)wrapa(k0 - 3, nz) * nxy;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l1[c] = src[c][pa + col];
-            pe[0][c] = src[c][pq + col];
+            LE[1][c] = src[c][pa + col];    // lE'(kbeg + 1)
+            pe[0][c] = src[c][pq + col];    // lE'(kbeg + 2)
             pb[0][c] = src[3 + c][pa + colb];
             pn[0][c] = en[c][pa + coln];
-            n0[c] = en[c][pm + coln];
+            EN[0][c] = en[c][pm + coln];    // E(kbeg)
         }
         if (isE) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                LEbuf[0][c][li] = l1[c];
-                Ebuf[0][c][li] = n0[c];
+                LEbuf[0][c][li] = LE[1][c];
+                Ebuf[0][c][li] = EN[0][c];
             }
         }
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) la[c] = l0[c] = mm[c] = mc[c] = T(0);
     __syncthreads();
 
     const int klast = k0 + KZe - 1;
-    // One plane iteration.  B = k & 1 relative to k0 - 3: LDS buffer parity
-    // and prefetch register set (set B is consumed, set B^1 refilled).
-    auto plane = [&](auto parity, int k) {
-        constexpr int B = decltype(parity)::value;
+    // One plane iteration, i = k - kbeg; I = i & 3 picks the ring slots,
+    // B = I & 1 the LDS buffers and the prefetch set consumed (set B^1 is
+    // refilled).
+    auto plane = [&](auto slot, int k) {
+        constexpr int I = decltype(slot)::value;
+        constexpr int B = I & 1;
         constexpr int eb = B, mb = B, sb = B;
-        T l2[3], bo[3], n1[3];
+        constexpr int m1 = (I + 3) & 3, s0 = I, p1 = (I + 1) & 3, p2 = (I + 2) & 3;
+        T bo[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l2[c] = pe[B][c];  // lE'(k+2)
-            bo[c] = pb[B][c];  // lB'(k+1)
-            n1[c] = pn[B][c];  // E(k+1)
+            LE[p2][c] = pe[B][c];  // lE'(k+2)
+            bo[c] = pb[B][c];      // lB'(k+1)
+            EN[p1][c] = pn[B][c];  // E(k+1)
         }
         // per-iteration copies of the lane offsets, opaque to the compiler, so
         // that addresses stay scalar plane base + 32-bit lane offset (no
@@ -233,30 +243,31 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         if (isE) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                LEbuf[eb ^ 1][c][li] = l2[c];
-                Ebuf[eb ^ 1][c][li] = n1[c];
+                LEbuf[eb ^ 1][c][li] = LE[p2][c];
+                Ebuf[eb ^ 1][c][li] = EN[p1][c];
             }
         }
 
         // mu(k+1) = lB'(k+1) + L^T lE' (lanes outside the mu region read the
         // neighbours of slot 0: in bounds, value unused)
-        T mn[3];
         {
             const int lg = isG ? li : 0;
             const T *Lx = LEbuf[eb][0], *Ly = LEbuf[eb][1], *Lz = LEbuf[eb][2];
+            const T *l1 = LE[p1], *l2 = LE[p2];
             const T fzy = l2[1] - l1[1], fzx = l2[0] - l1[0];
             const T fyz = Lz[lg + PX] - l1[2], fyx = Lx[lg + PX] - l1[0];
             const T fxz = Lz[lg + 1] - l1[2], fxy = Ly[lg + 1] - l1[1];
-            mn[0] = bo[0] + (w.wa[1] * fyz - w.wa[2] * fzy);
-            mn[1] = bo[1] + (w.wa[2] * fzx - w.wa[0] * fxz);
-            mn[2] = bo[2] + (w.wa[0] * fxy - w.wa[1] * fyx);
+            MU[p1][0] = bo[0] + (w.wa[1] * fyz - w.wa[2] * fzy);
+            MU[p1][1] = bo[1] + (w.wa[2] * fzx - w.wa[0] * fxz);
+            MU[p1][2] = bo[2] + (w.wa[0] * fxy - w.wa[1] * fyx);
         }
         if (isG) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Mbuf[mb ^ 1][c][li] = mn[c];
+            for (int c = 0; c < 3; ++c) Mbuf[mb ^ 1][c][li] = MU[p1][c];
         }
 
         // stars of mu at plane k
+        const T *mn = MU[p1], *mc = MU[s0], *mm = MU[m1];
         T s[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T px[3] = {T(0), T(0), T(0)}, py[3] = {T(0), T(0), T(0)}, pz[3] = {T(0), T(0), T(0)};
         if (isB && k >= k0 - 1 && k <= klast) {
@@ -277,6 +288,7 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             for (int m = 0; m < 6; ++m) Sbuf[sb][m][li] = s[m];
             if (isO && k >= k0) {
                 // coefficient gradient at plane k: forward differences of E(k)
+                const T *n0 = EN[s0], *n1 = EN[p1];
                 const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
                 const T gxEz = Ebuf[eb][2][li + 1] - n0[2], gxEy = Ebuf[eb][1][li + 1] - n0[1];
                 const T gyEz = Ebuf[eb][2][li + PX] - n0[2], gyEx = Ebuf[eb][0][li + PX] - n0[0];
@@ -297,13 +309,17 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
                 acc[11] += (double)(gzEy * pz[0] - gzEx * pz[1]);
             }
         }
+        S0[s0] = s[0];
+        S3[s0] = s[3];
 
         // outputs of plane k-1: lE = lE' + backward differences of its stars
+        // (stars 0 and 3 of planes k-1 and k-2 from registers)
         if (isO && k - 1 >= k0) {
             const T(*Sp)[P] = Sbuf[sb ^ 1];
             const uint64_t po = (uint64_t)(uint32_t)wm * nxy;
-            const T lx = la[0] + ((sp3 - sq3) - (Sp[4][li] - Sp[4][li - PX]));
-            const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (sp0 - sq0));
+            const T *la = LE[m1];
+            const T lx = la[0] + ((S3[m1] - S3[p2]) - (Sp[4][li] - Sp[4][li - PX]));
+            const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (S0[m1] - S0[p2]));
             const T lz = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
             st_plane_a(dst[0] + po, oc, lx);
             st_plane_a(dst[1] + po, oc, ly);
@@ -312,29 +328,21 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
             for (int c = 0; c < 3; ++c) st_plane_a(dst[3 + c] + po, oc, mm[c]);
         }
         __syncthreads();
-
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            la[c] = l0[c];
-            l0[c] = l1[c];
-            l1[c] = l2[c];
-            mm[c] = mc[c];
-            mc[c] = mn[c];
-            n0[c] = n1[c];
-        }
-        sq0 = sp0;
-        sq3 = sp3;
-        sp0 = s[0];
-        sp3 = s[3];
         w3 = inc(w3);
         wm = inc(wm);
     };
-    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), two per loop trip
-    for (int k = k0 - 3;; k += 2) {
+    // KZe + 4 iterations (k = k0 - 3 .. klast + 1), four per loop trip; the
+    // loop leaves after exactly that many (an extra iteration would write the
+    // outputs of a plane beyond the chunk)
+    for (int k = k0 - 3;; k += 4) {
         plane(std::integral_constant<int, 0>{}, k);
         if (k + 1 > klast + 1) break;
         plane(std::integral_constant<int, 1>{}, k + 1);
         if (k + 2 > klast + 1) break;
+        plane(std::integral_constant<int, 2>{}, k + 2);
+        if (k + 3 > klast + 1) break;
+        plane(std::integral_constant<int, 3>{}, k + 3);
+        if (k + 4 > klast + 1) break;
     }
 
     // delta_a: the centre term (that of alpha_a) plus the along-axis
