@@ -334,6 +334,12 @@ struct xfdtd_s {
         int64_t n, seg;
     };
     std::vector<Tape> tapes;
+    // xfdtd_run replays a captured graph of kGraphSteps steps (captured on
+    // `cap` once per configuration and bound arrays, key `graph_key`)
+    bool use_graph;
+    hipStream_t cap;
+    hipGraphExec_t gexec;
+    std::array<uintptr_t, 20> graph_key;
 };
 
 namespace {
@@ -381,15 +387,15 @@ const Weights<T> &weights_of(const xfdtd_s *h)
 }
 
 template <typename T>
-int run_t(xfdtd_t h, int64_t n)
+int run_t(xfdtd_t h, int64_t n, hipStream_t st)
 {
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
     Fields<T> f = as_fields<T>(h->fields);
     if (!h->have_scratch) {
         for (int64_t s = 0; s < n; ++s) {
-            HIP_TRY(launch_faraday<T>(f, d, w, h->stream), "faraday launch");
-            HIP_TRY(launch_ampere<T>(f, d, w, h->stream), "ampere launch");
+            HIP_TRY(launch_faraday<T>(f, d, w, st), "faraday launch");
+            HIP_TRY(launch_ampere<T>(f, d, w, st), "ampere launch");
         }
         return XFDTD_OK;
     }
@@ -404,14 +410,14 @@ int run_t(xfdtd_t h, int64_t n)
         Fields<T> a = f, b = s;
         int64_t pairs = n / 2;
         auto fused = [&]() -> int {
-            HIP_TRY(launch_fused<T>(a, b, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
+            HIP_TRY(launch_fused<T>(a, b, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
             std::swap(a, b);
             return XFDTD_OK;
         };
         int rc = XFDTD_OK;
         if ((n & 1) && pairs % 2 == 0) {
-            HIP_TRY(launch_faraday<T>(a, d, w, h->stream), "faraday launch");
-            HIP_TRY(launch_ampere<T>(a, d, w, h->stream), "ampere launch");
+            HIP_TRY(launch_faraday<T>(a, d, w, st), "faraday launch");
+            HIP_TRY(launch_ampere<T>(a, d, w, st), "ampere launch");
         } else if (n & 1) {
             rc = fused();
         } else if (pairs % 2 == 1) {
@@ -421,7 +427,7 @@ int run_t(xfdtd_t h, int64_t n)
         }
         if (rc) return rc;
         for (int64_t i = 0; i < pairs; ++i) {
-            HIP_TRY(launch_blocked2<T>(a, b, d, w, h->btile_x, h->btile_y, h->bzchunk, h->stream),
+            HIP_TRY(launch_blocked2<T>(a, b, d, w, h->btile_x, h->btile_y, h->bzchunk, st),
                     "two-step launch");
             std::swap(a, b);
         }
@@ -429,13 +435,13 @@ int run_t(xfdtd_t h, int64_t n)
     }
     int64_t left = n;
     if (left & 1) {  // odd count: one in-place step keeps the result in `fields`
-        HIP_TRY(launch_faraday<T>(f, d, w, h->stream), "faraday launch");
-        HIP_TRY(launch_ampere<T>(f, d, w, h->stream), "ampere launch");
+        HIP_TRY(launch_faraday<T>(f, d, w, st), "faraday launch");
+        HIP_TRY(launch_ampere<T>(f, d, w, st), "ampere launch");
         --left;
     }
     for (; left > 0; left -= 2) {
-        HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
-        HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_x, h->tile_y, h->zchunk, h->stream), "fused launch");
+        HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
+        HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
     }
     return XFDTD_OK;
 }
@@ -443,6 +449,66 @@ int run_t(xfdtd_t h, int64_t n)
 }  // namespace
 
 namespace {
+
+// Steps per replay of the captured run graph: a multiple of four, so that the
+// graph (like every xfdtd_run call) leaves the result in the bound fields with
+// only out-of-place launches whichever kernel runs.
+constexpr int64_t kGraphSteps = 32;
+
+std::array<uintptr_t, 20> run_graph_key(const xfdtd_s *h)
+{
+    std::array<uintptr_t, 20> k{};
+    for (int c = 0; c < 6; ++c) {
+        k[c] = (uintptr_t)h->fields[c];
+        k[6 + c] = (uintptr_t)h->scratch[c];
+    }
+    k[12] = (uintptr_t)h->spp;
+    k[13] = ((uintptr_t)h->tile_x << 16) | (uintptr_t)h->tile_y;
+    k[14] = (uintptr_t)h->zchunk;
+    k[15] = ((uintptr_t)h->btile_x << 16) | (uintptr_t)h->btile_y;
+    k[16] = (uintptr_t)h->bzchunk;
+    k[17] = (uintptr_t)h->have_scratch;
+    k[18] = (uintptr_t)h->device;
+    k[19] = 1;  // a graph is held
+    return k;
+}
+
+void drop_run_graph(xfdtd_s *h)
+{
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->graph_key = {};
+}
+
+// Captures kGraphSteps steps of xfdtd_run into a graph (on the handle's
+// capture stream) unless the cached graph was captured with the same bound
+// arrays and launch configuration.
+template <typename F>
+int ensure_run_graph(xfdtd_s *h, F &&eager)
+{
+    const std::array<uintptr_t, 20> key = run_graph_key(h);
+    if (h->gexec && h->graph_key == key) return XFDTD_OK;
+    if (h->gexec) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");  // a replay may be queued
+    drop_run_graph(h);
+    if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const int rc = eager(kGraphSteps, h->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    h->graph_key = key;
+    return XFDTD_OK;
+}
 
 // Tilings chosen by xfdtd_tune, per (nx, ny, nz, dtype, device): steps per
 // pass, then (tile_x, tile_y, zchunk) of the kernel that won.
@@ -675,6 +741,11 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
         h->grad_acc = nullptr;
         h->aux = nullptr;
         h->aux_device = -1;
+        const char *gr = getenv("XFDTD_GRAPH");
+        h->use_graph = !(gr && atoi(gr) == 0);
+        h->cap = nullptr;
+        h->gexec = nullptr;
+        h->graph_key = {};
         *out = h;
         return XFDTD_OK;
     });
@@ -692,6 +763,11 @@ void xfdtd_destroy(xfdtd_t h)
     if (h->partials) hipFree(h->partials);
     if (h->apartials) hipFree(h->apartials);
     if (h->grad_acc) hipFree(h->grad_acc);
+    if (h->gexec) {
+        hipStreamSynchronize(h->stream);  // a replay may still be queued
+        hipGraphExecDestroy(h->gexec);
+    }
+    if (h->cap) hipStreamDestroy(h->cap);
     delete h;
 }
 
@@ -723,6 +799,15 @@ int xfdtd_bind(xfdtd_t h, void *const fields[6], void *const scratch[6], void *s
                 const uintptr_t pa = (uintptr_t)all[a], pb = (uintptr_t)all[b];
                 if (pa < pb + bytes && pb < pa + bytes) return fail(XFDTD_EINVAL, "bound arrays %d and %d overlap", a, b);
             }
+        if (h->gexec) {  // the cached run graph holds the old arrays: drop it if they change
+            bool same = h->stream == (hipStream_t)stream && h->have_scratch == (scratch != nullptr);
+            for (int c = 0; c < 6 && same; ++c)
+                same = h->fields[c] == fields[c] && h->scratch[c] == (scratch ? scratch[c] : nullptr);
+            if (!same) {
+                HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+                drop_run_graph(h);
+            }
+        }
         for (int c = 0; c < 6; ++c) {
             h->fields[c] = fields[c];
             h->scratch[c] = scratch ? scratch[c] : nullptr;
@@ -798,7 +883,23 @@ int xfdtd_run(xfdtd_t h, int64_t n)
         int rc = check_bound(h);
         if (rc) return rc;
         if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
-        return h->dtype == XFDTD_F32 ? run_t<float>(h, n) : run_t<double>(h, n);
+        auto eager = [&](int64_t m, hipStream_t st) {
+            return h->dtype == XFDTD_F32 ? run_t<float>(h, m, st) : run_t<double>(h, m, st);
+        };
+        // inside a capture of the caller's stream the launches go straight
+        // into the caller's graph
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(h->stream, &cs), "hipStreamIsCapturing");
+        const int64_t units = h->use_graph && cs == hipStreamCaptureStatusNone ? n / kGraphSteps : 0;
+        if (units > 0) {
+            rc = ensure_run_graph(h, eager);
+            if (rc) return rc;
+            for (int64_t u = 0; u < units; ++u) HIP_TRY(hipGraphLaunch(h->gexec, h->stream), "hipGraphLaunch");
+        }
+        // the remaining steps (all of them without a graph) are launched
+        // directly; each part leaves the result in the bound fields, and the
+        // steps are the same kernels in the same order either way
+        return eager(n - units * kGraphSteps, h->stream);
     });
 }
 

@@ -295,6 +295,33 @@ def test_two_step_kernel_bitwise_equals_one_step(env, shape):
             assert rel_l2(got, exp) < 1e-6
 
 
+@pytest.mark.parametrize("dtype,shape,spp", [(torch.float32, (33, 17, 64), 1), (torch.float32, (37, 45, 150), 2),
+                                             (torch.float64, (20, 18, 70), 1)])
+def test_run_graph_replay_is_bitwise_the_direct_launches(env, dtype, shape, spp):
+    """xfdtd_run replays a captured graph of 32 steps and launches the rest
+    directly: bitwise the same as direct launches only, for step counts below,
+    at and above one replay, across rebinding to other arrays (which captures
+    a new graph) and after retuning."""
+    c = _coeffs(471)
+    dt = 0.95 * O.cfl_dt(c)
+    f0 = S.uniform_fields(shape, 472)
+    for n in (5, 32, 70, 131):
+        env(XFDTD_GRAPH=0, XFDTD_STEPS_PER_PASS=spp)
+        a = to_dev(f0, dtype)
+        pkg.Solver(a, dt, c).run(n)
+        env(XFDTD_GRAPH=1)
+        b = to_dev(f0, dtype)
+        sb = pkg.Solver(b, dt, c)
+        sb.run(n // 2)
+        sb.run(n - n // 2)
+        assert all(torch.equal(x, y) for x, y in zip(a, b)), n
+        # other arrays on the same handle: the old graph must not be replayed
+        b2 = to_dev(f0, dtype)
+        sb.fields = b2
+        sb.run(n)
+        assert all(torch.equal(x, y) for x, y in zip(a, b2)), n
+
+
 def test_two_step_kernel_rejects_fp64_and_bad_counts():
     shape = (6, 5, 7)
     c = _coeffs(485)
