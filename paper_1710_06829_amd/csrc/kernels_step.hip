@@ -701,8 +701,8 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                E[p2][r][c] = take(pe[Q][r][c]);
-                bo[r][c] = take(pb[Q][r][c]);
+                E[p2][r][c] = pe[Q][r][c];
+                bo[r][c] = pb[Q][r][c];
             }
         // lane offsets opaque to the compiler (scalar plane base + 32-bit
         // lane offset per access, as in the one-step kernel)
