@@ -555,8 +555,8 @@ __global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<
 // A workgroup owns a TX x TY output tile.  Two chained steps reach four cells
 // into the neighbouring tiles (each step two: the extended difference one cell
 // below and two above, Ampere one more below), so the workgroup covers the
-// (TX + 8) x (TY + 8) positions x, y in [-4, T + 4), laid out linearly (slot
-// s = threadIdx.x + r * THREADS is position (s mod PX, s / PX), LDS index s),
+// (TX + 8) x (TY + 8) positions x, y in [-4, T + 4), one per lane, waves
+// aligned with memory rows (blk2_position; LDS index (y + 4) PX + x + 4),
 // and evaluates each stage redundantly on the part of the halo the next stage
 // needs (regions below).  Every position computes the same per-cell
 // expressions as the one-step kernel, so the result is bitwise that of two
@@ -583,6 +583,31 @@ struct Blk2Smem {
     T G2[6][P];  // stage 2: g(j) of E^{n+1}
     T B2[3][P];  // stage 2: B^{n+3/2}(j-1)
 };
+
+// Position of slot sl of a 32-column two-step tile.  Waves are aligned with
+// memory rows: the first TX*TY slots are the output cells, two 32-column rows
+// per wave (every output row segment is one 128-byte line, stored by one
+// instruction); then the 8 halo columns x in [-4, 0) and [TX, TX+4) over all
+// TY + 8 rows; then the 8 halo rows y in [-4, 0) and [TY, TY+4) over the TX
+// inner columns.  Each part is a whole number of waves.
+template <typename C>
+__device__ __forceinline__ void blk2_position(int sl, int &rx, int &ry)
+{
+    constexpr int TX = C::TX, TY = C::TY, NI = TX * TY, NC = 8 * (TY + 8);
+    static_assert(TX == 32 && NI % 64 == 0 && NC % 64 == 0 && (8 * TX) % 64 == 0, "wave-aligned parts");
+    if (sl < NI) {
+        rx = sl % TX;
+        ry = sl / TX;
+    } else if (sl < NI + NC) {
+        const int t = sl - NI, c = t % 8;
+        rx = c < 4 ? c - 4 : TX + c - 4;
+        ry = t / 8 - 4;
+    } else {
+        const int t = sl - NI - NC, row = t / TX;
+        rx = t % TX;
+        ry = row < 4 ? row - 4 : TY + row - 4;
+    }
+}
 
 template <typename T, typename C>
 __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
@@ -618,8 +643,9 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int sl = (int)threadIdx.x + r * C::THREADS;
-        const int rx = sl % PX - 4, ry = sl / PX - 4;
-        const bool v = sl < P && rx < TXe + 4 && ry < TYe + 4;
+        int rx, ry;
+        blk2_position<C>(sl, rx, ry);
+        const bool v = rx < TXe + 4 && ry < TYe + 4;
         auto in_box = [&](int lo, int hx, int hy) { return v && rx >= lo && ry >= lo && rx < hx && ry < hy; };
         inL1[r] = v;
         inG1[r] = in_box(-4, TXe + 3, TYe + 3);
@@ -629,15 +655,15 @@ __device__ __forceinline__ void blocked2_tile(const Fields<T> &in, const Fields<
         inS2[r] = in_box(-1, TXe, TYe);
         inO[r] = in_box(0, TXe, TYe);
         // every slot is a position of the grid (static_assert in Blk2Cfg);
-        // positions past the tile's extent (ragged tiles) keep their own
+        // positions past the tile's extent (ragged tiles) keep their own LDS
         // slots, which no position of the tile reads
-        li[r] = sl;
+        li[r] = (ry + 4) * PX + (rx + 4);
         // Phase A evaluates every stage at every position without branches
         // (results outside a stage's region are never read), so the
         // neighbour indices of the reads are clamped into the planes: g reads
         // +1 and +PX (slot 0 outside the g regions), the stars and the Ampere
         // update +-1 and +-PX (an interior slot on the outermost ring).
-        inner[r] = sl < P && rx >= -3 && ry >= -3 && rx <= C::TX + 2 && ry <= C::TY + 2;
+        inner[r] = rx >= -3 && ry >= -3 && rx <= C::TX + 2 && ry <= C::TY + 2;
         // idle positions load column 0 (in bounds, value unused)
         col[r] = v ? wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx) : 0;
         // B^{n-1/2} is needed only where B^{n+1/2} is formed
