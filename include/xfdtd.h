@@ -165,7 +165,7 @@ int xfdtd_run(xfdtd_t h, int64_t n);
  *      on chip, redundantly on a 4-cell halo of each tile; every cell's
  *      arithmetic is the one-step kernel's, so the results are bitwise the
  *      same as with 1.
- * Default 2 for FP32 grids of at least 2^24 cells, else 1 (override with
+ * Default 2 for FP32 grids of at least 2^23 cells, else 1 (override with
  * XFDTD_STEPS_PER_PASS=1 or 2 at xfdtd_create); xfdtd_tune chooses between
  * them per grid.  XFDTD_EINVAL for other values and for 2 on an FP64 handle.
  * Host only.

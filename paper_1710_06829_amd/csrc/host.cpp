@@ -706,11 +706,12 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     h->btile_x = 32;
     h->btile_y = dtype == XFDTD_F32 ? pick_blocked2_tile_y(*g) : 8;
     h->bzchunk = dtype == XFDTD_F32 ? blocked2_zchunk(*g, h->btile_x, h->btile_y) : 1;
-    // Two steps per pass by default for FP32 boxes of at least 2^24 cells;
-    // below that the one-step kernel measured faster (32^3 .. 128^3: its
-    // shorter z-march warm-up and smaller halo win while the two-step
-    // kernel's halved traffic does not matter).  xfdtd_tune decides per box.
-    h->spp = dtype == XFDTD_F32 && (double)g->nx * g->ny * g->nz >= (double)(1 << 24) ? 2 : 1;
+    // Two steps per pass by default for FP32 boxes of at least 2^23 cells;
+    // below that the one-step kernel measured as fast or faster (32^3 ..
+    // 128^3: its shorter z-march warm-up and smaller halo win while the
+    // two-step kernel's halved traffic does not matter; 192^2 x 352 and up:
+    // two-step).  xfdtd_tune decides per box.
+    h->spp = dtype == XFDTD_F32 && (double)g->nx * g->ny * g->nz >= (double)(1 << 23) ? 2 : 1;
     const char *spp = getenv("XFDTD_STEPS_PER_PASS");
     if (spp && (atoi(spp) == 1 || (atoi(spp) == 2 && dtype == XFDTD_F32))) h->spp = atoi(spp);
     const char *bty = getenv("XFDTD_BLK_TILE_Y");
