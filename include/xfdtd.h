@@ -408,8 +408,10 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
  * xfdtd_batch_set_config / get_config: choose / report the configuration:
  *     tile_x 64 or 32, tile_y 4, 8 or 16 (16: FP32 only), zsplit 1..1024
  *     (each box is cut into z-chunks of ceil(nz / zsplit) >= 4 planes),
- *     grid >= 0 (0 = one workgroup per work item); nitems = work-list
- *     length (0 before binding).  XFDTD_EINVAL for any other value.  The
+ *     grid >= 0 (0 = one workgroup per work-list slot); nitems = work-list
+ *     length in slots (0 before binding): the tiles x z-chunks of every
+ *     box, dealt to the 8 XCDs in runs of neighbouring tiles with balanced
+ *     plane counts, padded with empty slots where an XCD's share is short.  XFDTD_EINVAL for any other value.  The
  *     untuned default: tile_x 32 only when every box has nx <= 32, tile_y 8,
  *     the z-split minimising max(total plane iterations / resident
  *     workgroups, longest work item), grid 0.
@@ -428,6 +430,18 @@ int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_x, int tile_y, int zsplit, 
 int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems);
 int xfdtd_batch_run(xfdtd_batch_t b, int64_t n);
 int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n);
+
+/*
+ * Steps per launch of a batch's run (as xfdtd_set_steps_per_pass for one
+ * box): 1, or 2 for the two-step kernel (the leapfrog of App. A eq.
+ * update1-6 applied twice per pass over each box's fields; FP32, tiling
+ * 32 x 8 or 32 x 16 set by xfdtd_batch_set_config or the tuner), bitwise the
+ * same results.  xfdtd_batch_tune also times two-step candidates and sets
+ * this; xfdtd_batch_set_config resets it to 1 for tilings the two-step kernel
+ * does not have.  XFDTD_EINVAL otherwise.  Host only.
+ */
+int xfdtd_batch_set_steps_per_pass(xfdtd_batch_t b, int steps);
+int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps);
 
 /*
  * Batched checkpointed gradients: the single-box schedule of

@@ -72,11 +72,17 @@ class Batch:
     def set_config(self, tile_y, zsplit, grid, tile_x=64):
         B.check(B.lib().xfdtd_batch_set_config(self._h, int(tile_x), int(tile_y), int(zsplit), int(grid)))
 
+    def set_steps_per_pass(self, steps):
+        """1, or 2: the two-step kernel (FP32, 32-column tiles); bitwise the same results."""
+        B.check(B.lib().xfdtd_batch_set_steps_per_pass(self._h, int(steps)))
+
     def config(self):
         v = [ctypes.c_int() for _ in range(5)]
         B.check(B.lib().xfdtd_batch_get_config(self._h, *[ctypes.byref(x) for x in v]))
+        spp = ctypes.c_int()
+        B.check(B.lib().xfdtd_batch_get_steps_per_pass(self._h, ctypes.byref(spp)))
         return {"tile_x": v[0].value, "tile_y": v[1].value, "zsplit": v[2].value, "grid": v[3].value,
-                "items": v[4].value}
+                "items": v[4].value, "steps_per_pass": spp.value}
 
     def run(self, n, graph=True):
         fn = B.lib().xfdtd_batch_run if graph else B.lib().xfdtd_batch_run_eager

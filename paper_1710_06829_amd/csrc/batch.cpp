@@ -37,8 +37,10 @@ namespace {
         if (e_ != hipSuccess) return set_error(XFDTD_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
     } while (0)
 
+// Launch configuration of a batch; spp = 2 runs the two-step kernel (FP32,
+// 32-column tiles, which the one-step kernel also has).
 struct Config {
-    int tile_x = 64, tile_y = 8, zsplit = 1, grid = 0;
+    int tile_x = 64, tile_y = 8, zsplit = 1, grid = 0, spp = 1;
 };
 
 std::mutex g_cache_mu;
@@ -150,12 +152,80 @@ bool prefer_narrow(const xfdtd_batch_s *b)
     return true;
 }
 
+// Dispatch order of a batch's work items.  Workgroup w of a launch goes to
+// XCD w mod 8 and, within an XCD, workgroups start in order as CUs free up,
+// so the order decides both the balance between the XCDs (whose L2s are
+// separate) and each XCD's schedule.  The items come in runs (consecutive
+// tiles of one box and z-chunk, whose halos overlap and are best fetched
+// once into one L2); runs go whole, largest first, to the XCD with the least
+// work so far, and each XCD's items then go longest first (stable, so a run
+// stays together).  Slot 8 j + x of the result holds the j-th item of XCD x,
+// or -1 where that XCD's list has ended.
+std::vector<int> xcd_schedule(const std::vector<double> &cost, const std::vector<int> &run)
+{
+    struct Run {
+        double cost;
+        size_t first, count;
+    };
+    std::vector<Run> runs;
+    for (size_t i = 0; i < cost.size(); ++i) {
+        if (i == 0 || run[i] != run[i - 1]) runs.push_back({0.0, i, 0});
+        runs.back().cost += cost[i];
+        runs.back().count += 1;
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.cost > c.cost; });
+    std::array<double, 8> load{};
+    std::array<std::vector<int>, 8> lists;
+    for (const Run &r : runs) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += r.cost;
+        for (size_t i = r.first; i < r.first + r.count; ++i) lists[x].push_back((int)i);
+    }
+    size_t len = 0;
+    for (auto &l : lists) {
+        std::stable_sort(l.begin(), l.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+        len = std::max(len, l.size());
+    }
+    std::vector<int> order(8 * len, -1);
+    for (int x = 0; x < 8; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) order[8 * j + x] = lists[x][j];
+    return order;
+}
+
+// Work items of box descriptor d in tile order (x fastest, then y, then the
+// z-chunk), with their costs in plane iterations (chunk length plus the
+// kernel's warm-up planes) and run numbers: runs of at most run_len
+// consecutive tiles of one z-chunk.
+void box_items(int box, int ntx, int nty, int nz, int zchunk, int warm, int run_len, std::vector<int2> &items,
+               std::vector<double> &cost, std::vector<int> &run)
+{
+    const int nzc = (nz + zchunk - 1) / zchunk;
+    const int per = ntx * nty;
+    for (int c = 0; c < nzc; ++c) {
+        const double k = (double)(std::min(zchunk, nz - c * zchunk) + warm);
+        for (int t = 0; t < per; ++t) {
+            if (t % run_len == 0) run.push_back(run.empty() ? 0 : run.back() + 1);
+            else run.push_back(run.back());
+            items.push_back(make_int2(box, c * per + t));
+            cost.push_back(k);
+        }
+    }
+}
+
+// Run length of a work list: about 1/16 of an XCD's share of the plane
+// iterations, in items of the typical cost.
+int run_length(double total_cost, double items)
+{
+    if (items <= 0) return 1;
+    const double per_item = total_cost / items;
+    return std::max(1, (int)(total_cost / 128.0 / per_item));
+}
+
 template <typename T>
 int build_t(xfdtd_batch_t b)
 {
     const int ty = b->cfg.tile_y;
     std::vector<BoxDesc<T>> descs((size_t)b->m);
-    std::vector<std::pair<double, int64_t>> order;
     for (int64_t i = 0; i < b->m; ++i) {
         const xfdtd_grid &g = b->g[i];
         BoxDesc<T> &d = descs[i];
@@ -170,18 +240,27 @@ int build_t(xfdtd_batch_t b)
         d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
         d.nty = (int)((g.ny + ty - 1) / ty);
         d.pad = 0;
-        order.push_back({-(double)g.nx * g.ny * g.nz, i});
     }
-    // largest boxes first: their tiles start in the first rounds
-    std::stable_sort(order.begin(), order.end());
-    std::vector<int2> items;
-    for (auto &o : order) {
-        const int64_t i = o.second;
-        const BoxDesc<T> &d = descs[i];
+    // warm-up planes of a z-chunk: 3 for the one-step march, 10 for two steps
+    const int warm = b->cfg.spp == 2 ? 10 : 3;
+    double total = 0, count = 0;
+    for (const BoxDesc<T> &d : descs) {
+        const double tiles = (double)d.ntx * d.nty;
         const int nzc = (d.d.nz + d.zchunk - 1) / d.zchunk;
-        const int64_t nt = (int64_t)d.ntx * d.nty * nzc;
-        for (int64_t t = 0; t < nt; ++t) items.push_back(make_int2((int)i, (int)t));
+        total += tiles * ((double)d.d.nz + (double)nzc * warm);
+        count += tiles * nzc;
     }
+    if (count > 0x3fffffff) return set_error(XFDTD_EINVAL, "too many work items");
+    const int run_len = run_length(total, count);
+    std::vector<int2> all;
+    std::vector<double> cost;
+    std::vector<int> run;
+    for (int64_t i = 0; i < b->m; ++i) {
+        const BoxDesc<T> &d = descs[i];
+        box_items((int)i, d.ntx, d.nty, d.d.nz, d.zchunk, warm, run_len, all, cost, run);
+    }
+    std::vector<int2> items;
+    for (int j : xcd_schedule(cost, run)) items.push_back(j < 0 ? make_int2(-1, -1) : all[j]);
     if (items.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     if (b->d_boxes) hipFree(b->d_boxes);
     if (b->d_items) hipFree(b->d_items);
@@ -223,6 +302,21 @@ int launch_step(xfdtd_batch_t b, int parity, hipStream_t s)
     return XFDTD_OK;
 }
 
+// One two-step launch (cfg.spp == 2): two steps of every box.
+int launch_pair(xfdtd_batch_t b, int parity, hipStream_t s)
+{
+    const hipError_t e = launch_batched2<float>((const BoxDesc<float> *)b->d_boxes, b->d_items, b->nitems, parity,
+                                                b->cfg.tile_y, grid_of(b), s);
+    if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched two-step launch: %s", hipGetErrorString(e));
+    return XFDTD_OK;
+}
+
+// The launches of n steps on stream s, ending in the state arrays: an odd n
+// starts with one in-place unfused step; with the two-step kernel an odd
+// number of pairs does one pair as two one-step launches, so that the number
+// of out-of-place launches is even.
+int launch_steps(xfdtd_batch_t b, int64_t n, hipStream_t s);
+
 template <typename T>
 int unfused_all(xfdtd_batch_t b, hipStream_t s)
 {
@@ -238,6 +332,27 @@ int unfused_all(xfdtd_batch_t b, hipStream_t s)
         if (e != hipSuccess) return set_error(XFDTD_EHIP, "unfused launch: %s", hipGetErrorString(e));
     }
     return XFDTD_OK;
+}
+
+int launch_steps(xfdtd_batch_t b, int64_t n, hipStream_t s)
+{
+    int rc = XFDTD_OK;
+    int64_t left = n;
+    if (left & 1) {  // odd count: one in-place step keeps the result in the state arrays
+        rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, s) : unfused_all<double>(b, s);
+        --left;
+    }
+    if (b->cfg.spp == 2) {
+        int64_t pairs = left / 2;
+        if (pairs & 1) {
+            for (int p = 0; p < 2 && !rc; ++p) rc = launch_step(b, p, s);
+            --pairs;
+        }
+        for (int64_t q = 0; q < pairs && !rc; ++q) rc = launch_pair(b, (int)(q & 1), s);
+        return rc;
+    }
+    for (int64_t q = 0; q < left && !rc; ++q) rc = launch_step(b, (int)(q & 1), s);
+    return rc;
 }
 
 std::string shape_key(const xfdtd_batch_t b)
@@ -356,9 +471,33 @@ int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_x, int tile_y, int zsplit, 
         b->cfg.tile_y = tile_y;
         b->cfg.zsplit = zsplit;
         b->cfg.grid = grid;
+        if (b->cfg.spp == 2 && (tile_x != 32 || tile_y == 4)) b->cfg.spp = 1;
         b->cfg_set = true;
         return b->bound ? build(b) : XFDTD_OK;
     });
+}
+
+int xfdtd_batch_set_steps_per_pass(xfdtd_batch_t b, int steps)
+{
+    return guarded([&]() -> int {
+        if (!b) return set_error(XFDTD_EINVAL, "null handle");
+        if (steps != 1 && steps != 2) return set_error(XFDTD_EINVAL, "steps per pass must be 1 or 2");
+        if (steps == 2 && (b->dtype != XFDTD_F32 || b->cfg.tile_x != 32 || b->cfg.tile_y == 4))
+            return set_error(XFDTD_EINVAL, "two steps per pass need FP32 and a 32 x 8 or 32 x 16 tiling");
+        if (b->cfg.spp != steps) {
+            b->cfg.spp = steps;
+            b->cfg_set = true;
+            drop_graph(b);
+        }
+        return XFDTD_OK;
+    });
+}
+
+int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps)
+{
+    if (!b || !steps) return set_error(XFDTD_EINVAL, "null argument");
+    *steps = b->cfg.spp;
+    return XFDTD_OK;
 }
 
 int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems)
@@ -411,6 +550,20 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
                 }
             }
         }
+        // FP32: the two-step kernel on 32-column tiles, whole-depth or split
+        // z-marches (its chunks start with 10 warm-up planes)
+        if (b->dtype == XFDTD_F32)
+            for (int ty : {8, 16})
+                for (int zs : {1, 2})
+                    for (int gm : {0, 1}) {
+                        Config c;
+                        c.tile_x = 32;
+                        c.tile_y = ty;
+                        c.zsplit = zs;
+                        c.grid = gm == 0 ? 0 : gm * ncu;
+                        c.spp = 2;
+                        cands.push_back(c);
+                    }
         hipEvent_t e0, e1;
         BTRY(hipEventCreate(&e0), "hipEventCreate");
         if (hipEventCreate(&e1) != hipSuccess) {
@@ -426,7 +579,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         int rc = XFDTD_OK;
         auto timed = [&](int r, float *ms) {
             int q = hipEventRecord(e0, b->stream) == hipSuccess ? XFDTD_OK : set_error(XFDTD_EHIP, "event record");
-            for (int i = 0; i < r && !q; ++i) q = launch_step(b, 0, b->stream);
+            for (int i = 0; i < r && !q; ++i) q = b->cfg.spp == 2 ? launch_pair(b, 0, b->stream) : launch_step(b, 0, b->stream);
             if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = set_error(XFDTD_EHIP, "event record");
             if (!q && hipEventSynchronize(e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event synchronize");
             if (!q && hipEventElapsedTime(ms, e0, e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event time");
@@ -443,7 +596,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
                     reps[i] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
                 }
                 if (!rc) rc = timed(reps[i], &ms);
-                if (!rc) per[i] = std::min(per[i], (double)ms / reps[i]);
+                if (!rc) per[i] = std::min(per[i], (double)ms / reps[i] / cands[i].spp);
             }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
@@ -482,13 +635,7 @@ int xfdtd_batch_run(xfdtd_batch_t b, int64_t n)
         if (b->graph_n != n || !b->gexec) {
             drop_graph(b);
             BTRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            int rc = XFDTD_OK;
-            int64_t left = n;
-            if (left & 1) {  // odd count: one in-place step keeps the result in the state arrays
-                rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->capture) : unfused_all<double>(b, b->capture);
-                --left;
-            }
-            for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->capture);
+            const int rc = launch_steps(b, n, b->capture);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(b->capture, &graph);
             if (rc) {
@@ -515,14 +662,7 @@ int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n)
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
         if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
-        int rc = XFDTD_OK;
-        int64_t left = n;
-        if (left & 1) {
-            rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, b->stream) : unfused_all<double>(b, b->stream);
-            --left;
-        }
-        for (int64_t s = 0; s < left && !rc; ++s) rc = launch_step(b, (int)(s & 1), b->stream);
-        return rc;
+        return launch_steps(b, n, b->stream);
     });
 }
 

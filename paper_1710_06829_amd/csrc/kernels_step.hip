@@ -519,19 +519,18 @@ __global__ __launch_bounds__(C::THREADS) void fused_step_kernel(Fields<T> in, Fi
 }
 
 // Batched step: every box of a batch advances one step.  Work item i is tile
-// items[i].y of box items[i].x; a persistent grid walks the list in rounds of
-// gridDim.x items (XCD-aware within a round).  parity 0: f -> s, 1: s -> f.
+// items[i].y of box items[i].x (box -1: no work); workgroup w takes items w,
+// w + gridDim.x, ...  The host orders the list for the XCD each slot lands
+// on.  parity 0: f -> s, 1: s -> f.
 template <typename T, typename C>
 __global__ __launch_bounds__(C::THREADS) void batched_step_kernel(const BoxDesc<T> *__restrict__ boxes,
                                                                   const int2 *__restrict__ items,
                                                                   int nitems, int parity)
 {
     __shared__ FusedSmem<T, C::TX, C::TY> sm;
-    const int slot = xcd_order(blockIdx.x, gridDim.x);
-    for (int base = 0; base < nitems; base += gridDim.x) {
-        const int i = base + slot;
-        if (i >= nitems) break;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
+        if (it.x < 0) continue;
         const BoxDesc<T> &b = boxes[it.x];
         const Fields<T> &in = parity ? b.s : b.f;
         const Fields<T> &out = parity ? b.f : b.s;
@@ -836,6 +835,27 @@ __global__ __launch_bounds__(C::THREADS) void blocked2_kernel(Fields<T> in, Fiel
     blocked2_tile<T, C>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
 }
 
+// Batched two-step launch: every box of a batch advances two steps; work item
+// i is tile items[i].y of box items[i].x (32-column tiles of the box's
+// tiling); a persistent grid walks the list as in batched_step_kernel.
+// parity 0: f -> s, 1: s -> f.
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void batched_blocked2_kernel(const BoxDesc<T> *__restrict__ boxes,
+                                                                      const int2 *__restrict__ items, int nitems,
+                                                                      int parity)
+{
+    __shared__ Blk2Smem<T, C::P> sm;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        if (it.x < 0) continue;
+        const BoxDesc<T> &b = boxes[it.x];
+        const Fields<T> &in = parity ? b.s : b.f;
+        const Fields<T> &out = parity ? b.f : b.s;
+        blocked2_tile<T, C>(in, out, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
 // Two-step tilings (FP32), one position per lane: 32x16 outputs on 40x24
 // positions (15 waves), 32x8 on 40x16 (10 waves, for small boxes).  With two
 // positions per lane (e.g. 32x24 on 40x32 in 10 waves) the two stages' register
@@ -946,6 +966,20 @@ hipError_t launch_blocked2(const Fields<T> &in, const Fields<T> &out, Dims d, co
 }
 
 template <typename T>
+hipError_t launch_batched2(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_y,
+                           int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (grid <= 0 || grid > nitems) grid = nitems;
+    return with_blk2<T>(32, tile_y, [&](auto cfg) {
+        using C = decltype(cfg);
+        hipLaunchKernelGGL((batched_blocked2_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items,
+                           nitems, parity);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
 int blocked2_occupancy(int tile_x, int tile_y)
 {
     int n = 0;
@@ -989,6 +1023,10 @@ int fused_occupancy(int tile_x, int tile_y)
     return n;
 }
 
+template hipError_t launch_batched2<float>(const BoxDesc<float> *, const int2 *, int, int, int, int,
+                                           hipStream_t);
+template hipError_t launch_batched2<double>(const BoxDesc<double> *, const int2 *, int, int, int, int,
+                                            hipStream_t);
 template int blocked2_occupancy<float>(int, int);
 template int blocked2_occupancy<double>(int, int);
 template hipError_t launch_blocked2<float>(const Fields<float> &, const Fields<float> &, Dims,

@@ -103,6 +103,13 @@ template <typename T>
 hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_x,
                           int tile_y, int grid, hipStream_t s);
 
+// Batched two-step launch (FP32): every box advances two steps; the boxes'
+// tilings must be 32 x tile_y (tile_y 8 or 16).  hipErrorInvalidValue for
+// other tilings or dtypes.
+template <typename T>
+hipError_t launch_batched2(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_y,
+                           int grid, hipStream_t s);
+
 // Adjoint step (kernels_adjoint.hip): lin -> lout (distinct buffers), primal
 // E of the step in en[3]; per-workgroup unscaled gradient sums in partials
 // (adjoint_blocks(...) x 12 doubles).

@@ -69,6 +69,32 @@ def test_batch_graph_replays_and_tuner_keeps_state_fp32():
             assert torch.equal(a, b), (i, shape)
 
 
+@pytest.mark.parametrize("cfg", [(8, 1, 0), (16, 2, 0), (8, 4, 3), (16, 1, 256)])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_two_steps_per_launch_equals_single_runs_fp32(cfg, graph):
+    """Two steps per launch (FP32, 32-column tiles): every tile height,
+    z-split and grid, and step counts that take each path that keeps the
+    result in the state arrays (odd n, odd and even numbers of pairs), give
+    bitwise the results of single-box runs."""
+    boxes = _small_batch(torch.float32, seed=740)
+    for n in (3, 4, 6, 9):
+        t = [to_dev(f, torch.float32) for (_, f, _, _, _) in boxes]
+        bt = pkg.Batch([(t[i], dt, c, sp) for i, (_, _, c, dt, sp) in enumerate(boxes)], tune=False)
+        bt.set_config(cfg[0], cfg[1], cfg[2], tile_x=32)
+        bt.set_steps_per_pass(2)
+        assert bt.config()["steps_per_pass"] == 2
+        bt.run(n, graph=graph)
+        for i, (shape, f0, c, dt, sp) in enumerate(boxes):
+            ref = to_dev(f0, torch.float32)
+            pkg.Solver(ref, dt, c, spacing=sp).run(n)
+            torch.cuda.synchronize()
+            for a, b in zip(t[i], ref):
+                assert torch.equal(a, b), (n, i, shape)
+    with pytest.raises(pkg.XfdtdError):  # 64-column tilings have no two-step kernel
+        bt.set_config(8, 1, 0, tile_x=64)
+        bt.set_steps_per_pass(2)
+
+
 def test_config3_64_boxes_500_steps():
     path = os.path.join(GOLD, "c3_boxes_fp32.npz")
     boxes = W.c3_boxes()
@@ -76,6 +102,7 @@ def test_config3_64_boxes_500_steps():
     seq = [to_dev(f, torch.float32) for (_, f, _, _) in boxes]
     bt = pkg.Batch([(t[i], dt, c) for i, (_, _, c, dt) in enumerate(boxes)], tune=True)
     bt.run(500)
+    print(f"c3 batch configuration: {bt.config()}")
     for i, (shape, f0, c, dt) in enumerate(boxes):
         pkg.Solver(seq[i], dt, c).run(500)
     torch.cuda.synchronize()
