@@ -30,6 +30,9 @@ PROFILES = {1: os.path.join(ROOT, "profiles", "fused_step_512x256x256_fp32.md"),
             2: os.path.join(ROOT, "profiles", "two_step_512x256x256_fp32.md")}
 TILE_NAMES = {(64, 4): "TileCfg<1,8,64>", (64, 8): "TileCfg<1,12,64>", (64, 16): "TileCfg<2,10,64>",
               (32, 4): "TileCfg<1,4,32>", (32, 8): "TileCfg<1,6,32>", (32, 16): "TileCfg<2,5,32>"}
+# Batches replay a captured graph and single boxes replay graphs of 32 steps;
+# --no-graph launches everything directly (rocprofv3 counter passes).
+USE_GRAPH = True
 BLK_NAMES = {(32, 16): "Blk2Cfg<32,16,1,15>", (32, 8): "Blk2Cfg<32,8,1,10>"}
 
 
@@ -102,6 +105,45 @@ def cpu_baseline(f64_fields, coeffs, dt, steps):
         "sample": f"{steps} FP64 steps of the full 512x256x256 pulse workload "
                   f"(plain C oracle, OpenMP, {el:.1f} s)",
     }
+
+
+def adjoint_step_rate(steps=40):
+    """One adjoint step (the transposed update with its 12 coefficient-gradient
+    partials) on the 512x256x256 FP32 workload with nothing else running:
+    time per step and HBM rate at 60 B per cell (the 6 adjoint components
+    read and written once, the 3 primal E components read once)."""
+    import torch
+
+    import paper_1710_06829_amd as pkg
+
+    fields, coeffs, dt, _ = make_inputs(SHAPE, torch.float32)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    la = [torch.rand(SHAPE, device="cuda", generator=g) * 2 - 1 for _ in range(6)]
+    lb = [torch.empty_like(x) for x in la]
+    s = pkg.Solver(fields, dt, coeffs, scratch=False)
+    gr = torch.zeros(12, dtype=torch.float64, device="cuda")
+    steps = max(2, steps + (steps & 1))
+    for i in range(4):
+        s.adjoint_step(la, lb, fields[:3], gr) if i % 2 == 0 else s.adjoint_step(lb, la, fields[:3], gr)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for rep in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            s.adjoint_step(la, lb, fields[:3], gr) if i % 2 == 0 else s.adjoint_step(lb, la, fields[:3], gr)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
+    cells = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    gbs = 60.0 * cells / (best * 1e-3) / 1e9
+    del s, fields, la, lb
+    return {"workload": "512x256x256 FP32 adjoint step (transposed update + 12 coefficient-gradient partials)",
+            "us_per_step": round(best * 1e3, 2), "bytes_per_cell": 60,
+            "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": "adjoint_step_kernel"}
 
 
 def fwd_adj_ratio(steps=200):
@@ -279,11 +321,11 @@ def batched_boxes(steps=500):
         cells += nx * ny * nz
     bt = pkg.Batch(boxes, tune=True)
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    bt.run(steps)  # captures the graph (first call)
+    bt.run(steps, graph=USE_GRAPH)  # captures the graph (first call)
     torch.cuda.synchronize()
     e0, e1 = ev(), ev()
     e0.record()
-    bt.run(steps)
+    bt.run(steps, graph=USE_GRAPH)
     e1.record()
     torch.cuda.synchronize()
     t_b = e0.elapsed_time(e1)
@@ -347,9 +389,9 @@ def batched_grads(steps=300, count=16, edge=96):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    bt.run(steps)  # graph capture
+    bt.run(steps, graph=USE_GRAPH)  # graph capture
     reset()
-    t_fwd = timed(lambda: bt.run(steps))
+    t_fwd = timed(lambda: bt.run(steps, graph=USE_GRAPH))
     ws = bt.grad_workspaces(steps)
     lams = [[x.clone() for x in lam0] for _ in range(count)]
     reset()
@@ -447,10 +489,14 @@ def main():
     ap.add_argument("--no-adj", action="store_true")
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB plain copy")
     ap.add_argument("--adj-only", action="store_true", help="only the fwd+adjoint measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the 512x256x256 adjoint step (--steps adjoint steps)")
     ap.add_argument("--grad-batch-only", action="store_true", help="only the batched gradient measurement")
     ap.add_argument("--norm-only", action="store_true", help="only the dispersion-norm measurement")
     ap.add_argument("--fp64-only", action="store_true", help="only the FP64 512x256x256 measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-box batched measurement")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch kernels directly instead of replaying captured graphs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 1024x256x256 sustained run and the 64-box batch")
     args = ap.parse_args()
@@ -458,12 +504,19 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    if args.no_graph:
+        global USE_GRAPH
+        USE_GRAPH = False
+        os.environ["XFDTD_GRAPH"] = "0"  # read when a solver is created
     import torch
 
     import paper_1710_06829_amd as pkg
 
     if args.adj_only:
         print(json.dumps({"fwd_adj": fwd_adj_ratio()}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_512x256x256": adjoint_step_rate(args.steps)}), flush=True)
         return
     if args.norm_only:
         print(json.dumps({"dispersion_norm": norm_bench()}), flush=True)
@@ -501,12 +554,16 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_step = ms / steps
     gcells = cells * steps / (ms * 1e-3) / 1e9
-    # every launch in the timed region is the tuned kernel; it reads and
-    # writes the six FP32 fields once per launch (48 B per cell), which is one
-    # step for the fused kernel and two for the two-step kernel
+    # every launch in the timed region is the tuned kernel, which advances
+    # every cell spp steps; its algorithmic bytes are 48 B per cell-update
+    # (each of the 6 FP32 components read once and written once per step)
+    # times the spp x cells cell-updates of a launch.  The kernel itself
+    # reads and writes the state once per launch (48 B per cell), which for
+    # the two-step kernel is half of that.
     launches = steps // spp
     ms_launch = ms / launches
-    bytes_per_launch = 48.0 * cells
+    bytes_per_launch = 48.0 * cells * spp
+    kernel_min_bytes = 48.0 * cells
     achieved = bytes_per_launch / (ms_launch * 1e-3) / 1e9
     if spp == 2:
         tl = lc["two_step"]
@@ -553,12 +610,18 @@ def main():
             "kernel": kname,
             "launch": lc,
             "bytes_per_launch": bytes_per_launch,
+            "cell_updates_per_launch": cells * spp,
+            "kernel_state_bytes_per_launch": kernel_min_bytes,
+            "kernel_state_GBs": round(kernel_min_bytes / (ms_launch * 1e-3) / 1e9, 1),
             "ms_per_launch": round(ms_launch, 5),
         },
         "cpu_baseline": None,
     }
     if not args.no_adj:
         line["fwd_adj"] = fwd_adj_ratio()
+        torch.cuda.empty_cache()
+        line["adjoint_512x256x256"] = adjoint_step_rate()
+        torch.cuda.empty_cache()
     if not args.no_extra:
         line["fp64_512x256x256"] = fp64_step()
         torch.cuda.empty_cache()

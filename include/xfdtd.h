@@ -400,21 +400,26 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
  *     height 4/8/16 (16: FP32), 32-column tiles as well when a box's nx
  *     leaves a 64-column tile at most half used, z-split 1/2/4 and the
  *     z-split of the step cost model below, persistent grid of 1x/2x the CU
- *     count or one workgroup per item) with steps that read the state and
- *     write only the scratch arrays, keeps the fastest, and caches it per
- *     set of box shapes (force = 1 re-times).  best_ms (nullable) receives
- *     the best time per step (-1 when taken from the cache).  Synchronises
- *     the stream; on failure the previous configuration stays.
+ *     count or one workgroup per work-list slot; for FP32 also the two-step
+ *     kernel on 32 x 8 and 32 x 16 tiles with z-split 1, 2 or 0) with
+ *     launches that read the state and write only the scratch arrays, keeps
+ *     the fastest per step, and caches it per set of box shapes (force = 1
+ *     re-times).  best_ms (nullable) receives the best time per step (-1
+ *     when taken from the cache).  Synchronises the stream; on failure the
+ *     previous configuration stays.
  * xfdtd_batch_set_config / get_config: choose / report the configuration:
- *     tile_x 64 or 32, tile_y 4, 8 or 16 (16: FP32 only), zsplit 1..1024
- *     (each box is cut into z-chunks of ceil(nz / zsplit) >= 4 planes),
- *     grid >= 0 (0 = one workgroup per work-list slot); nitems = work-list
- *     length in slots (0 before binding): the tiles x z-chunks of every
- *     box, dealt to the 8 XCDs in runs of neighbouring tiles with balanced
- *     plane counts, padded with empty slots where an XCD's share is short.  XFDTD_EINVAL for any other value.  The
- *     untuned default: tile_x 32 only when every box has nx <= 32, tile_y 8,
- *     the z-split minimising max(total plane iterations / resident
- *     workgroups, longest work item), grid 0.
+ *     tile_x 64 or 32, tile_y 4, 8 or 16 (16: FP32 only), zsplit 0..1024
+ *     (zsplit >= 1: each box is cut into z-chunks of ceil(nz / zsplit) >= 4
+ *     planes; 0: each box gets 1 to 4 chunks, chosen on the host by a
+ *     list-scheduling model of the work list below), grid >= 0 (0 = one
+ *     workgroup per work-list slot); nitems = work-list length in slots (0
+ *     before binding): the tiles x z-chunks of every box, dealt to the 8
+ *     XCDs in runs of neighbouring tiles with balanced plane counts, each
+ *     XCD's share longest first, padded with empty slots where an XCD's
+ *     share is short.  XFDTD_EINVAL for any other value.  The untuned
+ *     default: tile_x 32 only when every box has nx <= 32, tile_y 8, the
+ *     z-split minimising max(total plane iterations / resident workgroups,
+ *     longest work item), grid 0, one step per launch.
  * xfdtd_batch_run: n >= 0 steps of every box through the cached graph (the
  *     graph is re-captured when n or the configuration changes); the result
  *     is in the bound fields when the queued work completes.

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <queue>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -68,8 +69,12 @@ struct xfdtd_batch_s {
     std::string key;
     // batched gradient: adjoint work list, per-item gradient sums, per-box
     // item ranges, scales and accumulators
-    int2 *d_aitems = nullptr;
+    int2 *d_aitems = nullptr;  // per box contiguous (partial sums follow it)
     int naitems = 0;
+    int *d_aorder = nullptr;  // dispatch slots: item numbers, -1 for none
+    int naslots = 0;
+    std::vector<int> azc;  // adjoint z-chunk per box
+    std::vector<int> fzc;  // forward z-chunk per box (of the built work list)
     double *d_apart = nullptr;
     int *d_afirst = nullptr;
     double *d_scale = nullptr, *d_grad = nullptr;
@@ -221,10 +226,125 @@ int run_length(double total_cost, double items)
     return std::max(1, (int)(total_cost / 128.0 / per_item));
 }
 
+// Finish time of the dispatch order `order` when each XCD runs `per_xcd`
+// workgroups at a time and a workgroup takes the XCD's next slot as soon as
+// it is free (items of equal cost take equal time), and how many workgroups
+// finish at that time.
+std::pair<double, int> simulate_finish(const std::vector<int> &order, const std::vector<double> &cost, int per_xcd)
+{
+    double worst = 0;
+    int at = 0;
+    for (int x = 0; x < 8; ++x) {
+        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+        for (int i = 0; i < per_xcd; ++i) q.push(0.0);
+        for (size_t s = (size_t)x; s < order.size(); s += 8) {
+            if (order[s] < 0) continue;
+            const double t = q.top();
+            q.pop();
+            q.push(t + cost[(size_t)order[s]]);
+        }
+        while (!q.empty()) {
+            const double t = q.top();
+            q.pop();
+            if (t > worst) {
+                worst = t;
+                at = 1;
+            } else if (t == worst) {
+                ++at;
+            }
+        }
+    }
+    return {worst, at};
+}
+
+// Work list of the forward kernels with z-chunks zc[i] per box: items in
+// tile order, their costs and the dispatch order.  False if the list is too
+// long for 32-bit item numbers.
+bool forward_list(const xfdtd_batch_s *b, const std::vector<int> &zc, int warm, std::vector<int2> &all,
+                  std::vector<double> &cost, std::vector<int> &order)
+{
+    const int tx = b->cfg.tile_x, ty = b->cfg.tile_y;
+    all.clear();
+    cost.clear();
+    std::vector<int> run;
+    double total = 0, count = 0;
+    for (size_t i = 0; i < b->g.size(); ++i) {
+        const xfdtd_grid &g = b->g[i];
+        const double tiles = (double)((g.nx + tx - 1) / tx) * (double)((g.ny + ty - 1) / ty);
+        const int64_t nzc = (g.nz + zc[i] - 1) / zc[i];
+        total += tiles * ((double)g.nz + (double)nzc * warm);
+        count += tiles * (double)nzc;
+    }
+    if (count > 0x3fffffff) return false;
+    const int run_len = run_length(total, count);
+    for (size_t i = 0; i < b->g.size(); ++i) {
+        const xfdtd_grid &g = b->g[i];
+        box_items((int)i, (int)((g.nx + tx - 1) / tx), (int)((g.ny + ty - 1) / ty), (int)g.nz, zc[i], warm, run_len,
+                  all, cost, run);
+    }
+    order = xcd_schedule(cost, run);
+    return true;
+}
+
+// Per-box z-chunks of z-split 0: starting from whole-depth marches, one box
+// at a time gets one more chunk (up to 4) while that shortens the modelled
+// finish time of the dispatch order, or keeps it and has fewer workgroups
+// finish last.  Splitting a box costs its warm-up planes once more per chunk
+// but gives the schedule shorter items to fill in with.
+std::vector<int> model_chunks(const xfdtd_batch_s *b, int warm, int per_xcd)
+{
+    const size_t m = b->g.size();
+    std::vector<int> nch(m, 1), zc(m);
+    auto zc_of = [&]() {
+        for (size_t i = 0; i < m; ++i) zc[i] = (int)box_zchunk(b->g[i], nch[i]);
+    };
+    zc_of();
+    if (m > 256) return zc;  // the search is quadratic in the box count
+    std::vector<int2> all;
+    std::vector<double> cost;
+    std::vector<int> order;
+    auto score = [&]() -> std::pair<double, int> {
+        zc_of();
+        if (!forward_list(b, zc, warm, all, cost, order)) return {INFINITY, 0};
+        return simulate_finish(order, cost, per_xcd);
+    };
+    std::pair<double, int> cur = score();
+    for (int it = 0; it < 32; ++it) {
+        std::pair<double, int> best = cur;
+        size_t arg = m;
+        for (size_t i = 0; i < m; ++i) {
+            if (nch[i] >= 4 || box_zchunk(b->g[i], nch[i] + 1) == box_zchunk(b->g[i], nch[i])) continue;
+            ++nch[i];
+            const std::pair<double, int> sc = score();
+            --nch[i];
+            if (sc < best) {
+                best = sc;
+                arg = i;
+            }
+        }
+        if (arg == m) break;
+        ++nch[arg];
+        cur = best;
+    }
+    zc_of();
+    return zc;
+}
+
 template <typename T>
 int build_t(xfdtd_batch_t b)
 {
     const int ty = b->cfg.tile_y;
+    // warm-up planes of a z-chunk: 3 for the one-step march, 10 for two steps
+    const int warm = b->cfg.spp == 2 ? 10 : 3;
+    std::vector<int> zc(b->g.size());
+    if (b->cfg.zsplit == 0) {
+        const int occ = b->cfg.spp == 2 ? blocked2_occupancy<T>(b->cfg.tile_x, ty)
+                                        : fused_occupancy<T>(b->cfg.tile_x, ty);
+        zc = model_chunks(b, warm, std::max(1, cus() / 8) * std::max(1, occ));
+    } else {
+        for (size_t i = 0; i < b->g.size(); ++i) zc[i] = (int)box_zchunk(b->g[i], b->cfg.zsplit);
+    }
+    b->fzc = zc;
     std::vector<BoxDesc<T>> descs((size_t)b->m);
     for (int64_t i = 0; i < b->m; ++i) {
         const xfdtd_grid &g = b->g[i];
@@ -236,31 +356,17 @@ int build_t(xfdtd_batch_t b)
         d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
         const double sp[3] = {g.dx, g.dy, g.dz};
         d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
-        d.zchunk = (int)box_zchunk(g, b->cfg.zsplit);
+        d.zchunk = zc[(size_t)i];
         d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
         d.nty = (int)((g.ny + ty - 1) / ty);
         d.pad = 0;
     }
-    // warm-up planes of a z-chunk: 3 for the one-step march, 10 for two steps
-    const int warm = b->cfg.spp == 2 ? 10 : 3;
-    double total = 0, count = 0;
-    for (const BoxDesc<T> &d : descs) {
-        const double tiles = (double)d.ntx * d.nty;
-        const int nzc = (d.d.nz + d.zchunk - 1) / d.zchunk;
-        total += tiles * ((double)d.d.nz + (double)nzc * warm);
-        count += tiles * nzc;
-    }
-    if (count > 0x3fffffff) return set_error(XFDTD_EINVAL, "too many work items");
-    const int run_len = run_length(total, count);
     std::vector<int2> all;
     std::vector<double> cost;
-    std::vector<int> run;
-    for (int64_t i = 0; i < b->m; ++i) {
-        const BoxDesc<T> &d = descs[i];
-        box_items((int)i, d.ntx, d.nty, d.d.nz, d.zchunk, warm, run_len, all, cost, run);
-    }
+    std::vector<int> order;
+    if (!forward_list(b, zc, warm, all, cost, order)) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int2> items;
-    for (int j : xcd_schedule(cost, run)) items.push_back(j < 0 ? make_int2(-1, -1) : all[j]);
+    for (int j : order) items.push_back(j < 0 ? make_int2(-1, -1) : all[j]);
     if (items.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     if (b->d_boxes) hipFree(b->d_boxes);
     if (b->d_items) hipFree(b->d_items);
@@ -419,8 +525,8 @@ void xfdtd_batch_destroy(xfdtd_batch_t b)
     drop_graph(b);
     if (b->d_boxes) hipFree(b->d_boxes);
     if (b->d_items) hipFree(b->d_items);
-    for (void *p : {(void *)b->d_aitems, (void *)b->d_apart, (void *)b->d_afirst, (void *)b->d_scale,
-                    (void *)b->d_grad})
+    for (void *p : {(void *)b->d_aitems, (void *)b->d_aorder, (void *)b->d_apart, (void *)b->d_afirst,
+                    (void *)b->d_scale, (void *)b->d_grad})
         if (p) hipFree(p);
     if (b->capture) hipStreamDestroy(b->capture);
     if (b->aux) hipStreamDestroy(b->aux);
@@ -464,7 +570,7 @@ int xfdtd_batch_set_config(xfdtd_batch_t b, int tile_x, int tile_y, int zsplit, 
 {
     return guarded([&]() -> int {
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
-        if ((tile_x != 32 && tile_x != 64) || (tile_y != 4 && tile_y != 8 && tile_y != 16) || zsplit < 1 ||
+        if ((tile_x != 32 && tile_x != 64) || (tile_y != 4 && tile_y != 8 && tile_y != 16) || zsplit < 0 ||
             zsplit > 1024 || grid < 0 || (tile_y == 16 && b->dtype != XFDTD_F32))
             return set_error(XFDTD_EINVAL, "bad configuration");
         b->cfg.tile_x = tile_x;
@@ -551,10 +657,11 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             }
         }
         // FP32: the two-step kernel on 32-column tiles, whole-depth or split
-        // z-marches (its chunks start with 10 warm-up planes)
+        // z-marches (its chunks start with 10 warm-up planes), or per-box
+        // chunks from the schedule model (z-split 0)
         if (b->dtype == XFDTD_F32)
             for (int ty : {8, 16})
-                for (int zs : {1, 2})
+                for (int zs : {1, 2, 0})
                     for (int gm : {0, 1}) {
                         Config c;
                         c.tile_x = 32;
@@ -728,7 +835,7 @@ BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, cons
     d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
     const double sp[3] = {g.dx, g.dy, g.dz};
     d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
-    d.zchunk = (int)box_zchunk(g, b->cfg.zsplit);
+    d.zchunk = b->fzc.size() == b->g.size() ? b->fzc[(size_t)i] : (int)box_zchunk(g, std::max(1, b->cfg.zsplit));
     d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
     d.nty = (int)((g.ny + b->cfg.tile_y - 1) / b->cfg.tile_y);
     d.pad = 0;
@@ -771,50 +878,97 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
     for (int c = 0; c < 3; ++c) a.en[c] = en[c];
     a.d = f.d;
     a.w = f.w;
-    a.zchunk = f.zchunk;
+    a.zchunk = b->azc.empty() ? f.zchunk : b->azc[(size_t)i];
     a.ntx = (int)((b->g[i].nx + b->atx - 1) / b->atx);
     a.nty = (int)((b->g[i].ny + adj_tile(b) - 1) / adj_tile(b));
     a.pad = 0;
     return a;
 }
 
-// adjoint work list (tile height adj_tile), item ranges per box, scales
+// Adjoint work list (tile atx x adj_tile): per-box contiguous items, their
+// dispatch order, item ranges per box and gradient scales.  The adjoint's
+// z-split is its own: the one whose dispatch order finishes first in the
+// list-scheduling model (chunks cost their planes plus 4 warm-up iterations;
+// CUs x resident workgroups run at once), fewer chunks on ties.
 template <typename T>
 int build_adjoint(xfdtd_batch_t b)
 {
+    const int aty = adj_tile(b);
+    const int occ = std::max(1, adjoint_occupancy<T>(b->atx, aty));
+    const int per_xcd = std::max(1, cus() / 8) * occ;
+    const int warm = 4;
     std::vector<int2> items;
+    std::vector<double> cost;
+    std::vector<int> run, order;
+    auto make = [&](int zs) {
+        items.clear();
+        cost.clear();
+        run.clear();
+        b->azc.assign((size_t)b->m, 1);
+        double total = 0, count = 0;
+        for (int64_t i = 0; i < b->m; ++i) {
+            const xfdtd_grid &g = b->g[i];
+            const int zc = (int)box_zchunk(g, zs);
+            b->azc[(size_t)i] = zc;
+            const double tiles = (double)((g.nx + b->atx - 1) / b->atx) * (double)((g.ny + aty - 1) / aty);
+            const int nzc = (int)((g.nz + zc - 1) / zc);
+            total += tiles * ((double)g.nz + (double)nzc * warm);
+            count += tiles * nzc;
+        }
+        if (count > 0x3fffffff) return false;
+        const int run_len = run_length(total, count);
+        for (int64_t i = 0; i < b->m; ++i) {
+            const xfdtd_grid &g = b->g[i];
+            box_items((int)i, (int)((g.nx + b->atx - 1) / b->atx), (int)((g.ny + aty - 1) / aty), (int)g.nz,
+                      b->azc[(size_t)i], warm, run_len, items, cost, run);
+        }
+        order = xcd_schedule(cost, run);
+        return true;
+    };
+    int best_zs = 1;
+    double best = INFINITY;
+    for (int zs : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        if (!make(zs)) continue;
+        const double t = simulate_finish(order, cost, per_xcd).first;
+        if (t < best * (1.0 - 1e-9)) {
+            best = t;
+            best_zs = zs;
+        }
+    }
+    if (!make(best_zs)) return set_error(XFDTD_EINVAL, "too many work items");
+    if (order.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int> first;
     std::vector<double> scale;
-    Fields<T> z;
-    for (int c = 0; c < 6; ++c) z.c[c] = nullptr;
-    T *en0[3] = {nullptr, nullptr, nullptr};
     for (int64_t i = 0; i < b->m; ++i) {
-        const AdjDesc<T> a = adj_desc<T>(b, i, z, z, en0);
-        first.push_back((int)items.size());
-        const int nzc = (a.d.nz + a.zchunk - 1) / a.zchunk;
-        const int64_t nt = (int64_t)a.ntx * a.nty * nzc;
-        for (int64_t t = 0; t < nt; ++t) items.push_back(make_int2((int)i, (int)t));
         const double sp[3] = {b->g[i].dx, b->g[i].dy, b->g[i].dz};
         for (int j = 0; j < 12; ++j) scale.push_back(b->dt[i] / sp[j / 4]);
     }
-    first.push_back((int)items.size());
-    for (void *p : {(void *)b->d_aitems, (void *)b->d_apart, (void *)b->d_afirst, (void *)b->d_scale,
-                    (void *)b->d_grad})
+    for (size_t j = 0; j < items.size(); ++j)
+        while ((int64_t)first.size() <= items[j].x) first.push_back((int)j);
+    while ((int64_t)first.size() <= b->m) first.push_back((int)items.size());
+    for (void *p : {(void *)b->d_aitems, (void *)b->d_aorder, (void *)b->d_apart, (void *)b->d_afirst,
+                    (void *)b->d_scale, (void *)b->d_grad})
         if (p) hipFree(p);
     b->d_aitems = nullptr;
+    b->d_aorder = nullptr;
     b->d_apart = nullptr;
     b->d_afirst = nullptr;
     b->d_scale = nullptr;
     b->d_grad = nullptr;
-    BTRY(hipMalloc((void **)&b->d_aitems, sizeof(int2) * items.size()), "hipMalloc");
-    BTRY(hipMalloc((void **)&b->d_apart, sizeof(double) * 12 * items.size()), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_aitems, sizeof(int2) * std::max<size_t>(1, items.size())), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_aorder, sizeof(int) * std::max<size_t>(1, order.size())), "hipMalloc");
+    BTRY(hipMalloc((void **)&b->d_apart, sizeof(double) * 12 * std::max<size_t>(1, items.size())), "hipMalloc");
     BTRY(hipMalloc((void **)&b->d_afirst, sizeof(int) * first.size()), "hipMalloc");
     BTRY(hipMalloc((void **)&b->d_scale, sizeof(double) * scale.size()), "hipMalloc");
     BTRY(hipMalloc((void **)&b->d_grad, sizeof(double) * scale.size()), "hipMalloc");
-    BTRY(hipMemcpy(b->d_aitems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    if (!items.empty())
+        BTRY(hipMemcpy(b->d_aitems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice), "hipMemcpy");
+    if (!order.empty())
+        BTRY(hipMemcpy(b->d_aorder, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice), "hipMemcpy");
     BTRY(hipMemcpy(b->d_afirst, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice), "hipMemcpy");
     BTRY(hipMemcpy(b->d_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice), "hipMemcpy");
     b->naitems = (int)items.size();
+    b->naslots = (int)order.size();
     return XFDTD_OK;
 }
 
@@ -1029,16 +1183,14 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
         BTRY(hipEventRecord(ev_rec(k), aux), "hipEventRecord");
         return XFDTD_OK;
     };
-    // adjoint grid: the tuned persistent size if one is set (and the adjoint
-    // tiles are as wide as the forward's), else one workgroup per item
-    const int ga = (b->cfg.grid > 0 && b->cfg.grid < b->naitems && b->atx == b->cfg.tile_x) ? b->cfg.grid
-                                                                                        : b->naitems;
+    // adjoint grid: one workgroup per dispatch slot
+    const int ga = b->naslots;
     bool first = true;
     for (int64_t k = nck - 1; k >= 0 && n > 0; --k) {
         if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, ev_rec(k), 0), "hipStreamWaitEvent");
         for (int64_t l = al[k]; l < aend(k); ++l) {
-            hipError_t e = launch_batched_adjoint<T>(d_a + aoff[(size_t)l], b->d_aitems, b->naitems, b->d_apart,
-                                                     first ? 0 : 1, b->atx, adj_tile(b), ga, mainS);
+            hipError_t e = launch_batched_adjoint<T>(d_a + aoff[(size_t)l], b->d_aitems, b->d_aorder, b->naslots,
+                                                     b->d_apart, first ? 0 : 1, b->atx, adj_tile(b), ga, mainS);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
             first = false;
         }

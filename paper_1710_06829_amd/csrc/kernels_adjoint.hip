@@ -380,26 +380,26 @@ __global__ __launch_bounds__(C::THREADS) void adjoint_step_kernel(
                        partials + (int64_t)blockIdx.x * 12, accumulate);
 }
 
-// Batched adjoint step: work item i is tile items[i].y of box items[i].x;
-// its 12 gradient sums live at partials[12 i] (the item list is fixed for a
-// batch, so the sums accumulate per item across steps).
+// Batched adjoint step: work item j is tile items[j].y of box items[j].x
+// (each box's items contiguous); its 12 gradient sums live at partials[12 j]
+// (the item list is fixed for a batch, so the sums accumulate per item across
+// steps).  Workgroup w takes the slots w, w + gridDim.x, ... of `order`, which
+// holds item numbers in the host's dispatch order (-1: no work).
 template <typename T, typename C>
 __global__ __launch_bounds__(C::THREADS) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
                                                                      const int2 *__restrict__ items,
-                                                                     int nitems, double *__restrict__ partials,
+                                                                     const int *__restrict__ order, int nslots,
+                                                                     double *__restrict__ partials,
                                                                      int accumulate)
 {
     __shared__ AdjSmem<T, C> sm;
-    const int nb = gridDim.x, bid = blockIdx.x;
-    const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
-    const int slot = xcd * q + min(xcd, r) + (bid >> 3);
-    for (int base = 0; base < nitems; base += gridDim.x) {
-        const int i = base + slot;
-        if (i >= nitems) break;
-        const int2 it = items[i];
+    for (int i = blockIdx.x; i < nslots; i += gridDim.x) {
+        const int j = order[i];
+        if (j < 0) continue;
+        const int2 it = items[j];
         const AdjDesc<T> &b = boxes[it.x];
         adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
-                           partials + (int64_t)i * 12, accumulate);
+                           partials + (int64_t)j * 12, accumulate);
         __syncthreads();
     }
 }
@@ -517,15 +517,15 @@ hipError_t launch_reduce_partials(const double *partials, int nblocks, const Sca
 }
 
 template <typename T>
-hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, int nitems, double *partials,
-                                 int accumulate, int tile_x, int tile_y, int grid, hipStream_t s)
+hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, const int *order, int nslots,
+                                 double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s)
 {
-    if (nitems <= 0) return hipSuccess;
-    if (grid <= 0 || grid > nitems) grid = nitems;
+    if (nslots <= 0) return hipSuccess;
+    if (grid <= 0 || grid > nslots) grid = nslots;
     return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
         hipLaunchKernelGGL((batched_adjoint_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items,
-                           nitems, partials, accumulate);
+                           order, nslots, partials, accumulate);
         return hipGetLastError();
     });
 }
@@ -537,10 +537,10 @@ hipError_t launch_reduce_boxes(const double *partials, const int *first, int nbo
     return hipGetLastError();
 }
 
-template hipError_t launch_batched_adjoint<float>(const AdjDesc<float> *, const int2 *, int, double *, int, int,
-                                                  int, int, hipStream_t);
-template hipError_t launch_batched_adjoint<double>(const AdjDesc<double> *, const int2 *, int, double *, int, int,
-                                                   int, int, hipStream_t);
+template hipError_t launch_batched_adjoint<float>(const AdjDesc<float> *, const int2 *, const int *, int, double *,
+                                                  int, int, int, int, hipStream_t);
+template hipError_t launch_batched_adjoint<double>(const AdjDesc<double> *, const int2 *, const int *, int,
+                                                   double *, int, int, int, int, hipStream_t);
 template hipError_t launch_adjoint<float>(const Fields<float> &, const Fields<float> &, const float *const[3],
                                           Dims, const Weights<float> &, int, int, int, double *, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const Fields<double> &, const Fields<double> &,

@@ -228,7 +228,8 @@ def test_batch_create_validates_every_box():
     assert B.lib().xfdtd_batch_run(h, 2) == -5
     assert B.lib().xfdtd_batch_tune(h, 0, None) == -5
     assert B.lib().xfdtd_batch_set_config(h, 64, 5, 1, 0) == -1
-    assert B.lib().xfdtd_batch_set_config(h, 64, 4, 0, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 64, 4, -1, 0) == -1
+    assert B.lib().xfdtd_batch_set_config(h, 64, 4, 0, 0) == 0  # 0: per-box z-chunks from the model
     assert B.lib().xfdtd_batch_set_config(h, 48, 4, 1, 0) == -1
     assert B.lib().xfdtd_batch_set_config(h, 64, 4, 2, 0) == 0
     assert B.lib().xfdtd_batch_set_config(h, 32, 16, 1, 0) == 0

@@ -32,7 +32,7 @@ def _small_batch(dtype, seed=700):
 
 
 @pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 0), (8, 4, 3), (4, 1, 1), (8, 2, 512), (4, 1, 0, 32),
-                                 (8, 2, 3, 32)])
+                                 (8, 2, 3, 32), (8, 0, 0), (4, 0, 5, 32)])
 @pytest.mark.parametrize("n", [6, 5])
 @pytest.mark.parametrize("graph", [True, False])
 def test_batch_matches_oracle_fp64(cfg, n, graph):
@@ -69,7 +69,7 @@ def test_batch_graph_replays_and_tuner_keeps_state_fp32():
             assert torch.equal(a, b), (i, shape)
 
 
-@pytest.mark.parametrize("cfg", [(8, 1, 0), (16, 2, 0), (8, 4, 3), (16, 1, 256)])
+@pytest.mark.parametrize("cfg", [(8, 1, 0), (16, 2, 0), (8, 4, 3), (16, 1, 256), (16, 0, 0), (8, 0, 7)])
 @pytest.mark.parametrize("graph", [True, False])
 def test_batch_two_steps_per_launch_equals_single_runs_fp32(cfg, graph):
     """Two steps per launch (FP32, 32-column tiles): every tile height,

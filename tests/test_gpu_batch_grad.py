@@ -32,7 +32,7 @@ def _boxes(seed):
 
 
 @pytest.mark.parametrize("n,seg", [(7, 0), (7, 3), (10, 2), (5, 1), (9, 9), (1, 0), (0, 0), (13, 1), (13, 2)])
-@pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 3), (4, 1, 0, 32)])
+@pytest.mark.parametrize("cfg", [(8, 1, 0), (4, 2, 3), (4, 1, 0, 32), (8, 0, 0)])
 def test_batch_grad_matches_oracle_fp64(n, seg, cfg):
     boxes = _boxes(900)
     t = [to_dev(f) for (_, f, _, _, _, _) in boxes]
