@@ -15,20 +15,31 @@ import numpy as np
 from . import fdtd  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfdtd_oracle.so")
+# XFDTD_ORACLE_LIB names another build of the C oracle (e.g. a sanitized one)
+LIB_PATH = os.environ.get("XFDTD_ORACLE_LIB") or os.path.join(_HERE, "libfdtd_oracle.so")
 SRC_PATH = os.path.join(_HERE, "fdtd_oracle.c")
 _lib = None
 
 
-def build_c_oracle(verbose: bool = False) -> str:
-    """Compile the plain-C oracle (gcc, OpenMP, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           SRC_PATH, "-o", LIB_PATH + ".tmp"]
+def build_c_oracle(verbose: bool = False, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the plain-C oracle (gcc, OpenMP, no FMA contraction) to `out`
+    (default: the in-tree library).  sanitize=True builds it with ROCm's clang
+    under AddressSanitizer and UBSan instead, for a process that preloads that
+    clang's ASan runtime (the sanitized host build of libxfdtd uses the same
+    one)."""
+    out = out or LIB_PATH
+    if sanitize:
+        cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libsan",
+               "-fno-omit-frame-pointer", SRC_PATH, "-o", out + ".tmp", "-lm"]
+    else:
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               SRC_PATH, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def c_oracle():

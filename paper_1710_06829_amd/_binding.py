@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libxfdtd.so")
+# XFDTD_LIB names another build of the same library (e.g. one whose host code
+# is built with sanitizers); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("XFDTD_LIB") or os.path.join(HERE, "libxfdtd.so")
 
 XFDTD_F32 = 1
 XFDTD_F64 = 2

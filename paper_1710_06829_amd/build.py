@@ -51,6 +51,53 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host-side sanitizers for the build variant below: each -fsanitize= applies
+# to the host compilation only (device code is built as in build()).
+HOST_SOURCES = ["host.cpp", "batch.cpp", "norm.cpp"]
+SAN_FLAGS = [
+    "-O1", "-g", "-Wno-unused-value",
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+]
+
+
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """libxfdtd with its host code (argument validation, work lists, tuning,
+    checkpoint schedules, the C ABI) built under AddressSanitizer and UBSan,
+    linked with the device objects of build() (compiled here if that build
+    has not run).  The result is loaded by a process that preloads ROCm
+    clang's ASan runtime and names it in XFDTD_LIB."""
+    os.makedirs(out_dir, exist_ok=True)
+
+    def host_obj(src: str) -> str:
+        obj = os.path.join(out_dir, src + ".san.o")
+        cmd = [HIPCC, *FLAGS, *SAN_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    def device_obj(src: str) -> str:
+        obj = os.path.join(BUILD, src + ".o")
+        return obj if os.path.exists(obj) else _compile(src)
+
+    os.makedirs(BUILD, exist_ok=True)
+    kernels = [s for s in SOURCES if s not in HOST_SOURCES]
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(host_obj, HOST_SOURCES)) + list(ex.map(device_obj, kernels))
+    out = os.path.join(out_dir, "libxfdtd_hostsan.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", *objs, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
