@@ -839,20 +839,31 @@ __global__ __launch_bounds__(C::THREADS) void blocked2_kernel(Fields<T> in, Fiel
 // i is tile items[i].y of box items[i].x (32-column tiles of the box's
 // tiling); a persistent grid walks the list as in batched_step_kernel.
 // parity 0: f -> s, 1: s -> f.
-template <typename T, typename C>
+// ONE: one workgroup per slot (gridDim.x == nitems), no item loop.  Without
+// a loop nothing stays live from one item to the next: the looping variant
+// keeps its lane positions across the loop and, at the 128 VGPRs that 15
+// waves per workgroup allow, spills some of them into the z-loop.
+template <typename T, typename C, bool ONE>
 __global__ __launch_bounds__(C::THREADS) void batched_blocked2_kernel(const BoxDesc<T> *__restrict__ boxes,
                                                                       const int2 *__restrict__ items, int nitems,
                                                                       int parity)
 {
     __shared__ Blk2Smem<T, C::P> sm;
-    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
-        const int2 it = items[i];
-        if (it.x < 0) continue;
+    if constexpr (ONE) {
+        const int2 it = items[blockIdx.x];
+        if (it.x < 0) return;
         const BoxDesc<T> &b = boxes[it.x];
-        const Fields<T> &in = parity ? b.s : b.f;
-        const Fields<T> &out = parity ? b.f : b.s;
-        blocked2_tile<T, C>(in, out, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
-        __syncthreads();  // LDS is reused by the next item
+        blocked2_tile<T, C>(parity ? b.s : b.f, parity ? b.f : b.s, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
+    } else {
+        for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+            const int2 it = items[i];
+            if (it.x < 0) continue;
+            const BoxDesc<T> &b = boxes[it.x];
+            const Fields<T> &in = parity ? b.s : b.f;
+            const Fields<T> &out = parity ? b.f : b.s;
+            blocked2_tile<T, C>(in, out, b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm);
+            __syncthreads();  // LDS is reused by the next item
+        }
     }
 }
 
@@ -973,8 +984,12 @@ hipError_t launch_batched2(const BoxDesc<T> *boxes, const int2 *items, int nitem
     if (grid <= 0 || grid > nitems) grid = nitems;
     return with_blk2<T>(32, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
-        hipLaunchKernelGGL((batched_blocked2_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items,
-                           nitems, parity);
+        if (grid == nitems)
+            hipLaunchKernelGGL((batched_blocked2_kernel<T, C, true>), dim3(grid), dim3(C::THREADS), 0, s, boxes,
+                               items, nitems, parity);
+        else
+            hipLaunchKernelGGL((batched_blocked2_kernel<T, C, false>), dim3(grid), dim3(C::THREADS), 0, s, boxes,
+                               items, nitems, parity);
         return hipGetLastError();
     });
 }
