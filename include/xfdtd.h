@@ -385,6 +385,53 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
                         void *const lam[6], double grad[12]);
 
 /*
+ * Instrumentation (not part of the method): what a handle has run, an
+ * algorithmic-bytes model and optional device timing.
+ *
+ * xfdtd_stats fields (counted since xfdtd_create or the last reset):
+ *   run_calls, steps    xfdtd_run calls and the steps they advanced;
+ *   in_place_steps      of those, unfused in-place steps (a Faraday and an
+ *                       Ampere launch each);
+ *   fused_launches      one-step out-of-place launches;
+ *   two_step_launches   two-step launches (two steps each), so that
+ *                       steps = in_place_steps + fused_launches
+ *                               + 2 two_step_launches;
+ *   graph_replays, graph_captures   of xfdtd_run's 32-step graph;
+ *   tunes               xfdtd_tune calls that timed candidates;
+ *   grad_forward_steps  steps of xfdtd_grad_forward;
+ *   adjoint_steps       adjoint steps (xfdtd_grad_backward,
+ *                       xfdtd_adjoint_step, xfdtd_adjoint_step_noalloc);
+ *   recomputed_steps    forward steps recomputed by xfdtd_grad_backward;
+ *   model_bytes         algorithmic HBM bytes of all these steps: 12 values
+ *                       per cell per forward step (run, checkpointed forward,
+ *                       recompute; each component read and written once) and
+ *                       15 per adjoint step, at the handle's dtype size;
+ *   elapsed_ms          with timing on: device time from the start of the
+ *                       first xfdtd_run after the reset to the end of the
+ *                       last (gaps between calls included); else -1;
+ *   gcells_per_s        with timing on: steps x cells / elapsed, in
+ *                       Gcell-updates/s; else -1.
+ * xfdtd_get_stats: fills *out (host); synchronises the stream when timing is
+ *     on and a run was timed.  xfdtd_reset_stats: zeroes the counters and
+ *     sets timing on (1) or off (0); with timing on each xfdtd_run records a
+ *     device event before and after its work (not inside a capture of the
+ *     caller's stream).  XFDTD_EINVAL for a null argument.
+ * XFDTD_LOG=1 in the environment prints configuration and tuning decisions
+ * (creation, tuning winners, graph captures, gradient schedules, batch work
+ * lists) to stderr; run, tune, gradient passes and each backward segment's
+ * recompute and adjoint are marked as roctx ranges (rocprofv3
+ * --marker-trace).
+ */
+typedef struct xfdtd_stats {
+    int64_t run_calls, steps, in_place_steps, fused_launches, two_step_launches;
+    int64_t graph_replays, graph_captures, tunes;
+    int64_t grad_forward_steps, adjoint_steps, recomputed_steps;
+    double model_bytes, elapsed_ms, gcells_per_s;
+} xfdtd_stats;
+int xfdtd_get_stats(xfdtd_t h, xfdtd_stats *out);
+int xfdtd_reset_stats(xfdtd_t h, int timing);
+
+/*
  * Batches: m independent periodic boxes of any sizes, each with its own
  * coefficients and time step (each box obeys the conventions above), advanced
  * together.  A step is one launch of a persistent kernel over a work list of

@@ -41,6 +41,14 @@ class StencilProblem(ctypes.Structure):
                 ("starts", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
 
 
+class Stats(ctypes.Structure):
+    """xfdtd_stats."""
+    _fields_ = [(n, ctypes.c_int64) for n in ("run_calls", "steps", "in_place_steps", "fused_launches",
+                                               "two_step_launches", "graph_replays", "graph_captures", "tunes",
+                                               "grad_forward_steps", "adjoint_steps", "recomputed_steps")] + \
+               [(n, ctypes.c_double) for n in ("model_bytes", "elapsed_ms", "gcells_per_s")]
+
+
 XFDTD_WEIGHT_UNIT = 0
 XFDTD_WEIGHT_AXIS = 1
 
@@ -77,6 +85,8 @@ SIGNATURES = {
     "xfdtd_divergence": ([_vp, _vp, _vp], _int),
     "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),
     "xfdtd_adjoint_step": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
+    "xfdtd_get_stats": ([_vp, ctypes.POINTER(Stats)], _int),
+    "xfdtd_reset_stats": ([_vp, _int], _int),
     "xfdtd_adjoint_step_noalloc": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
                                    _int),
     "xfdtd_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),

@@ -27,6 +27,10 @@ FLAGS = [
 ]
 
 
+# roctx ranges around run, tune and the gradient phases (ROCm's roctx library)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -41,7 +45,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -89,7 +93,7 @@ def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
         objs = list(ex.map(host_obj, HOST_SOURCES)) + list(ex.map(device_obj, kernels))
     out = os.path.join(out_dir, "libxfdtd_hostsan.so")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
-           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", *objs, "-o", out]
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", *objs, *LIBS, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -367,6 +367,9 @@ int build_t(xfdtd_batch_t b)
     if (!forward_list(b, zc, warm, all, cost, order)) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int2> items;
     for (int j : order) items.push_back(j < 0 ? make_int2(-1, -1) : all[j]);
+    xlog("batch of %lld boxes: %s %dx%d tiles, z-split %d, %zu items in %zu slots, grid %d",
+         (long long)b->m, b->cfg.spp == 2 ? "two-step" : "one-step", b->cfg.tile_x, ty, b->cfg.zsplit, all.size(),
+         order.size(), b->cfg.grid);
     if (items.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     if (b->d_boxes) hipFree(b->d_boxes);
     if (b->d_items) hipFree(b->d_items);
@@ -620,6 +623,7 @@ int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zspli
 int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
 {
     return guarded([&]() -> int {
+        Range range("xfdtd_batch_tune");
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
         if (!force) {
@@ -727,6 +731,9 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             std::lock_guard<std::mutex> lk(g_cache_mu);
             g_cache[b->key] = bestc;
         }
+        xlog("batch tune: %zu candidates, best %s %dx%d tiles, z-split %d, grid %d, %.2f us per step", cands.size(),
+             bestc.spp == 2 ? "two-step" : "one-step", bestc.tile_x, bestc.tile_y, bestc.zsplit, bestc.grid,
+             best * 1e3);
         if (best_ms) *best_ms = best;
         return build(b);
     });
@@ -735,6 +742,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
 int xfdtd_batch_run(xfdtd_batch_t b, int64_t n)
 {
     return guarded([&]() -> int {
+        Range range("xfdtd_batch_run");
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
         if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
@@ -766,6 +774,7 @@ int xfdtd_batch_run(xfdtd_batch_t b, int64_t n)
 int xfdtd_batch_run_eager(xfdtd_batch_t b, int64_t n)
 {
     return guarded([&]() -> int {
+        Range range("xfdtd_batch_run");
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
         if (n < 0) return set_error(XFDTD_EINVAL, "n must be >= 0");
@@ -936,6 +945,8 @@ int build_adjoint(xfdtd_batch_t b)
         }
     }
     if (!make(best_zs)) return set_error(XFDTD_EINVAL, "too many work items");
+    xlog("batched adjoint: %dx%d tiles, z-split %d (modelled finish %.0f plane iterations), %zu items in %zu slots",
+         b->atx, aty, best_zs, best, items.size(), order.size());
     if (order.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int> first;
     std::vector<double> scale;
@@ -1308,6 +1319,7 @@ int xfdtd_batch_grad_workspace(xfdtd_batch_t b, int64_t n, int64_t seg, uint64_t
 int xfdtd_batch_grad_forward(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, const uint64_t *ws_bytes)
 {
     return guarded([&]() -> int {
+        Range range("xfdtd_batch_grad_forward");
         seg = bseg(n, seg);
         int rc = check_bws(b, n, seg, ws, ws_bytes);
         if (rc) return rc;
@@ -1326,6 +1338,7 @@ int xfdtd_batch_grad_backward(xfdtd_batch_t b, int64_t n, int64_t seg, void *con
                               void *const *lam, double *grad)
 {
     return guarded([&]() -> int {
+        Range range("xfdtd_batch_grad_backward");
         seg = bseg(n, seg);
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!lam || !grad) return set_error(XFDTD_EINVAL, "null argument");

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/xfdtd.h"
 #include "xfdtd_internal.h"
 
@@ -46,6 +48,29 @@ int xfdtd::set_error(int code, const char *fmt, ...)
     va_end(ap);
     return code;
 }
+
+bool xfdtd::log_on()
+{
+    static const bool on = [] {
+        const char *v = getenv("XFDTD_LOG");
+        return v && atoi(v) > 0;
+    }();
+    return on;
+}
+
+void xfdtd::xlog(const char *fmt, ...)
+{
+    if (!log_on()) return;
+    char line[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(line, sizeof line, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[xfdtd] %s\n", line);
+}
+
+xfdtd::Range::Range(const char *name) noexcept { roctxRangePushA(name); }
+xfdtd::Range::~Range() { roctxRangePop(); }
 
 namespace {
 
@@ -340,6 +365,16 @@ struct xfdtd_s {
     hipStream_t cap;
     hipGraphExec_t gexec;
     std::array<uintptr_t, 20> graph_key;
+    // instrumentation: counters, the launches of one replay of the run graph,
+    // and the events that time xfdtd_run when timing is on
+    struct RunCounts {
+        int64_t in_place = 0, fused = 0, two_step = 0;
+    };
+    xfdtd_stats st{};
+    RunCounts graph_counts;
+    bool timing = false, t0_set = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int ev_device = -1;
 };
 
 namespace {
@@ -387,7 +422,7 @@ const Weights<T> &weights_of(const xfdtd_s *h)
 }
 
 template <typename T>
-int run_t(xfdtd_t h, int64_t n, hipStream_t st)
+int run_t(xfdtd_t h, int64_t n, hipStream_t st, xfdtd_s::RunCounts &cnt)
 {
     const Dims d = dims_of(h->g);
     const Weights<T> &w = weights_of<T>(h);
@@ -396,6 +431,7 @@ int run_t(xfdtd_t h, int64_t n, hipStream_t st)
         for (int64_t s = 0; s < n; ++s) {
             HIP_TRY(launch_faraday<T>(f, d, w, st), "faraday launch");
             HIP_TRY(launch_ampere<T>(f, d, w, st), "ampere launch");
+            ++cnt.in_place;
         }
         return XFDTD_OK;
     }
@@ -412,12 +448,14 @@ int run_t(xfdtd_t h, int64_t n, hipStream_t st)
         auto fused = [&]() -> int {
             HIP_TRY(launch_fused<T>(a, b, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
             std::swap(a, b);
+            ++cnt.fused;
             return XFDTD_OK;
         };
         int rc = XFDTD_OK;
         if ((n & 1) && pairs % 2 == 0) {
             HIP_TRY(launch_faraday<T>(a, d, w, st), "faraday launch");
             HIP_TRY(launch_ampere<T>(a, d, w, st), "ampere launch");
+            ++cnt.in_place;
         } else if (n & 1) {
             rc = fused();
         } else if (pairs % 2 == 1) {
@@ -430,6 +468,7 @@ int run_t(xfdtd_t h, int64_t n, hipStream_t st)
             HIP_TRY(launch_blocked2<T>(a, b, d, w, h->btile_x, h->btile_y, h->bzchunk, st),
                     "two-step launch");
             std::swap(a, b);
+            ++cnt.two_step;
         }
         return XFDTD_OK;
     }
@@ -437,13 +476,42 @@ int run_t(xfdtd_t h, int64_t n, hipStream_t st)
     if (left & 1) {  // odd count: one in-place step keeps the result in `fields`
         HIP_TRY(launch_faraday<T>(f, d, w, st), "faraday launch");
         HIP_TRY(launch_ampere<T>(f, d, w, st), "ampere launch");
+        ++cnt.in_place;
         --left;
     }
     for (; left > 0; left -= 2) {
         HIP_TRY(launch_fused<T>(f, s, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
         HIP_TRY(launch_fused<T>(s, f, d, w, h->tile_x, h->tile_y, h->zchunk, st), "fused launch");
+        cnt.fused += 2;
     }
     return XFDTD_OK;
+}
+
+// The two events that time xfdtd_run, on the handle's device.
+int ensure_timing_events(xfdtd_s *h)
+{
+    if (h->t0 && h->t1 && h->ev_device == h->device) return XFDTD_OK;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != h->device) HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+    hipError_t e = hipSuccess;
+    for (hipEvent_t *ev : {&h->t0, &h->t1}) {
+        if (*ev) hipEventDestroy(*ev);
+        *ev = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(ev);
+    }
+    if (cur != h->device) hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "creating the timing events");
+    h->ev_device = h->device;
+    h->t0_set = false;
+    return XFDTD_OK;
+}
+
+// algorithmic HBM bytes of one step of `values` values per cell
+double model_bytes(const xfdtd_s *h, int64_t steps, int values)
+{
+    const double cells = (double)h->g.nx * (double)h->g.ny * (double)h->g.nz;
+    return (double)steps * cells * values * (h->dtype == XFDTD_F32 ? 4.0 : 8.0);
 }
 
 }  // namespace
@@ -492,7 +560,8 @@ int ensure_run_graph(xfdtd_s *h, F &&eager)
     drop_run_graph(h);
     if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreate");
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    const int rc = eager(kGraphSteps, h->cap);
+    xfdtd_s::RunCounts cnt;
+    const int rc = eager(kGraphSteps, h->cap, cnt);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap, &graph);
     if (rc) {
@@ -507,6 +576,10 @@ int ensure_run_graph(xfdtd_s *h, F &&eager)
         return hip_fail(e, "hipGraphInstantiate");
     }
     h->graph_key = key;
+    h->graph_counts = cnt;
+    ++h->st.graph_captures;
+    xlog("run graph captured: %lld steps (%lld one-step, %lld two-step launches, %lld in-place steps)",
+         (long long)kGraphSteps, (long long)cnt.fused, (long long)cnt.two_step, (long long)cnt.in_place);
     return XFDTD_OK;
 }
 
@@ -615,6 +688,10 @@ int tune_t(xfdtd_t h, double *best_ms)
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[tune_key(h)] = bestc;
     }
+    ++h->st.tunes;
+    xlog("tune %lldx%lldx%lld %s: %zu candidates, best %s %dx%d tiles, z-chunk %d, %.2f us per step",
+         (long long)h->g.nx, (long long)h->g.ny, (long long)h->g.nz, h->dtype == XFDTD_F32 ? "FP32" : "FP64",
+         cands.size(), bestc[0] == 2 ? "two-step" : "one-step", bestc[1], bestc[2], bestc[3], best * 1e3);
     if (best_ms) *best_ms = best;
     return XFDTD_OK;
 }
@@ -747,6 +824,11 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
         h->cap = nullptr;
         h->gexec = nullptr;
         h->graph_key = {};
+        xlog("create %lldx%lldx%lld %s: one-step %dx%d tiles, z-chunk %d; two-step %dx%d tiles, z-chunk %d; "
+             "%d step%s per pass; adjoint %dx%d tiles, z-chunk %d; run graph %s",
+             (long long)g->nx, (long long)g->ny, (long long)g->nz, dtype == XFDTD_F32 ? "FP32" : "FP64", h->tile_x,
+             h->tile_y, h->zchunk, h->btile_x, h->btile_y, h->bzchunk, h->spp, h->spp == 2 ? "s" : "", h->atile_x,
+             h->atile_y, h->azchunk, h->use_graph ? "on" : "off");
         *out = h;
         return XFDTD_OK;
     });
@@ -769,6 +851,8 @@ void xfdtd_destroy(xfdtd_t h)
         hipGraphExecDestroy(h->gexec);
     }
     if (h->cap) hipStreamDestroy(h->cap);
+    if (h->t0) hipEventDestroy(h->t0);
+    if (h->t1) hipEventDestroy(h->t1);
     delete h;
 }
 
@@ -884,23 +968,76 @@ int xfdtd_run(xfdtd_t h, int64_t n)
         int rc = check_bound(h);
         if (rc) return rc;
         if (n < 0) return fail(XFDTD_EINVAL, "n must be >= 0");
-        auto eager = [&](int64_t m, hipStream_t st) {
-            return h->dtype == XFDTD_F32 ? run_t<float>(h, m, st) : run_t<double>(h, m, st);
+        Range range("xfdtd_run");
+        auto eager = [&](int64_t m, hipStream_t st, xfdtd_s::RunCounts &cnt) {
+            return h->dtype == XFDTD_F32 ? run_t<float>(h, m, st, cnt) : run_t<double>(h, m, st, cnt);
         };
         // inside a capture of the caller's stream the launches go straight
         // into the caller's graph
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(hipStreamIsCapturing(h->stream, &cs), "hipStreamIsCapturing");
-        const int64_t units = h->use_graph && cs == hipStreamCaptureStatusNone ? n / kGraphSteps : 0;
+        const bool capturing = cs != hipStreamCaptureStatusNone;
+        const bool timed = h->timing && !capturing && n > 0;
+        if (timed) {
+            rc = ensure_timing_events(h);
+            if (rc) return rc;
+            if (!h->t0_set) HIP_TRY(hipEventRecord(h->t0, h->stream), "hipEventRecord");
+            h->t0_set = true;
+        }
+        const int64_t units = h->use_graph && !capturing ? n / kGraphSteps : 0;
+        xfdtd_s::RunCounts cnt;
         if (units > 0) {
             rc = ensure_run_graph(h, eager);
             if (rc) return rc;
             for (int64_t u = 0; u < units; ++u) HIP_TRY(hipGraphLaunch(h->gexec, h->stream), "hipGraphLaunch");
+            cnt.in_place = units * h->graph_counts.in_place;
+            cnt.fused = units * h->graph_counts.fused;
+            cnt.two_step = units * h->graph_counts.two_step;
+            h->st.graph_replays += units;
         }
         // the remaining steps (all of them without a graph) are launched
         // directly; each part leaves the result in the bound fields, and the
         // steps are the same kernels in the same order either way
-        return eager(n - units * kGraphSteps, h->stream);
+        rc = eager(n - units * kGraphSteps, h->stream, cnt);
+        if (rc) return rc;
+        if (timed) HIP_TRY(hipEventRecord(h->t1, h->stream), "hipEventRecord");
+        ++h->st.run_calls;
+        h->st.steps += n;
+        h->st.in_place_steps += cnt.in_place;
+        h->st.fused_launches += cnt.fused;
+        h->st.two_step_launches += cnt.two_step;
+        h->st.model_bytes += model_bytes(h, n, 12);
+        return XFDTD_OK;
+    });
+}
+
+int xfdtd_get_stats(xfdtd_t h, xfdtd_stats *out)
+{
+    return guarded([&]() -> int {
+        if (!h || !out) return fail(XFDTD_EINVAL, "null argument");
+        *out = h->st;
+        out->elapsed_ms = -1.0;
+        out->gcells_per_s = -1.0;
+        if (h->timing && h->t0_set) {
+            HIP_TRY(hipEventSynchronize(h->t1), "hipEventSynchronize");
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1), "hipEventElapsedTime");
+            const double cells = (double)h->g.nx * (double)h->g.ny * (double)h->g.nz;
+            out->elapsed_ms = ms;
+            out->gcells_per_s = ms > 0 ? (double)h->st.steps * cells / ((double)ms * 1e-3) / 1e9 : -1.0;
+        }
+        return XFDTD_OK;
+    });
+}
+
+int xfdtd_reset_stats(xfdtd_t h, int timing)
+{
+    return guarded([&]() -> int {
+        if (!h) return fail(XFDTD_EINVAL, "null handle");
+        h->st = xfdtd_stats{};
+        h->timing = timing != 0;
+        h->t0_set = false;
+        return XFDTD_OK;
     });
 }
 
@@ -910,6 +1047,7 @@ int xfdtd_tune(xfdtd_t h, int force, double *best_ms)
         const int rc = check_bound(h);
         if (rc) return rc;
         if (!h->have_scratch) return fail(XFDTD_ESTATE, "tuning times the fused step: bind scratch arrays");
+        Range range("xfdtd_tune");
         if (!force) {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(tune_key(h));
@@ -1337,7 +1475,12 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
 
     // recompute segment m on the second stream, keeping E of every step
     auto recompute = [&](int64_t m) -> int {
+        Range range("recompute segment");
         const int64_t s0 = m * seg, s1 = (s0 + seg < n) ? s0 + seg : n;
+        if (s1 - s0 > 1) {
+            h->st.recomputed_steps += s1 - s0 - 1;
+            h->st.model_bytes += model_bytes(h, s1 - s0 - 1, 12);
+        }
         Fields<T> in = state_at<T>(ws, fb, 6 * m);
         for (int64_t s = s0; s + 1 < s1; ++s) {
             Fields<T> out;
@@ -1358,6 +1501,7 @@ int grad_backward_t(xfdtd_t h, int64_t n, int64_t seg, char *ws, void *const lam
         Fields<T> ck = state_at<T>(ws, fb, 6 * m);
         if (m < nck - 2) HIP_TRY(hipStreamWaitEvent(mainS, ev_rec(m), 0), "hipStreamWaitEvent");
         // reverse through the segment
+        Range range("adjoint segment");
         for (int64_t s = s1 - 1; s >= s0; --s) {
             const T *en[3];
             if (s == s0) {
@@ -1436,10 +1580,15 @@ int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
         if (rc) return rc;
         if (h->dtype == XFDTD_F32) {
             const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
-            return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1);
+            rc = adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1);
+        } else {
+            const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
+            rc = adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
         }
-        const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
-        return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1);
+        if (rc) return rc;
+        ++h->st.adjoint_steps;
+        h->st.model_bytes += model_bytes(h, 1, 15);
+        return XFDTD_OK;
     });
 }
 
@@ -1465,10 +1614,15 @@ int xfdtd_adjoint_step_noalloc(xfdtd_t h, void *const lam_in[6], void *const lam
         // (nothing in the scratch needs to start at zero)
         if (h->dtype == XFDTD_F32) {
             const float *en[3] = {(const float *)e_n[0], (const float *)e_n[1], (const float *)e_n[2]};
-            return adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1, ws);
+            rc = adjoint_one<float>(h, as_fields<float>(lam_in), as_fields<float>(lam_out), en, grad, 0, 1, ws);
+        } else {
+            const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
+            rc = adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1, ws);
         }
-        const double *en[3] = {(const double *)e_n[0], (const double *)e_n[1], (const double *)e_n[2]};
-        return adjoint_one<double>(h, as_fields<double>(lam_in), as_fields<double>(lam_out), en, grad, 0, 1, ws);
+        if (rc) return rc;
+        ++h->st.adjoint_steps;  // counters only: nothing here allocates
+        h->st.model_bytes += model_bytes(h, 1, 15);
+        return XFDTD_OK;
     });
 }
 
@@ -1501,9 +1655,14 @@ int xfdtd_grad_forward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws_
             if (ranges_overlap(ws, wsb, h->fields[c], raw_field_bytes(h)))
                 return fail(XFDTD_EINVAL, "the workspace overlaps bound field %d", c);
         drop_tapes(h, ws, wsb);
+        Range range("xfdtd_grad_forward");
         rc = h->dtype == XFDTD_F32 ? grad_forward_t<float>(h, n, seg, (char *)ws)
                                    : grad_forward_t<double>(h, n, seg, (char *)ws);
         if (rc) return rc;
+        h->st.grad_forward_steps += n;
+        h->st.model_bytes += model_bytes(h, n, 12);
+        xlog("gradient forward pass: %lld steps, segments of %lld (%lld checkpoints)", (long long)n, (long long)seg,
+             (long long)(n > 0 ? (n + seg - 1) / seg : 0));
         if (h->tapes.size() >= kMaxTapes) h->tapes.erase(h->tapes.begin());
         h->tapes.push_back({(uintptr_t)ws, (uintptr_t)wsb, n, seg});
         return XFDTD_OK;
@@ -1536,8 +1695,16 @@ int xfdtd_grad_backward(xfdtd_t h, int64_t n, int64_t seg, void *ws, uint64_t ws
                                       "(a backward pass consumes it; run xfdtd_grad_forward again)",
                         (long long)n, (long long)seg);
         h->tapes.erase(it);
-        return h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
-                                     : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
+        Range range("xfdtd_grad_backward");
+        const int64_t before = h->st.recomputed_steps;
+        rc = h->dtype == XFDTD_F32 ? grad_backward_t<float>(h, n, seg, (char *)ws, lam, grad)
+                                   : grad_backward_t<double>(h, n, seg, (char *)ws, lam, grad);
+        if (rc) return rc;
+        h->st.adjoint_steps += n;
+        h->st.model_bytes += model_bytes(h, n, 15);
+        xlog("gradient backward pass: %lld adjoint steps, %lld steps recomputed beside them", (long long)n,
+             (long long)(h->st.recomputed_steps - before));
+        return XFDTD_OK;
     });
 }
 

@@ -210,6 +210,19 @@ int set_error(int code, const char *fmt, ...);
 // Runs the body of a C entry point: a C++ exception (a failed host
 // allocation in a std::vector or std::map, a std::system_error from a
 // mutex) becomes an error code instead of unwinding into the C caller.
+// Instrumentation.  log_on(): XFDTD_LOG=1 in the environment (read once);
+// xlog() prints one "[xfdtd] ..." line to stderr when it is set.  Range marks
+// a roctx range from construction to destruction (host time of the calls it
+// encloses; rocprofv3 --marker-trace records it).
+bool log_on();
+void xlog(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+struct Range {
+    explicit Range(const char *name) noexcept;
+    ~Range();
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
 template <typename F>
 int guarded(F &&f) noexcept
 {

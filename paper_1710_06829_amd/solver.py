@@ -166,6 +166,17 @@ class Solver:
                 "two_step": {"tile_x": u[1].value, "tile_y": u[2].value, "zchunk": u[3].value,
                              "workgroups": u[4].value}}
 
+    def stats(self):
+        """Counters of what this solver ran (xfdtd_get_stats) as a dict;
+        elapsed_ms and gcells_per_s are -1 unless timing is on."""
+        st = B.Stats()
+        B.check(B.lib().xfdtd_get_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in B.Stats._fields_}
+
+    def reset_stats(self, timing=False):
+        """Zero the counters; timing=True times xfdtd_run on the device."""
+        B.check(B.lib().xfdtd_reset_stats(self._h, int(bool(timing))))
+
     def weights(self):
         w = (ctypes.c_double * 15)()
         nw = ctypes.c_int()

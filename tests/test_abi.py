@@ -4,6 +4,8 @@ checks, weight folding) matches the oracle.  No GPU work is issued."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -418,3 +420,48 @@ def test_host_allocation_failure_is_an_error_code_not_an_exception():
     r = subprocess.run([sys.executable, "-c", _ALLOC_CHILD, ROOT], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "rc -1 out of host memory" in r.stdout, r.stdout + r.stderr[-2000:]
+
+
+def test_stats_of_a_fresh_handle_and_argument_errors():
+    """xfdtd_stats on a created, unbound handle: all counters zero, no timing
+    (-1); reset with timing on needs no device; null arguments are errors."""
+    rc, h = _create()
+    assert rc == 0
+    try:
+        st = B.Stats()
+        assert B.lib().xfdtd_get_stats(h, ctypes.byref(st)) == 0
+        assert st.steps == 0 and st.run_calls == 0 and st.model_bytes == 0.0
+        assert st.elapsed_ms == -1.0 and st.gcells_per_s == -1.0
+        assert B.lib().xfdtd_reset_stats(h, 1) == 0
+        assert B.lib().xfdtd_get_stats(h, ctypes.byref(st)) == 0 and st.elapsed_ms == -1.0
+        assert B.lib().xfdtd_get_stats(h, None) == -1
+        assert B.lib().xfdtd_get_stats(None, ctypes.byref(st)) == -1
+        assert B.lib().xfdtd_reset_stats(None, 0) == -1
+    finally:
+        B.lib().xfdtd_destroy(h)
+
+
+def test_log_prints_the_configuration_and_roctx_is_linked():
+    """XFDTD_LOG=1: xfdtd_create prints its launch configuration to stderr (a
+    child process, host only); the library links ROCm's roctx library for its
+    ranges."""
+    code = (
+        "import ctypes, sys\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from paper_1710_06829_amd import _binding as B\n"
+        "g = B.Grid(64, 48, 40, 1.0, 1.0, 1.0)\n"
+        "c = (ctypes.c_double * 12)(*([1.0, 0, 0, 0] * 3))\n"
+        "h = ctypes.c_void_p()\n"
+        "assert B.lib().xfdtd_create(ctypes.byref(g), 0.5, c, 1, 0, ctypes.byref(h)) == 0\n"
+        "B.lib().xfdtd_destroy(h)\n"
+    )
+    env = dict(os.environ, XFDTD_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert "[xfdtd] create 64x48x40 FP32" in r.stderr, r.stderr
+    r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, XFDTD_LOG="0"),
+                       capture_output=True, text=True, timeout=300)
+    assert "[xfdtd]" not in r.stderr
+    d = subprocess.run(["readelf", "-d", B.LIB_PATH], capture_output=True, text=True)
+    if d.returncode == 0:
+        assert "librocprofiler-sdk-roctx" in d.stdout
