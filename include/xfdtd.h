@@ -496,6 +496,16 @@ int xfdtd_batch_set_steps_per_pass(xfdtd_batch_t b, int steps);
 int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps);
 
 /*
+ * The batched adjoint's launch configuration, chosen by each
+ * xfdtd_batch_grad_backward (all 0 before the first): tile_x 32 or 64;
+ * tile_y 4, 8, or 12 (FP32 32-column tiles only); zsplit, the z-chunks per
+ * box; nslots, its dispatch slots.  The tile height and z-split come from a
+ * list-scheduling model of the work list (tile positions x planes per
+ * item).  XFDTD_EINVAL for a null handle.  Host only.
+ */
+int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *nslots);
+
+/*
  * Batched checkpointed gradients: the single-box schedule of
  * xfdtd_grad_forward / xfdtd_grad_backward for every box of the batch at once
  * (same n and seg for all boxes), one batched launch per step.  As there,

@@ -102,6 +102,7 @@ SIGNATURES = {
     "xfdtd_batch_run": ([_vp, _i64], _int),
     "xfdtd_batch_set_steps_per_pass": ([_vp, _int], _int),
     "xfdtd_batch_get_steps_per_pass": ([_vp, ctypes.POINTER(_int)], _int),
+    "xfdtd_batch_get_adjoint_config": ([_vp] + [ctypes.POINTER(_int)] * 4, _int),
     "xfdtd_batch_run_eager": ([_vp, _i64], _int),
     "xfdtd_batch_grad_workspace": ([_vp, _i64, _i64, ctypes.POINTER(ctypes.c_uint64)], _int),
     "xfdtd_batch_grad_forward": ([_vp, _i64, _i64, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)], _int),

@@ -84,6 +84,13 @@ class Batch:
         return {"tile_x": v[0].value, "tile_y": v[1].value, "zsplit": v[2].value, "grid": v[3].value,
                 "items": v[4].value, "steps_per_pass": spp.value}
 
+    def adjoint_config(self):
+        """The batched adjoint's tiling of the last grad_backward (zeros
+        before the first)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        B.check(B.lib().xfdtd_batch_get_adjoint_config(self._h, *[ctypes.byref(x) for x in v]))
+        return {"tile_x": v[0].value, "tile_y": v[1].value, "zsplit": v[2].value, "slots": v[3].value}
+
     def run(self, n, graph=True):
         fn = B.lib().xfdtd_batch_run if graph else B.lib().xfdtd_batch_run_eager
         B.check(fn(self._h, int(n)))

@@ -78,7 +78,8 @@ struct xfdtd_batch_s {
     double *d_apart = nullptr;
     int *d_afirst = nullptr;
     double *d_scale = nullptr, *d_grad = nullptr;
-    int atx = 64;  // adjoint tile width, chosen when the work list is built
+    int atx = 64;  // adjoint tile width, height and z-split, chosen when the work list is built
+    int aty = 8, azs = 0;
     // Workspace lists filled by a forward pass and not yet consumed by a
     // backward pass (which overwrites their E snapshots).
     struct Tape {
@@ -609,6 +610,17 @@ int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps)
     return XFDTD_OK;
 }
 
+int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *nslots)
+{
+    if (!b) return set_error(XFDTD_EINVAL, "null handle");
+    const bool built = b->naslots > 0;
+    if (tile_x) *tile_x = built ? b->atx : 0;
+    if (tile_y) *tile_y = built ? b->aty : 0;
+    if (zsplit) *zsplit = built ? b->azs : 0;
+    if (nslots) *nslots = b->naslots;
+    return XFDTD_OK;
+}
+
 int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems)
 {
     if (!b) return set_error(XFDTD_EINVAL, "null handle");
@@ -868,9 +880,16 @@ int pick_adj_tx(const xfdtd_batch_s *b)
     return c32 < c64 ? 32 : 64;
 }
 
-// The batched adjoint's tile height: one it supports (4 or 8; the 64x8 FP64
-// tile does not fit in LDS).
+// The batched adjoint's tile height, chosen with its work list
+// (build_adjoint).
 int adj_tile(const xfdtd_batch_s *b)
+{
+    return b->aty;
+}
+
+// The default candidate: one the kernel supports (4 or 8; the 64x8 FP64 tile
+// does not fit in LDS).
+int adj_tile_default(const xfdtd_batch_s *b)
 {
     if (b->dtype == XFDTD_F64 && b->atx == 64) return 4;
     return b->cfg.tile_y > 8 ? 8 : b->cfg.tile_y;
@@ -902,9 +921,7 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
 template <typename T>
 int build_adjoint(xfdtd_batch_t b)
 {
-    const int aty = adj_tile(b);
-    const int occ = std::max(1, adjoint_occupancy<T>(b->atx, aty));
-    const int per_xcd = std::max(1, cus() / 8) * occ;
+    int aty = adj_tile_default(b);
     const int warm = 4;
     std::vector<int2> items;
     std::vector<double> cost;
@@ -934,18 +951,33 @@ int build_adjoint(xfdtd_batch_t b)
         order = xcd_schedule(cost, run);
         return true;
     };
-    int best_zs = 1;
+    // candidate tile heights: the default, and for FP32 32-column tiles the
+    // 32x12 tile (9 waves, two per CU: 1.5 loaded positions per cell against
+    // 1.69 at 32x8); costs in position-planes (tile positions x planes)
+    std::vector<int> tys = {aty};
+    if (b->dtype == XFDTD_F32 && b->atx == 32 && aty != 12) tys.push_back(12);
+    int best_zs = 1, best_ty = aty;
     double best = INFINITY;
-    for (int zs : {1, 2, 3, 4, 6, 8, 12, 16}) {
-        if (!make(zs)) continue;
-        const double t = simulate_finish(order, cost, per_xcd).first;
-        if (t < best * (1.0 - 1e-9)) {
-            best = t;
-            best_zs = zs;
+    for (int ty : tys) {
+        aty = ty;
+        const int occ = std::max(1, adjoint_occupancy<T>(b->atx, ty));
+        const int per_xcd = std::max(1, cus() / 8) * occ;
+        const double positions = (double)(b->atx + 4) * (double)(ty + 4);
+        for (int zs : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            if (!make(zs)) continue;
+            const double t = simulate_finish(order, cost, per_xcd).first * positions;
+            if (t < best * (1.0 - 1e-9)) {
+                best = t;
+                best_zs = zs;
+                best_ty = ty;
+            }
         }
     }
+    aty = best_ty;
+    b->aty = best_ty;
+    b->azs = best_zs;
     if (!make(best_zs)) return set_error(XFDTD_EINVAL, "too many work items");
-    xlog("batched adjoint: %dx%d tiles, z-split %d (modelled finish %.0f plane iterations), %zu items in %zu slots",
+    xlog("batched adjoint: %dx%d tiles, z-split %d (modelled finish %.0f position-planes), %zu items in %zu slots",
          b->atx, aty, best_zs, best, items.size(), order.size());
     if (order.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int> first;

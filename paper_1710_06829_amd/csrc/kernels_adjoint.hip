@@ -77,6 +77,9 @@ struct AdjCfg {
     static_assert(TX_ == 64 || TX_ == 32, "tile width");
     static_assert((TY_ + 4) % SLOTS == 0, "rows per row wave");
     static_assert(4 * (TY_ + 4) <= 64, "halo wave must cover 4 columns x TY + 4 rows");
+    // waves per SIMD the compiler must leave room for: two 9-wave workgroups
+    // of the 32x12 tile per CU need five
+    static constexpr int MIN_WAVES = (TX_ == 32 && TY_ == 12) ? 5 : 1;
 };
 
 // gradient slots: the 12-coefficient order (alpha, beta_t1, beta_t2, delta per axis)
@@ -367,7 +370,7 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
 }
 
 template <typename T, typename C>
-__global__ __launch_bounds__(C::THREADS) void adjoint_step_kernel(
+__global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void adjoint_step_kernel(
     Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
     const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
     double *__restrict__ partials, int accumulate)
@@ -385,14 +388,26 @@ __global__ __launch_bounds__(C::THREADS) void adjoint_step_kernel(
 // (the item list is fixed for a batch, so the sums accumulate per item across
 // steps).  Workgroup w takes the slots w, w + gridDim.x, ... of `order`, which
 // holds item numbers in the host's dispatch order (-1: no work).
-template <typename T, typename C>
-__global__ __launch_bounds__(C::THREADS) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
+// ONE: one workgroup per slot (gridDim.x == nslots), no slot loop: nothing
+// stays live from one item to the next (the looping variant of the 32x12 tile
+// spills at the register budget of five waves per SIMD).
+template <typename T, typename C, bool ONE>
+__global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
                                                                      const int2 *__restrict__ items,
                                                                      const int *__restrict__ order, int nslots,
                                                                      double *__restrict__ partials,
                                                                      int accumulate)
 {
     __shared__ AdjSmem<T, C> sm;
+    if constexpr (ONE) {
+        const int j = order[blockIdx.x];
+        if (j < 0) return;
+        const int2 it = items[j];
+        const AdjDesc<T> &b = boxes[it.x];
+        adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
+                           partials + (int64_t)j * 12, accumulate);
+        return;
+    }
     for (int i = blockIdx.x; i < nslots; i += gridDim.x) {
         const int j = order[i];
         if (j < 0) continue;
@@ -449,7 +464,8 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
 }
 
 // Calls f(C{}) with the adjoint tile configuration of (tile_x, tile_y); the
-// 64x8 tile is FP32 only (in FP64 it would exceed the 160 KiB of LDS).
+// 64x8 tile is FP32 only (in FP64 it would exceed the 160 KiB of LDS), and so
+// is the 32x12 tile (8 row waves and the halo wave; two workgroups per CU).
 template <typename T, typename F>
 hipError_t with_adj_tile(int tile_x, int tile_y, F &&f)
 {
@@ -460,6 +476,8 @@ hipError_t with_adj_tile(int tile_x, int tile_y, F &&f)
     } else if (tile_x == 32) {
         if (tile_y == 4) return f(AdjCfg<32, 4>{});
         if (tile_y == 8) return f(AdjCfg<32, 8>{});
+        if constexpr (sizeof(T) == 4)
+            if (tile_y == 12) return f(AdjCfg<32, 12>{});
     }
     return hipErrorInvalidValue;
 }
@@ -524,8 +542,12 @@ hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, co
     if (grid <= 0 || grid > nslots) grid = nslots;
     return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
-        hipLaunchKernelGGL((batched_adjoint_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items,
-                           order, nslots, partials, accumulate);
+        if (grid == nslots)
+            hipLaunchKernelGGL((batched_adjoint_kernel<T, C, true>), dim3(grid), dim3(C::THREADS), 0, s, boxes,
+                               items, order, nslots, partials, accumulate);
+        else
+            hipLaunchKernelGGL((batched_adjoint_kernel<T, C, false>), dim3(grid), dim3(C::THREADS), 0, s, boxes,
+                               items, order, nslots, partials, accumulate);
         return hipGetLastError();
     });
 }

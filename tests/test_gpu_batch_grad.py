@@ -52,11 +52,14 @@ def test_batch_grad_matches_oracle_fp64(n, seg, cfg):
             assert np.all(np.asarray(g[i]) == 0)
 
 
-def test_batch_grad_equals_single_box_fp32():
-    """Same launch shapes per box (tile 8, whole z): final states and adjoint
-    fields bitwise equal to the single-box schedule; coefficient gradients
-    equal up to the order of the FP64 workgroup sums."""
-    shapes = [(32, 40, 96), (24, 24, 64), (48, 17, 70)]
+@pytest.mark.parametrize("shapes", [[(32, 40, 96), (24, 24, 64), (48, 17, 70)],
+                                    # 16 boxes of 96^3: the model picks the 32x12 adjoint tile
+                                    [(96, 96, 96)] * 16])
+def test_batch_grad_equals_single_box_fp32(shapes):
+    """Final states and adjoint fields bitwise equal to the single-box
+    schedule whatever the batched tilings (the per-cell arithmetic is the
+    same); coefficient gradients equal up to the order of the FP64
+    workgroup sums."""
     n = 23
     boxes = []
     for b, shape in enumerate(shapes):
@@ -71,6 +74,10 @@ def test_batch_grad_equals_single_box_fp32():
     bt.grad_forward(n, ws)
     lb = [to_dev(l, torch.float32) for (*_, l) in boxes]
     gb = bt.grad_backward(n, ws, lb)
+    acfg = bt.adjoint_config()
+    print(f"batched adjoint configuration: {acfg}")
+    if len(shapes) > 3:
+        assert acfg["tile_x"] == 32 and acfg["tile_y"] == 12, acfg
     for i, (shape, f0, c, dt, lamN) in enumerate(boxes):
         ts = to_dev(f0, torch.float32)
         s = pkg.Solver(ts, dt, c, scratch=False)
