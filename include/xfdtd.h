@@ -517,6 +517,12 @@ int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, in
  *   lam[m*6] : device, dL/d(final state) of each box in, dL/d(initial state)
  *       out (box-major, Ex..Bz).
  *   grad : host, m*12 doubles, dL/dcoeffs of each box.
+ * The forward steps run on the batch's one-step configuration; the adjoint
+ * steps on a tiling of their own, chosen per backward pass
+ * (xfdtd_batch_get_adjoint_config).  The results do not depend on either
+ * tiling: the adjoint fields are bitwise those of single-box runs and the
+ * coefficient gradients differ from them only in the order of the FP64
+ * workgroup sums.
  * The forward leaves the final states in the bound fields.  Both synchronise
  * the stream and allocate small internal buffers (launch descriptors).  The
  * backward consumes the forward pass like xfdtd_grad_backward: it needs the
