@@ -212,9 +212,15 @@ int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *w
  * fastest per step (setting the steps per pass) and caches it per (grid size,
  * dtype, device); force = 1 re-times, otherwise a cached choice is taken.
  * best_ms (nullable) receives the best time per step (-1 when taken from the
- * cache).  Requires bound fields and scratch arrays (XFDTD_ESTATE
- * otherwise); synchronises the stream.  Results are bitwise the same for
- * every configuration. */
+ * cache).  With XFDTD_TUNE_CACHE=<file> in the environment the choice also
+ * persists across processes: a grid not tuned in this process is looked up
+ * in the file (lines "<gpu arch>/<CUs> single:<f32|f64>:<nx>x<ny>x<nz>
+ * <steps per pass> <tile_x> <tile_y> <z-chunk>", the last one for a key
+ * wins, lines this handle cannot launch are ignored) and every timed choice
+ * is appended; xfdtd_batch_tune does the same with "batch:<shapes>" keys.
+ * File errors never fail a tuning.  Requires bound fields and scratch arrays
+ * (XFDTD_ESTATE otherwise); synchronises the stream.  Results are bitwise the
+ * same for every configuration. */
 int xfdtd_tune(xfdtd_t h, int force, double *best_ms);
 
 /*

@@ -472,6 +472,22 @@ std::string shape_key(const xfdtd_batch_t b)
     return k;
 }
 
+// a stored configuration (tile_x, tile_y, zsplit, grid, steps per pass) the
+// batch can launch
+bool valid_config(const xfdtd_batch_s *b, const std::vector<int> &v, Config &c)
+{
+    if (v.size() != 5) return false;
+    c.tile_x = v[0];
+    c.tile_y = v[1];
+    c.zsplit = v[2];
+    c.grid = v[3];
+    c.spp = v[4];
+    if ((c.tile_x != 32 && c.tile_x != 64) || (c.tile_y != 4 && c.tile_y != 8 && c.tile_y != 16) || c.zsplit < 0 ||
+        c.zsplit > 1024 || c.grid < 0 || (c.tile_y == 16 && b->dtype != XFDTD_F32) || (c.spp != 1 && c.spp != 2))
+        return false;
+    return c.spp == 1 || (b->dtype == XFDTD_F32 && c.tile_x == 32 && c.tile_y != 4);
+}
+
 }  // namespace
 
 extern "C" {
@@ -641,6 +657,13 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         if (!force) {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto it = g_cache.find(b->key);
+            std::vector<int> file;
+            Config fc;
+            if (it == g_cache.end() && tune_cache_lookup("batch:" + b->key, file) && valid_config(b, file, fc)) {
+                it = g_cache.emplace(b->key, fc).first;
+                xlog("batch tune: taken from the tuning file (%s %dx%d tiles, z-split %d, grid %d)",
+                     fc.spp == 2 ? "two-step" : "one-step", fc.tile_x, fc.tile_y, fc.zsplit, fc.grid);
+            }
             if (it != g_cache.end()) {
                 b->cfg = it->second;
                 b->cfg_set = true;
@@ -743,6 +766,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             std::lock_guard<std::mutex> lk(g_cache_mu);
             g_cache[b->key] = bestc;
         }
+        tune_cache_store("batch:" + b->key, {bestc.tile_x, bestc.tile_y, bestc.zsplit, bestc.grid, bestc.spp});
         xlog("batch tune: %zu candidates, best %s %dx%d tiles, z-split %d, grid %d, %.2f us per step", cands.size(),
              bestc.spp == 2 ? "two-step" : "one-step", bestc.tile_x, bestc.tile_y, bestc.zsplit, bestc.grid,
              best * 1e3);

@@ -74,6 +74,80 @@ xfdtd::Range::~Range() { roctxRangePop(); }
 
 namespace {
 
+std::mutex g_tune_file_mu;
+
+// "<architecture>/<CUs>" of the current device ("" if it cannot be read)
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "";
+    }
+    std::string arch = p.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ') c = '_';
+    return arch + "/" + std::to_string(p.multiProcessorCount);
+}
+
+}  // namespace
+
+bool xfdtd::tune_cache_lookup(const std::string &key, std::vector<int> &vals)
+{
+    const char *path = getenv("XFDTD_TUNE_CACHE");
+    if (!path || !*path) return false;
+    const std::string tag = device_tag();
+    if (tag.empty()) return false;
+    std::lock_guard<std::mutex> lk(g_tune_file_mu);
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[8192];
+    while (fgets(line, sizeof line, f)) {
+        char *save = nullptr;
+        const char *t = strtok_r(line, " \t\n", &save);
+        const char *k = t ? strtok_r(nullptr, " \t\n", &save) : nullptr;
+        if (!t || !k || tag != t || key != k) continue;
+        std::vector<int> v;
+        bool ok = true;
+        for (const char *w = strtok_r(nullptr, " \t\n", &save); w; w = strtok_r(nullptr, " \t\n", &save)) {
+            char *end = nullptr;
+            const long x = strtol(w, &end, 10);
+            if (!end || *end || x < -1000000 || x > 1000000) {
+                ok = false;
+                break;
+            }
+            v.push_back((int)x);
+        }
+        if (ok && !v.empty()) {
+            vals = v;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void xfdtd::tune_cache_store(const std::string &key, const std::vector<int> &vals)
+{
+    const char *path = getenv("XFDTD_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tag = device_tag();
+    if (tag.empty()) return;
+    std::string line = tag + " " + key;
+    for (int v : vals) line += " " + std::to_string(v);
+    line += "\n";
+    if (line.size() >= 8000) return;  // longer than a line the lookup reads
+    std::lock_guard<std::mutex> lk(g_tune_file_mu);
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fputs(line.c_str(), f);
+    fclose(f);
+}
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what)
 {
     return fail(XFDTD_EHIP, "%s: %s", what, hipGetErrorString(e));
@@ -593,6 +667,23 @@ std::array<int64_t, 5> tune_key(const xfdtd_s *h)
     return {h->g.nx, h->g.ny, h->g.nz, (int64_t)h->dtype, (int64_t)h->device};
 }
 
+// key of a box in the tuning file
+std::string tune_file_key(const xfdtd_s *h)
+{
+    return std::string("single:") + (h->dtype == XFDTD_F32 ? "f32:" : "f64:") + std::to_string(h->g.nx) + "x" +
+           std::to_string(h->g.ny) + "x" + std::to_string(h->g.nz);
+}
+
+// a stored (steps per pass, tile_x, tile_y, z-chunk) this box can launch
+bool valid_tuning(const xfdtd_s *h, const std::vector<int> &c)
+{
+    if (c.size() != 4 || c[3] < 1 || c[3] > h->g.nz) return false;
+    if (c[0] == 2)
+        return h->dtype == XFDTD_F32 && h->have_scratch && c[1] == 32 && (c[2] == 8 || c[2] == 16);
+    return c[0] == 1 && (c[1] == 32 || c[1] == 64) &&
+           (c[2] == 4 || c[2] == 8 || (c[2] == 16 && h->dtype == XFDTD_F32));
+}
+
 // z-chunk lengths worth timing for a kernel whose chunks start with `warm`
 // warm-up planes: the cost model's choice, the whole depth and a few splits
 std::vector<int> zchunk_candidates(const xfdtd_grid &g, int model)
@@ -689,6 +780,7 @@ int tune_t(xfdtd_t h, double *best_ms)
         g_tune[tune_key(h)] = bestc;
     }
     ++h->st.tunes;
+    tune_cache_store(tune_file_key(h), {bestc[0], bestc[1], bestc[2], bestc[3]});
     xlog("tune %lldx%lldx%lld %s: %zu candidates, best %s %dx%d tiles, z-chunk %d, %.2f us per step",
          (long long)h->g.nx, (long long)h->g.ny, (long long)h->g.nz, h->dtype == XFDTD_F32 ? "FP32" : "FP64",
          cands.size(), bestc[0] == 2 ? "two-step" : "one-step", bestc[1], bestc[2], bestc[3], best * 1e3);
@@ -1051,6 +1143,12 @@ int xfdtd_tune(xfdtd_t h, int force, double *best_ms)
         if (!force) {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune.find(tune_key(h));
+            std::vector<int> file;
+            if (it == g_tune.end() && tune_cache_lookup(tune_file_key(h), file) && valid_tuning(h, file)) {
+                it = g_tune.emplace(tune_key(h), std::array<int, 4>{file[0], file[1], file[2], file[3]}).first;
+                xlog("tune %s: taken from the tuning file (%s %dx%d tiles, z-chunk %d)", tune_file_key(h).c_str(),
+                     file[0] == 2 ? "two-step" : "one-step", file[1], file[2], file[3]);
+            }
             if (it != g_tune.end()) {
                 const std::array<int, 4> &c = it->second;
                 h->spp = c[0];

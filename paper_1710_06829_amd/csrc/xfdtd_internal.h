@@ -6,6 +6,8 @@
 #include <stdint.h>
 
 #include <exception>
+#include <string>
+#include <vector>
 #include <new>
 
 #include "../../include/xfdtd.h"
@@ -222,6 +224,14 @@ struct Range {
     Range(const Range &) = delete;
     Range &operator=(const Range &) = delete;
 };
+
+// Persistent tuning results: with XFDTD_TUNE_CACHE=<file> in the environment
+// the tuners look a configuration up there when they have none in memory,
+// and append the one they time.  A line is "<device> <key> <values...>",
+// <device> being the GPU's architecture name and CU count; the last line of
+// a key wins.  I/O errors and malformed lines are ignored.
+bool tune_cache_lookup(const std::string &key, std::vector<int> &vals);
+void tune_cache_store(const std::string &key, const std::vector<int> &vals);
 
 template <typename F>
 int guarded(F &&f) noexcept
