@@ -313,6 +313,16 @@ int xfdtd_divergence(xfdtd_t h, void *div_star_b, void *div_e);
 int xfdtd_divergence_max(xfdtd_t h, const void *ref_b, const void *ref_e, double out[3]);
 
 /*
+ * Failure detection: xfdtd_run in blocks of `every` steps, each followed by
+ * the non-finite check of xfdtd_divergence_max (one read of the six fields
+ * and a stream synchronisation per block).  Stops after the first block
+ * that leaves a non-finite value and returns XFDTD_ENONFINITE; *done
+ * (nullable) receives the steps completed either way.  n >= 0 and
+ * every >= 1, else XFDTD_EINVAL; other errors as xfdtd_run.
+ */
+int xfdtd_run_checked(xfdtd_t h, int64_t n, int64_t every, int64_t *done);
+
+/*
  * Reverse-mode differentiation (adjoint of the step; not in the paper: the
  * transposes of its update equations).  The forward step is
  *   B' = B + K E   (Faraday increment, extended difference D*),

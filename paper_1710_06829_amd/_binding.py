@@ -86,6 +86,7 @@ SIGNATURES = {
     "xfdtd_divergence_max": ([_vp, _vp, _vp, _dp], _int),
     "xfdtd_adjoint_step": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp], _int),
     "xfdtd_get_stats": ([_vp, ctypes.POINTER(Stats)], _int),
+    "xfdtd_run_checked": ([_vp, _i64, _i64, ctypes.POINTER(_i64)], _int),
     "xfdtd_reset_stats": ([_vp, _int], _int),
     "xfdtd_adjoint_step_noalloc": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
                                    _int),

@@ -1103,6 +1103,29 @@ int xfdtd_run(xfdtd_t h, int64_t n)
     });
 }
 
+int xfdtd_run_checked(xfdtd_t h, int64_t n, int64_t every, int64_t *done)
+{
+    return guarded([&]() -> int {
+        if (done) *done = 0;
+        int rc = check_bound(h);
+        if (rc) return rc;
+        if (n < 0 || every < 1) return fail(XFDTD_EINVAL, "need n >= 0 and every >= 1");
+        for (int64_t s = 0; s < n;) {
+            const int64_t m = std::min(every, n - s);
+            rc = xfdtd_run(h, m);
+            if (rc) return rc;
+            s += m;
+            if (done) *done = s;
+            double out[3];
+            rc = xfdtd_divergence_max(h, nullptr, nullptr, out);
+            if (rc == XFDTD_ENONFINITE)
+                return fail(XFDTD_ENONFINITE, "%.0f non-finite field values after %lld steps", out[2], (long long)s);
+            if (rc) return rc;
+        }
+        return XFDTD_OK;
+    });
+}
+
 int xfdtd_get_stats(xfdtd_t h, xfdtd_stats *out)
 {
     return guarded([&]() -> int {

@@ -133,8 +133,17 @@ class Solver:
         arr = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in J])
         B.check(B.lib().xfdtd_step_ampere_current(self._h, arr))
 
-    def run(self, n: int):
+    def run(self, n: int, check_every: int = 0):
+        """n leapfrog steps.  check_every > 0: stop at the first block of that
+        many steps that leaves a non-finite value (XfdtdError with code
+        XFDTD_ENONFINITE; self.steps_done holds the steps completed)."""
         self._bind()
+        if check_every > 0:
+            done = ctypes.c_int64()
+            rc = B.lib().xfdtd_run_checked(self._h, int(n), int(check_every), ctypes.byref(done))
+            self.steps_done = done.value
+            B.check(rc)
+            return
         B.check(B.lib().xfdtd_run(self._h, int(n)))
 
     def set_steps_per_pass(self, steps: int):

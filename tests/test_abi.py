@@ -465,3 +465,15 @@ def test_log_prints_the_configuration_and_roctx_is_linked():
     d = subprocess.run(["readelf", "-d", B.LIB_PATH], capture_output=True, text=True)
     if d.returncode == 0:
         assert "librocprofiler-sdk-roctx" in d.stdout
+
+
+def test_checked_run_needs_bound_fields():
+    """xfdtd_run_checked on an unbound handle is a state error; done is 0."""
+    rc, h = _create()
+    assert rc == 0
+    try:
+        done = ctypes.c_int64(7)
+        assert B.lib().xfdtd_run_checked(h, 10, 5, ctypes.byref(done)) == -5
+        assert done.value == 0
+    finally:
+        B.lib().xfdtd_destroy(h)

@@ -83,3 +83,24 @@ def test_gradient_counters():
     s.adjoint_step(lam, out, e, g)
     assert s.stats()["adjoint_steps"] == n + 1
     assert np.isfinite(g.cpu().numpy()).all()
+
+
+def test_checked_run_stops_at_the_first_non_finite_block():
+    """An unstable time step (1.3x the bound, allowed on purpose) blows the
+    fields up: the checked run stops after the first block of 25 steps that
+    leaves a non-finite value; a stable run completes every step."""
+    shape = (24, 20, 36)
+    beta, delta = S.extended_beta_delta(895)
+    c = O.coeffs_from(beta, delta)
+    f = to_dev(S.uniform_fields(shape, 896), torch.float32)
+    s = pkg.Solver(f, 1.3 * O.cfl_dt(c), c, allow_unstable=True)
+    with pytest.raises(pkg.XfdtdError) as err:
+        s.run(4000, check_every=25)
+    assert err.value.code == -3  # XFDTD_ENONFINITE
+    assert 0 < s.steps_done < 4000 and s.steps_done % 25 == 0
+    assert not all(torch.isfinite(x).all() for x in f)
+    g = to_dev(S.uniform_fields(shape, 897), torch.float32)
+    s2 = pkg.Solver(g, 0.9 * O.cfl_dt(c), c)
+    s2.run(120, check_every=50)
+    assert s2.steps_done == 120
+    assert all(torch.isfinite(x).all() for x in g)
