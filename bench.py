@@ -344,6 +344,8 @@ def batched_boxes(steps=500):
     return {"workload": "64 boxes, edges in {32,48,64,96,128}, FP32, 500 steps", "cells": cells,
             "batched_ms": round(t_b, 3), "sequential_ms": round(t_s, 3),
             "batched_Gcell_updates_per_s": round(cells * steps / (t_b * 1e-3) / 1e9, 2),
+            # the metric's 48 B per cell-update over the batch / 8 TB/s
+            "hbm_roofline_frac": round(cells * steps / (t_b * 1e-3) * 48.0 / (HBM_PEAK_GBS * 1e9), 4),
             "sequential_Gcell_updates_per_s": round(cells * steps / (t_s * 1e-3) / 1e9, 2),
             "speedup": round(t_s / t_b, 3), "config": bt.config()}
 
@@ -422,7 +424,7 @@ def batched_grads(steps=300, count=16, edge=96):
             "fwd_adj_ms": round(t_f + t_b, 3), "ratio_to_forward": round((t_f + t_b) / t_fwd, 3),
             "sequential_fwd_adj_ms": round(t_s, 3), "speedup_vs_sequential": round(t_s / (t_f + t_b), 3),
             "Gcell_updates_per_s_fwd_adj": round(cells * steps / ((t_f + t_b) * 1e-3) / 1e9, 2),
-            "config": bt.config()}
+            "config": bt.config(), "adjoint_config": bt.adjoint_config()}
 
 
 def norm_bench():
