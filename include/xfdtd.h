@@ -156,26 +156,26 @@ int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3]);
 int xfdtd_run(xfdtd_t h, int64_t n);
 
 /*
- * Steps per pass of xfdtd_run (FP32 with scratch arrays bound):
+ * Steps per pass of xfdtd_run (with scratch arrays bound):
  *   1: one fused step per launch (reads and writes the state once per step:
- *      48 B per cell-update in FP32);
+ *      48 B per cell-update in FP32, 96 B in FP64);
  *   2: two chained steps per launch (the leapfrog of App. A eq. update1-6
  *      applied twice in one z-march: the state is read and written once per
- *      two steps, 24 B per cell-update).  The second step's inputs are formed
- *      on chip, redundantly on a 4-cell halo of each tile; every cell's
- *      arithmetic is the one-step kernel's, so the results are bitwise the
- *      same as with 1.
+ *      two steps, 24 B per cell-update in FP32, 48 B in FP64).  The second
+ *      step's inputs are formed on chip, redundantly on a 4-cell halo of each
+ *      tile (32 x 8 or 32 x 16 output tiles in FP32, 24 x 8 in FP64); every
+ *      cell's arithmetic is the one-step kernel's, so the results are
+ *      bitwise the same as with 1.
  * Default 2 for FP32 grids of at least 2^23 cells, else 1 (override with
  * XFDTD_STEPS_PER_PASS=1 or 2 at xfdtd_create); xfdtd_tune chooses between
- * them per grid.  XFDTD_EINVAL for other values and for 2 on an FP64 handle.
- * Host only.
+ * them per grid.  XFDTD_EINVAL for other values.  Host only.
  */
 int xfdtd_set_steps_per_pass(xfdtd_t h, int steps);
 
 /* Launch configuration of the two-step kernel for this handle, and the steps
  * per pass xfdtd_run uses (1 or 2): tile width and height of its output tiles
- * (32 x 8 or 32 x 16), z-planes per workgroup, workgroups per launch.  Any
- * pointer may be NULL.  Host only. */
+ * (32 x 8 or 32 x 16 in FP32, 24 x 8 in FP64), z-planes per workgroup,
+ * workgroups per launch.  Any pointer may be NULL.  Host only. */
 int xfdtd_launch_config2(xfdtd_t h, int *steps_per_pass, int *tile_x, int *tile_y, int *zchunk,
                          int *workgroups);
 
@@ -206,7 +206,8 @@ int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *w
 
 /* Autotunes the launch configuration of xfdtd_run for this handle: times
  * the fused step's tile widths 64 and 32, tile heights 8 and 16 (FP32; 4 and
- * 8 for FP64) and, for FP32, the two-step kernel's 32 x 8 and 32 x 16 tiles,
+ * 8 for FP64) and the two-step kernel's tiles (32 x 8 and 32 x 16 in FP32,
+ * 24 x 8 in FP64),
  * each with a few z-chunk lengths, with launches that read the bound fields
  * and write only the scratch arrays (the state is unchanged); keeps the
  * fastest per step (setting the steps per pass) and caches it per (grid size,

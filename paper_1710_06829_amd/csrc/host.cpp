@@ -381,15 +381,16 @@ int pick_tile_x(const xfdtd_grid &g)
 // Two-step kernel: workgroups resident per CU, and the default tiling.  Its
 // z-march needs 10 warm-up planes per chunk (each stage's 3 plus stage 2's lag
 // of 3 and one more plane of E^{n+1}).
-int64_t blocked2_slots(int tile_x, int tile_y)
+int64_t blocked2_slots(int dtype, int tile_x, int tile_y)
 {
-    const int per = blocked2_occupancy<float>(tile_x, tile_y);
+    const int per = dtype == XFDTD_F32 ? blocked2_occupancy<float>(tile_x, tile_y)
+                                       : blocked2_occupancy<double>(tile_x, tile_y);
     return (int64_t)device_cus() * (per > 0 ? per : 1);
 }
 
-int blocked2_zchunk(const xfdtd_grid &g, int tile_x, int tile_y)
+int blocked2_zchunk(const xfdtd_grid &g, int tile_x, int tile_y, int dtype = XFDTD_F32)
 {
-    return auto_zchunk(g, tile_x, tile_y, blocked2_slots(tile_x, tile_y), 10);
+    return auto_zchunk(g, tile_x, tile_y, blocked2_slots(dtype, tile_x, tile_y), 10);
 }
 
 // 32x16 tiles while their z-chunks stay long (>= 64 planes), 32x8 otherwise
@@ -679,7 +680,8 @@ bool valid_tuning(const xfdtd_s *h, const std::vector<int> &c)
 {
     if (c.size() != 4 || c[3] < 1 || c[3] > h->g.nz) return false;
     if (c[0] == 2)
-        return h->dtype == XFDTD_F32 && h->have_scratch && c[1] == 32 && (c[2] == 8 || c[2] == 16);
+        return h->have_scratch && (h->dtype == XFDTD_F32 ? c[1] == 32 && (c[2] == 8 || c[2] == 16)
+                                                         : c[1] == 24 && c[2] == 8);
     return c[0] == 1 && (c[1] == 32 || c[1] == 64) &&
            (c[2] == 4 || c[2] == 8 || (c[2] == 16 && h->dtype == XFDTD_F32));
 }
@@ -700,8 +702,8 @@ std::vector<int> zchunk_candidates(const xfdtd_grid &g, int model)
 }
 
 // Times each candidate with launches fields -> scratch (the bound state is
-// only read) and keeps the fastest per step: one-step tilings, and for FP32
-// the two-step kernel's tilings (two steps per launch).
+// only read) and keeps the fastest per step: one-step tilings and the
+// two-step kernel's (two steps per launch).
 template <typename T>
 int tune_t(xfdtd_t h, double *best_ms)
 {
@@ -717,10 +719,14 @@ int tune_t(xfdtd_t h, double *best_ms)
         for (int ty : tys)
             for (int z : zchunk_candidates(h->g, auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty))))
                 if (fits(tx, ty, z)) cands.push_back({1, tx, ty, z});
-    if (sizeof(T) == 4)
+    if (sizeof(T) == 4) {
         for (int ty : {8, 16})
             for (int z : zchunk_candidates(h->g, blocked2_zchunk(h->g, 32, ty)))
                 if (fits(32, ty, z)) cands.push_back({2, 32, ty, z});
+    } else {
+        for (int z : zchunk_candidates(h->g, blocked2_zchunk(h->g, 24, 8, XFDTD_F64)))
+            if (fits(24, 8, z)) cands.push_back({2, 24, 8, z});
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     hipError_t he = hipEventCreate(&e1);
@@ -870,11 +876,11 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
         const char *ty = getenv("XFDTD_TILE_Y");
         if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
         h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
-    // two-step kernel (FP32): 32-column tiles; the default steps per pass
-    // can be overridden with XFDTD_STEPS_PER_PASS (1 or 2)
-    h->btile_x = 32;
+    // two-step kernel: 32-column tiles (FP32), 24 x 8 (FP64); the default
+    // steps per pass can be overridden with XFDTD_STEPS_PER_PASS (1 or 2)
+    h->btile_x = dtype == XFDTD_F32 ? 32 : 24;
     h->btile_y = dtype == XFDTD_F32 ? pick_blocked2_tile_y(*g) : 8;
-    h->bzchunk = dtype == XFDTD_F32 ? blocked2_zchunk(*g, h->btile_x, h->btile_y) : 1;
+    h->bzchunk = blocked2_zchunk(*g, h->btile_x, h->btile_y, dtype);
     // Two steps per pass by default for FP32 boxes of at least 2^23 cells;
     // below that the one-step kernel measured as fast or faster (32^3 ..
     // 128^3: its shorter z-march warm-up and smaller halo win while the
@@ -882,14 +888,14 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
     // two-step).  xfdtd_tune decides per box.
     h->spp = dtype == XFDTD_F32 && (double)g->nx * g->ny * g->nz >= (double)(1 << 23) ? 2 : 1;
     const char *spp = getenv("XFDTD_STEPS_PER_PASS");
-    if (spp && (atoi(spp) == 1 || (atoi(spp) == 2 && dtype == XFDTD_F32))) h->spp = atoi(spp);
+    if (spp && (atoi(spp) == 1 || atoi(spp) == 2)) h->spp = atoi(spp);
     const char *bty = getenv("XFDTD_BLK_TILE_Y");
     if (dtype == XFDTD_F32 && bty && (atoi(bty) == 8 || atoi(bty) == 16)) {
         h->btile_y = atoi(bty);
         h->bzchunk = blocked2_zchunk(*g, h->btile_x, h->btile_y);
     }
     const char *bzc = getenv("XFDTD_BLK_ZCHUNK");
-    if (dtype == XFDTD_F32 && bzc && atoi(bzc) > 0) h->bzchunk = atoi(bzc);
+    if (bzc && atoi(bzc) > 0) h->bzchunk = atoi(bzc);
         // adjoint: 64x8 tiles for FP32 (64x4 for FP64, whose 64x8 tile does not
         // fit in LDS), its own z-chunk for that tile height
         h->atile_x = pick_tile_x(*g);
@@ -1207,7 +1213,6 @@ int xfdtd_set_steps_per_pass(xfdtd_t h, int steps)
     return guarded([&]() -> int {
         if (!h) return fail(XFDTD_EINVAL, "null handle");
         if (steps != 1 && steps != 2) return fail(XFDTD_EINVAL, "steps per pass must be 1 or 2");
-        if (steps == 2 && h->dtype != XFDTD_F32) return fail(XFDTD_EINVAL, "the two-step kernel is FP32 only");
         h->spp = steps;
         return XFDTD_OK;
     });

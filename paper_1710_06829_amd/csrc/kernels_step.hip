@@ -583,17 +583,25 @@ struct Blk2Smem {
     T B2[3][P];  // stage 2: B^{n+3/2}(j-1)
 };
 
-// Position of slot sl of a 32-column two-step tile.  Waves are aligned with
-// memory rows: the first TX*TY slots are the output cells, two 32-column rows
-// per wave (every output row segment is one 128-byte line, stored by one
-// instruction); then the 8 halo columns x in [-4, 0) and [TX, TX+4) over all
-// TY + 8 rows; then the 8 halo rows y in [-4, 0) and [TY, TY+4) over the TX
-// inner columns.  Each part is a whole number of waves.
+// Position of slot sl of a two-step tile.  Waves are aligned with memory
+// rows.  32-column tiles: the first TX*TY slots are the output cells, two
+// 32-column rows per wave (every output row segment is one 128-byte line,
+// stored by one instruction); then the 8 halo columns x in [-4, 0) and
+// [TX, TX+4) over all TY + 8 rows; then the 8 halo rows y in [-4, 0) and
+// [TY, TY+4) over the TX inner columns.  Each part is a whole number of
+// waves.  24-column tiles (FP64): the 32 positions of a row, halo included,
+// are one half wave, in row order.
 template <typename C>
 __device__ __forceinline__ void blk2_position(int sl, int &rx, int &ry)
 {
     constexpr int TX = C::TX, TY = C::TY, NI = TX * TY, NC = 8 * (TY + 8);
-    static_assert(TX == 32 && NI % 64 == 0 && NC % 64 == 0 && (8 * TX) % 64 == 0, "wave-aligned parts");
+    if constexpr (C::PX == 32) {
+        rx = sl % 32 - 4;
+        ry = sl / 32 - 4;
+        return;
+    }
+    static_assert(C::PX == 32 || (TX == 32 && NI % 64 == 0 && NC % 64 == 0 && (8 * TX) % 64 == 0),
+                  "wave-aligned parts");
     if (sl < NI) {
         rx = sl % TX;
         ry = sl / TX;
@@ -873,6 +881,9 @@ __global__ __launch_bounds__(C::THREADS) void batched_blocked2_kernel(const BoxD
 // queues exceed the 168 VGPRs of three waves per SIMD and spill.
 using Blk32x16 = Blk2Cfg<32, 16, 1, 15>;
 using Blk32x8 = Blk2Cfg<32, 8, 1, 10>;
+// FP64: 24x8 outputs on 32x16 positions (8 waves, 98 KB of LDS for the 24
+// double planes; a 32-column FP64 tile's planes would exceed the LDS).
+using Blk24x8 = Blk2Cfg<24, 8, 1, 8>;
 
 template <typename T, typename F>
 hipError_t with_blk2(int tile_x, int tile_y, F &&f)
@@ -880,6 +891,8 @@ hipError_t with_blk2(int tile_x, int tile_y, F &&f)
     if constexpr (sizeof(T) == 4) {
         if (tile_x == 32 && tile_y == 16) return f(Blk32x16{});
         if (tile_x == 32 && tile_y == 8) return f(Blk32x8{});
+    } else {
+        if (tile_x == 24 && tile_y == 8) return f(Blk24x8{});
     }
     return hipErrorInvalidValue;
 }

@@ -147,7 +147,7 @@ class Solver:
         B.check(B.lib().xfdtd_run(self._h, int(n)))
 
     def set_steps_per_pass(self, steps: int):
-        """1: one fused step per launch; 2: the two-step kernel (FP32).  The
+        """1: one fused step per launch; 2: the two-step kernel.  The
         results are bitwise the same."""
         B.check(B.lib().xfdtd_set_steps_per_pass(self._h, int(steps)))
 

@@ -295,6 +295,35 @@ def test_two_step_kernel_bitwise_equals_one_step(env, shape):
             assert rel_l2(got, exp) < 1e-6
 
 
+@pytest.mark.parametrize("shape", TWO_STEP_SHAPES)
+def test_two_step_kernel_fp64_equals_one_step_and_oracle(env, shape):
+    """FP64 two steps per launch (24 x 8 tiles): bitwise the one-step
+    launches for run lengths that take each path and several z-chunkings,
+    and within 1e-13 of the FP64 oracle."""
+    c = _coeffs(487)
+    sp = (1.0, 0.9, 1.1)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 488)
+    for n in (1, 2, 3, 4, 7, 8):
+        env(XFDTD_STEPS_PER_PASS=1)
+        ref = to_dev(f0)
+        pkg.Solver(ref, dt, c, spacing=sp).run(n)
+        ref = to_host(ref)
+        env(XFDTD_STEPS_PER_PASS=2)
+        for zc in (1, 3, 7, 64) if n in (4, 7) else (64,):
+            env(XFDTD_BLK_ZCHUNK=zc)
+            t = to_dev(f0)
+            s = pkg.Solver(t, dt, c, spacing=sp)
+            lc = s.launch_config()
+            assert lc["steps_per_pass"] == 2 and lc["two_step"]["tile_x"] == 24 and lc["two_step"]["zchunk"] == zc
+            s.run(n)
+            got = to_host(t)
+            assert all(np.array_equal(a, b) for a, b in zip(got, ref)), (n, zc)
+        if n == 8:
+            exp = oracle.c_run(f0, n, c, dt, sp)
+            assert rel_l2(got, exp) < 1e-13
+
+
 @pytest.mark.parametrize("dtype,shape,spp", [(torch.float32, (33, 17, 64), 1), (torch.float32, (37, 45, 150), 2),
                                              (torch.float64, (20, 18, 70), 1)])
 def test_run_graph_replay_is_bitwise_the_direct_launches(env, dtype, shape, spp):
@@ -322,14 +351,15 @@ def test_run_graph_replay_is_bitwise_the_direct_launches(env, dtype, shape, spp)
         assert all(torch.equal(x, y) for x, y in zip(a, b2)), n
 
 
-def test_two_step_kernel_rejects_fp64_and_bad_counts():
+def test_two_step_kernel_rejects_bad_counts():
     shape = (6, 5, 7)
     c = _coeffs(485)
     dt = 0.9 * O.cfl_dt(c)
     s = pkg.Solver(to_dev(S.uniform_fields(shape, 486)), dt, c)
     assert s.launch_config()["steps_per_pass"] == 1
-    with pytest.raises(pkg.XfdtdError):
-        s.set_steps_per_pass(2)
+    s.set_steps_per_pass(2)  # FP64: the 24 x 8 two-step tile
+    lc = s.launch_config()
+    assert lc["steps_per_pass"] == 2 and (lc["two_step"]["tile_x"], lc["two_step"]["tile_y"]) == (24, 8)
     s32 = pkg.Solver(to_dev(S.uniform_fields(shape, 486), torch.float32), dt, c)
     for bad in (0, 3, -1):
         with pytest.raises(pkg.XfdtdError):
