@@ -218,7 +218,8 @@ int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *w
  * in the file (lines "<gpu arch>/<CUs> single:<f32|f64>:<nx>x<ny>x<nz>
  * <steps per pass> <tile_x> <tile_y> <z-chunk>", the last one for a key
  * wins, lines this handle cannot launch are ignored) and every timed choice
- * is appended; xfdtd_batch_tune does the same with "batch:<shapes>" keys.
+ * is appended; xfdtd_batch_tune does the same with "batch:<shapes>" keys
+ * (and "batchadj:<shapes>" for the batched adjoint's tiling).
  * File errors never fail a tuning.  Requires bound fields and scratch arrays
  * (XFDTD_ESTATE otherwise); synchronises the stream.  Results are bitwise the
  * same for every configuration. */
@@ -468,9 +469,15 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     kernel on 32 x 8 and 32 x 16 tiles with z-split 1, 2 or 0) with
  *     launches that read the state and write only the scratch arrays, keeps
  *     the fastest per step, and caches it per set of box shapes (force = 1
- *     re-times).  best_ms (nullable) receives the best time per step (-1
- *     when taken from the cache).  Synchronises the stream; on failure the
- *     previous configuration stays.
+ *     re-times).  It then times the batched adjoint's tilings for the
+ *     gradient passes the same way (the state read as lambda and primal E,
+ *     the scratch arrays written): the default tile height and, for FP32
+ *     32-column tiles, 12; z-split 1-4 and the model's; each box's items
+ *     dispatched as one run or in runs of a few tiles.  best_ms (nullable)
+ *     receives the forward's best time per step (-1 when taken from the
+ *     cache; the adjoint's choice is then also taken from the cache if it
+ *     holds one, else the model below chooses).  Synchronises the stream;
+ *     on failure the previous forward configuration stays.
  * xfdtd_batch_set_config / get_config: choose / report the configuration:
  *     tile_x 64 or 32, tile_y 4, 8 or 16 (16: FP32 only), zsplit 0..1024
  *     (zsplit >= 1: each box is cut into z-chunks of ceil(nz / zsplit) >= 4
@@ -514,11 +521,13 @@ int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps);
 
 /*
  * The batched adjoint's launch configuration, chosen by each
- * xfdtd_batch_grad_backward (all 0 before the first): tile_x 32 or 64;
- * tile_y 4, 8, or 12 (FP32 32-column tiles only); zsplit, the z-chunks per
- * box; nslots, its dispatch slots.  The tile height and z-split come from a
- * list-scheduling model of the work list (tile positions x planes per
- * item).  XFDTD_EINVAL for a null handle.  Host only.
+ * xfdtd_batch_grad_backward and by xfdtd_batch_tune (all 0 before either):
+ * tile_x 32 or 64; tile_y 4, 8, or 12 (FP32 32-column tiles only); zsplit,
+ * the z-chunks per box; nslots, its dispatch slots.  The tile height and
+ * z-split are the ones xfdtd_batch_tune timed fastest for the batch's shapes
+ * (while the adjoint's tile width is the one they were timed with), else
+ * those of a list-scheduling model of the work list (tile positions x planes
+ * per item).  XFDTD_EINVAL for a null handle.  Host only.
  */
 int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *nslots);
 

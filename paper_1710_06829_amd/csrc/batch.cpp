@@ -44,8 +44,17 @@ struct Config {
     int tile_x = 64, tile_y = 8, zsplit = 1, grid = 0, spp = 1;
 };
 
+// The batched adjoint's tiling as timed by xfdtd_batch_tune: tile width
+// (0: nothing timed, the list-scheduling model chooses), tile height, z-split,
+// and whether each box's items form one dispatch run (one XCD's L2 then holds
+// all of a box's halos) rather than runs of a few tiles.
+struct AdjPick {
+    int tx = 0, ty = 0, zs = 0, boxrun = 0;
+};
+
 std::mutex g_cache_mu;
 std::map<std::string, Config> g_cache;
+std::map<std::string, AdjPick> g_acache;  // per key, beside g_cache
 
 }  // namespace
 
@@ -80,6 +89,7 @@ struct xfdtd_batch_s {
     double *d_scale = nullptr, *d_grad = nullptr;
     int atx = 64;  // adjoint tile width, height and z-split, chosen when the work list is built
     int aty = 8, azs = 0;
+    AdjPick apick;  // timed adjoint tiling, used while its tile width is the batch's
     // Workspace lists filled by a forward pass and not yet consumed by a
     // backward pass (which overwrites their E snapshots).
     struct Tape {
@@ -488,6 +498,10 @@ bool valid_config(const xfdtd_batch_s *b, const std::vector<int> &v, Config &c)
     return c.spp == 1 || (b->dtype == XFDTD_F32 && c.tile_x == 32 && c.tile_y != 4);
 }
 
+// Times the batched adjoint's tilings for the bound batch (defined with the
+// gradient passes below).
+int tune_adjoint(xfdtd_batch_t b, bool lookup);
+
 }  // namespace
 
 extern "C" {
@@ -581,6 +595,8 @@ int xfdtd_batch_bind(xfdtd_batch_t b, void *const *fields, void *const *scratch,
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto it = g_cache.find(b->key);
             if (!b->cfg_set && it != g_cache.end()) b->cfg = it->second;
+            auto ia = g_acache.find(b->key);
+            if (b->apick.tx == 0 && ia != g_acache.end()) b->apick = ia->second;
         }
         return build(b);
     });
@@ -655,20 +671,27 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         if (!b) return set_error(XFDTD_EINVAL, "null handle");
         if (!b->bound) return set_error(XFDTD_ESTATE, "bind the batch first");
         if (!force) {
-            std::lock_guard<std::mutex> lk(g_cache_mu);
-            auto it = g_cache.find(b->key);
-            std::vector<int> file;
-            Config fc;
-            if (it == g_cache.end() && tune_cache_lookup("batch:" + b->key, file) && valid_config(b, file, fc)) {
-                it = g_cache.emplace(b->key, fc).first;
-                xlog("batch tune: taken from the tuning file (%s %dx%d tiles, z-split %d, grid %d)",
-                     fc.spp == 2 ? "two-step" : "one-step", fc.tile_x, fc.tile_y, fc.zsplit, fc.grid);
+            bool hit = false;
+            {
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                auto it = g_cache.find(b->key);
+                std::vector<int> file;
+                Config fc;
+                if (it == g_cache.end() && tune_cache_lookup("batch:" + b->key, file) && valid_config(b, file, fc)) {
+                    it = g_cache.emplace(b->key, fc).first;
+                    xlog("batch tune: taken from the tuning file (%s %dx%d tiles, z-split %d, grid %d)",
+                         fc.spp == 2 ? "two-step" : "one-step", fc.tile_x, fc.tile_y, fc.zsplit, fc.grid);
+                }
+                if (it != g_cache.end()) {
+                    b->cfg = it->second;
+                    hit = true;
+                }
             }
-            if (it != g_cache.end()) {
-                b->cfg = it->second;
+            if (hit) {  // the cache lock is released: the adjoint's lookup takes it again
                 b->cfg_set = true;
                 if (best_ms) *best_ms = -1.0;
-                return build(b);
+                const int rc = build(b);
+                return rc ? rc : tune_adjoint(b, true);
             }
         }
         const int ncu = cus();
@@ -771,7 +794,8 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
              bestc.spp == 2 ? "two-step" : "one-step", bestc.tile_x, bestc.tile_y, bestc.zsplit, bestc.grid,
              best * 1e3);
         if (best_ms) *best_ms = best;
-        return build(b);
+        rc = build(b);
+        return rc ? rc : tune_adjoint(b, false);
     });
 }
 
@@ -937,11 +961,20 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
     return a;
 }
 
+// Whether the batched adjoint kernel has an atx x ty tile for this dtype
+// (FP64 has no 64x8 or 32x12 tile: their planes exceed the LDS).
+bool adj_tile_ok(const xfdtd_batch_s *b, int ty)
+{
+    if (b->atx == 64) return ty == 4 || (ty == 8 && b->dtype == XFDTD_F32);
+    return ty == 4 || ty == 8 || (ty == 12 && b->dtype == XFDTD_F32);
+}
+
 // Adjoint work list (tile atx x adj_tile): per-box contiguous items, their
-// dispatch order, item ranges per box and gradient scales.  The adjoint's
-// z-split is its own: the one whose dispatch order finishes first in the
-// list-scheduling model (chunks cost their planes plus 4 warm-up iterations;
-// CUs x resident workgroups run at once), fewer chunks on ties.
+// dispatch order, item ranges per box and gradient scales.  The tiling is the
+// timed one (apick) when it was timed for this tile width; otherwise the
+// adjoint's z-split is its own: the one whose dispatch order finishes first in
+// the list-scheduling model (chunks cost their planes plus 4 warm-up
+// iterations; CUs x resident workgroups run at once), fewer chunks on ties.
 template <typename T>
 int build_adjoint(xfdtd_batch_t b)
 {
@@ -950,6 +983,7 @@ int build_adjoint(xfdtd_batch_t b)
     std::vector<int2> items;
     std::vector<double> cost;
     std::vector<int> run, order;
+    bool boxrun = false;
     auto make = [&](int zs) {
         items.clear();
         cost.clear();
@@ -969,8 +1003,11 @@ int build_adjoint(xfdtd_batch_t b)
         const int run_len = run_length(total, count);
         for (int64_t i = 0; i < b->m; ++i) {
             const xfdtd_grid &g = b->g[i];
+            const size_t r0 = run.size();
             box_items((int)i, (int)((g.nx + b->atx - 1) / b->atx), (int)((g.ny + aty - 1) / aty), (int)g.nz,
                       b->azc[(size_t)i], warm, run_len, items, cost, run);
+            if (boxrun)
+                for (size_t j = r0; j < run.size(); ++j) run[j] = (int)i;
         }
         order = xcd_schedule(cost, run);
         return true;
@@ -982,6 +1019,13 @@ int build_adjoint(xfdtd_batch_t b)
     if (b->dtype == XFDTD_F32 && b->atx == 32 && aty != 12) tys.push_back(12);
     int best_zs = 1, best_ty = aty;
     double best = INFINITY;
+    const AdjPick &pk = b->apick;
+    if (pk.tx == b->atx && adj_tile_ok(b, pk.ty) && pk.zs >= 1 && pk.zs <= 1024) {
+        tys.clear();
+        best_zs = pk.zs;
+        best_ty = pk.ty;
+        boxrun = pk.boxrun != 0;
+    }
     for (int ty : tys) {
         aty = ty;
         const int occ = std::max(1, adjoint_occupancy<T>(b->atx, ty));
@@ -1001,8 +1045,12 @@ int build_adjoint(xfdtd_batch_t b)
     b->aty = best_ty;
     b->azs = best_zs;
     if (!make(best_zs)) return set_error(XFDTD_EINVAL, "too many work items");
-    xlog("batched adjoint: %dx%d tiles, z-split %d (modelled finish %.0f position-planes), %zu items in %zu slots",
-         b->atx, aty, best_zs, best, items.size(), order.size());
+    if (tys.empty())
+        xlog("batched adjoint: %dx%d tiles, z-split %d, %s runs (timed), %zu items in %zu slots", b->atx, aty,
+             best_zs, boxrun ? "whole-box" : "short", items.size(), order.size());
+    else
+        xlog("batched adjoint: %dx%d tiles, z-split %d (modelled finish %.0f position-planes), %zu items in %zu slots",
+             b->atx, aty, best_zs, best, items.size(), order.size());
     if (order.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     std::vector<int> first;
     std::vector<double> scale;
@@ -1282,6 +1330,124 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     BTRY(hipStreamSynchronize(mainS), "hipStreamSynchronize");
     BTRY(hipStreamSynchronize(aux), "hipStreamSynchronize");
     return XFDTD_OK;
+}
+
+// Timing of the batched adjoint's tilings: the model's choice and, per tile
+// height (the default, and 32x12 for FP32 32-column tiles), z-splits 1-4 and
+// the model's, each with short runs and with whole-box runs.  The launches
+// read the bound state as both lambda and primal E and write only the
+// scratch arrays (and the per-item gradient sums, which every backward pass
+// overwrites); two interleaved passes of about 2 ms each, a candidate keeping
+// its faster.
+template <typename T>
+int tune_adjoint_t(xfdtd_batch_t b)
+{
+    b->atx = pick_adj_tx(b);
+    b->apick = AdjPick{};
+    int rc = build_adjoint<T>(b);  // the model's choice
+    if (rc) return rc;
+    std::vector<int> tys = {adj_tile_default(b)};
+    if (b->dtype == XFDTD_F32 && b->atx == 32 && tys[0] != 12) tys.push_back(12);
+    std::vector<int> zss = {1, 2, 3, 4};
+    if (std::find(zss.begin(), zss.end(), b->azs) == zss.end()) zss.push_back(b->azs);
+    std::vector<AdjPick> cands;
+    for (int ty : tys)
+        for (int zs : zss)
+            for (int run : {0, 1}) cands.push_back(AdjPick{b->atx, ty, zs, run});
+    struct Ev {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Ev()
+        {
+            for (hipEvent_t x : e)
+                if (x) hipEventDestroy(x);
+        }
+    } ev;
+    BTRY(hipEventCreate(&ev.e[0]), "hipEventCreate");
+    BTRY(hipEventCreate(&ev.e[1]), "hipEventCreate");
+    std::vector<double> per(cands.size(), INFINITY);
+    std::vector<int> reps(cands.size(), 0);
+    for (int pass = 0; pass < 2 && !rc; ++pass)
+        for (size_t c = 0; c < cands.size() && !rc; ++c) {
+            b->apick = cands[c];
+            rc = build_adjoint<T>(b);
+            if (rc) break;
+            std::vector<AdjDesc<T>> descs;
+            for (int64_t i = 0; i < b->m; ++i) {
+                Fields<T> fin, fout;
+                T *en[3];
+                for (int k = 0; k < 6; ++k) {
+                    fin.c[k] = (T *)b->f[(size_t)(6 * i + k)];
+                    fout.c[k] = (T *)b->s[(size_t)(6 * i + k)];
+                }
+                for (int k = 0; k < 3; ++k) en[k] = fin.c[k];
+                descs.push_back(adj_desc<T>(b, i, fin, fout, en));
+            }
+            AdjDesc<T> *d = nullptr;
+            rc = upload(descs, &d);
+            if (rc) break;
+            auto timed = [&](int r, float *ms) -> int {
+                BTRY(hipEventRecord(ev.e[0], b->stream), "hipEventRecord");
+                for (int i = 0; i < r; ++i) {
+                    const hipError_t e = launch_batched_adjoint<T>(d, b->d_aitems, b->d_aorder, b->naslots,
+                                                                   b->d_apart, 0, b->atx, adj_tile(b),
+                                                                   b->naslots, b->stream);
+                    if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched adjoint launch: %s", hipGetErrorString(e));
+                }
+                BTRY(hipEventRecord(ev.e[1], b->stream), "hipEventRecord");
+                BTRY(hipEventSynchronize(ev.e[1]), "hipEventSynchronize");
+                BTRY(hipEventElapsedTime(ms, ev.e[0], ev.e[1]), "hipEventElapsedTime");
+                return XFDTD_OK;
+            };
+            float ms = 0.f;
+            if (reps[c] == 0) {  // warm-up launch, whose time sizes the repetitions
+                rc = timed(1, &ms);
+                reps[c] = (int)std::min(50.0, std::max(3.0, ceil(2.0 / std::max(ms, 1e-3f))));
+            }
+            if (!rc) rc = timed(reps[c], &ms);
+            if (!rc) per[c] = std::min(per[c], (double)ms / reps[c]);
+            hipStreamSynchronize(b->stream);
+            hipFree(d);
+        }
+    if (rc) {
+        b->apick = AdjPick{};
+        return rc;
+    }
+    size_t best = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+        if (per[c] < per[best]) best = c;
+    b->apick = cands[best];
+    xlog("batched adjoint tune: %zu candidates, best %dx%d tiles, z-split %d, %s runs, %.2f us per step",
+         cands.size(), b->apick.tx, b->apick.ty, b->apick.zs, b->apick.boxrun ? "whole-box" : "short",
+         per[best] * 1e3);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_acache[b->key] = b->apick;
+    }
+    tune_cache_store("batchadj:" + b->key, {b->apick.tx, b->apick.ty, b->apick.zs, b->apick.boxrun});
+    return build_adjoint<T>(b);
+}
+
+// The adjoint's tiling for xfdtd_batch_tune.  lookup: take a choice of this
+// process or of the tuning file for the batch's shapes if there is one (else
+// keep the model's), instead of timing.
+int tune_adjoint(xfdtd_batch_t b, bool lookup)
+{
+    if (lookup) {
+        b->atx = pick_adj_tx(b);
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_acache.find(b->key);
+        std::vector<int> v;
+        if (it != g_acache.end()) {
+            b->apick = it->second;
+        } else if (tune_cache_lookup("batchadj:" + b->key, v) && v.size() == 4 && v[0] == b->atx &&
+                   (v[3] == 0 || v[3] == 1) && v[2] >= 1 && v[2] <= 1024) {
+            b->apick = AdjPick{v[0], v[1], v[2], v[3]};
+            if (!adj_tile_ok(b, v[1])) b->apick = AdjPick{};
+            else g_acache[b->key] = b->apick;
+        }
+        return XFDTD_OK;
+    }
+    return b->dtype == XFDTD_F32 ? tune_adjoint_t<float>(b) : tune_adjoint_t<double>(b);
 }
 
 // Workspaces: present, aligned, large enough and disjoint from each other.

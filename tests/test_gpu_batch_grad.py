@@ -94,6 +94,45 @@ def test_batch_grad_equals_single_box_fp32(shapes):
         assert np.abs(np.asarray(gb[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batch_grad_timed_adjoint_tiling_equals_single_boxes(dtype):
+    """xfdtd_batch_tune also times the batched adjoint's tilings; the timed
+    choice changes the launch only: states and adjoint fields bitwise equal
+    to the single-box schedule, gradients up to the order of the FP64
+    workgroup sums."""
+    shapes = [(30, 40, 96), (24, 24, 64), (40, 17, 70), (16, 20, 33)]
+    n = 11
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.extended_beta_delta(1810 + b)
+        c = O.coeffs_from(beta, delta)
+        boxes.append((shape, S.uniform_fields(shape, 1820 + b), c, 0.95 * O.cfl_dt(c),
+                      S.uniform_fields(shape, 1830 + b)))
+    tb = [to_dev(f, dtype) for (_, f, _, _, _) in boxes]
+    bt = pkg.Batch([(tb[i], dt, c) for i, (_, _, c, dt, _) in enumerate(boxes)], tune=True)
+    acfg = bt.adjoint_config()
+    print(f"forward {bt.config()}, timed adjoint tiling {acfg}")
+    assert acfg["tile_y"] in (4, 8, 12) and 1 <= acfg["zsplit"] <= 1024 and acfg["slots"] > 0
+    ws = bt.grad_workspaces(n)
+    bt.grad_forward(n, ws)
+    lb = [to_dev(l, dtype) for (*_, l) in boxes]
+    gb = bt.grad_backward(n, ws, lb)
+    assert bt.adjoint_config() == acfg
+    for i, (shape, f0, c, dt, lamN) in enumerate(boxes):
+        ts = to_dev(f0, dtype)
+        s = pkg.Solver(ts, dt, c, scratch=False)
+        w1 = torch.empty(s.grad_workspace_bytes(n), dtype=torch.uint8, device=DEV)
+        s.grad_forward(n, w1)
+        ls = to_dev(lamN, dtype)
+        gs = np.asarray(s.grad_backward(n, w1, ls))
+        torch.cuda.synchronize()
+        for a, b in zip(tb[i], ts):
+            assert torch.equal(a, b), (i, shape)
+        for a, b in zip(lb[i], ls):
+            assert torch.equal(a, b), (i, shape)
+        assert np.abs(np.asarray(gb[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
+
+
 def test_batch_grad_rejects_bad_workspaces():
     boxes = _boxes(950)[:2]
     t = [to_dev(f) for (_, f, _, _, _, _) in boxes]

@@ -68,9 +68,17 @@ def test_batch_tuning_file_round_trip(tmp_path, monkeypatch):
     launched = cfg["items"] if stored[3] == 0 or stored[3] > cfg["items"] else stored[3]
     assert stored[:3] + stored[4:] == [cfg["tile_x"], cfg["tile_y"], cfg["zsplit"], cfg["steps_per_pass"]]
     assert launched == cfg["grid"]
+    # the batched adjoint's timed tiling: tile width, height, z-split, whole-box runs
+    aline = [ln.split() for ln in path.read_text().splitlines()
+             if ln.split()[1] == "batchadj:f32:50x20x30:44x26x18"]
+    assert len(aline) == 1
+    acfg = bt.adjoint_config()
+    astored = [int(x) for x in aline[0][2:]]
+    assert astored[:3] == [acfg["tile_x"], acfg["tile_y"], acfg["zsplit"]] and astored[3] in (0, 1)
     dev = line[0][0]
-    # another set of shapes, stored: taken without timing
-    path.write_text(path.read_text() + f"{dev} batch:f32:40x24x16:36x36x20 32 8 2 0 1\n")
+    # another set of shapes, stored: taken without timing, the adjoint's tiling too
+    path.write_text(path.read_text() + f"{dev} batch:f32:40x24x16:36x36x20 32 8 2 0 1\n"
+                    + f"{dev} batchadj:f32:40x24x16:36x36x20 32 12 3 1\n")
     boxes2 = []
     for b, shape in enumerate([(16, 24, 40), (20, 36, 36)]):
         beta, delta = S.extended_beta_delta(1750 + b)
@@ -82,4 +90,9 @@ def test_batch_tuning_file_round_trip(tmp_path, monkeypatch):
     assert (c2["tile_x"], c2["tile_y"], c2["zsplit"], c2["steps_per_pass"]) == (32, 8, 2, 1)
     assert c2["grid"] == c2["items"]  # grid 0: one workgroup per slot
     bt2.run(4)
+    ws = bt2.grad_workspaces(5)
+    bt2.grad_forward(5, ws)
+    bt2.grad_backward(5, ws, [[torch.ones_like(x) for x in f] for (f, _, _) in boxes2])
+    a2 = bt2.adjoint_config()
+    assert (a2["tile_x"], a2["tile_y"], a2["zsplit"]) == (32, 12, 3)
     torch.cuda.synchronize()
