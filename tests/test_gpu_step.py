@@ -325,7 +325,7 @@ def test_two_step_kernel_fp64_equals_one_step_and_oracle(env, shape):
 
 
 @pytest.mark.parametrize("dtype,shape,spp", [(torch.float32, (33, 17, 64), 1), (torch.float32, (37, 45, 150), 2),
-                                             (torch.float64, (20, 18, 70), 1)])
+                                             (torch.float64, (20, 18, 70), 1), (torch.float64, (21, 19, 50), 2)])
 def test_run_graph_replay_is_bitwise_the_direct_launches(env, dtype, shape, spp):
     """xfdtd_run replays a captured graph of 32 steps and launches the rest
     directly: bitwise the same as direct launches only, for step counts below,

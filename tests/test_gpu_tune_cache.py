@@ -13,10 +13,10 @@ from tests._gpu import to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _solver(shape, seed):
+def _solver(shape, seed, dtype=torch.float32):
     beta, delta = S.extended_beta_delta(seed)
     c = O.coeffs_from(beta, delta)
-    return pkg.Solver(to_dev(S.uniform_fields(shape, seed + 1), torch.float32), 0.9 * O.cfl_dt(c), c)
+    return pkg.Solver(to_dev(S.uniform_fields(shape, seed + 1), dtype), 0.9 * O.cfl_dt(c), c)
 
 
 def test_tuning_file_round_trip(tmp_path, monkeypatch):
@@ -47,6 +47,16 @@ def test_tuning_file_round_trip(tmp_path, monkeypatch):
     s3 = _solver((28, 20, 72), 1720)
     s3.tune()
     assert s3.tuned_ms > 0
+    # FP64: the two-step kernel's 24x8 tiles are taken, its 32x8 FP32 tiles are not
+    path.write_text(text + f"{dev} single:f64:60x26x30 2 24 8 10\n" + f"{dev} single:f64:44x22x18 2 32 8 6\n")
+    s4 = _solver((30, 26, 60), 1730, torch.float64)
+    lc4 = s4.tune()
+    assert s4.tuned_ms == -1.0
+    assert lc4["steps_per_pass"] == 2 and (lc4["two_step"]["tile_x"], lc4["two_step"]["tile_y"],
+                                           lc4["two_step"]["zchunk"]) == (24, 8, 10)
+    s5 = _solver((18, 22, 44), 1740, torch.float64)
+    s5.tune()
+    assert s5.tuned_ms > 0
 
 
 def test_batch_tuning_file_round_trip(tmp_path, monkeypatch):
