@@ -15,11 +15,11 @@
 // (times dt/d_a and the term's sign); the neighbour sums of mu are exactly
 // those the stars use, so the gradient costs a few FMAs per cell.
 //
-// The kernel mirrors fused_step_kernel: a workgroup owns a 64 x TY tile,
-// marches a chunk of z-planes, stages lE', mu and the stars in LDS for x/y
-// neighbours and keeps z-neighbours in registers; the primal E neighbours
-// that the gradient needs (x+1, y+1) are re-read through L1/L2.  HBM traffic
-// per cell: read lE', lB', E (9 values), write lE, lB (6 values).
+// The kernel mirrors fused_step_kernel: a workgroup owns a TX x TY tile
+// (TX = 64 or 32), marches a chunk of z-planes, stages lE', mu, the stars of
+// mu and the primal E (whose x+1 / y+1 neighbours the gradient needs) in LDS
+// for x/y neighbours and keeps z-neighbours in registers.  HBM traffic per
+// cell: read lE', lB', E (9 values), write lE, lB (6 values).
 // Per-workgroup gradient sums (unscaled, FP64) go to `partials`.
 
 #include <type_traits>
