@@ -94,13 +94,17 @@ def test_batch_grad_equals_single_box_fp32(shapes):
         assert np.abs(np.asarray(gb[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_batch_grad_timed_adjoint_tiling_equals_single_boxes(dtype):
+@pytest.mark.parametrize("dtype,shapes", [
+    (torch.float32, [(30, 40, 96), (24, 24, 64), (40, 17, 70), (16, 20, 33)]),
+    (torch.float64, [(30, 40, 96), (24, 24, 64), (40, 17, 70), (16, 20, 33)]),
+    # degenerate boxes: one-cell planes and columns, a 3-wide box, a ragged 130-wide one
+    (torch.float32, [(5, 4, 3), (1, 1, 5), (7, 1, 64), (9, 33, 130)]),
+    (torch.float64, [(5, 4, 3), (1, 1, 5), (7, 1, 64), (9, 33, 130)])])
+def test_batch_grad_timed_adjoint_tiling_equals_single_boxes(dtype, shapes):
     """xfdtd_batch_tune also times the batched adjoint's tilings; the timed
     choice changes the launch only: states and adjoint fields bitwise equal
     to the single-box schedule, gradients up to the order of the FP64
     workgroup sums."""
-    shapes = [(30, 40, 96), (24, 24, 64), (40, 17, 70), (16, 20, 33)]
     n = 11
     boxes = []
     for b, shape in enumerate(shapes):
