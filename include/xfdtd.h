@@ -152,7 +152,11 @@ int xfdtd_step_ampere_current(xfdtd_t h, const void *const J[3]);
 /* n >= 0 full steps (Faraday then Ampere each); the result is in the bound
  * fields when the queued work completes.  With scratch arrays bound, FP32
  * handles advance two steps per pass over the fields by default (see
- * xfdtd_set_steps_per_pass). */
+ * xfdtd_set_steps_per_pass).  Runs of 32 steps or more replay a HIP graph of
+ * 32 steps captured on the first such call (again when the bound arrays,
+ * stream or launch configuration change); XFDTD_GRAPH=0 at xfdtd_create
+ * launches every step directly.  Both orders of launches give bitwise the
+ * same result. */
 int xfdtd_run(xfdtd_t h, int64_t n);
 
 /*
@@ -175,7 +179,10 @@ int xfdtd_set_steps_per_pass(xfdtd_t h, int steps);
 /* Launch configuration of the two-step kernel for this handle, and the steps
  * per pass xfdtd_run uses (1 or 2): tile width and height of its output tiles
  * (32 x 8 or 32 x 16 in FP32, 24 x 8 in FP64), z-planes per workgroup,
- * workgroups per launch.  Any pointer may be NULL.  Host only. */
+ * workgroups per launch.  Any pointer may be NULL.  Until xfdtd_tune is
+ * called the tile height and z-planes come from the grid, overridable with
+ * XFDTD_BLK_TILE_Y (FP32: 8 or 16) and XFDTD_BLK_ZCHUNK read at
+ * xfdtd_create.  Host only. */
 int xfdtd_launch_config2(xfdtd_t h, int *steps_per_pass, int *tile_x, int *tile_y, int *zchunk,
                          int *workgroups);
 
