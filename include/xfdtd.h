@@ -483,8 +483,11 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     dispatched as one run or in runs of a few tiles.  best_ms (nullable)
  *     receives the forward's best time per step (-1 when taken from the
  *     cache; the adjoint's choice is then also taken from the cache if it
- *     holds one, else the model below chooses).  Synchronises the stream;
- *     on failure the previous forward configuration stays.
+ *     holds one, else the model below chooses).  Synchronises the stream.
+ *     A failure while timing the forward candidates keeps the previous
+ *     forward configuration; a failure while timing the adjoint's keeps the
+ *     new forward configuration and leaves the adjoint's tiling to the
+ *     model; either returns the error.
  * xfdtd_batch_set_config / get_config: choose / report the configuration:
  *     tile_x 64 or 32, tile_y 4, 8 or 16 (16: FP32 only), zsplit 0..1024
  *     (zsplit >= 1: each box is cut into z-chunks of ceil(nz / zsplit) >= 4
