@@ -2,6 +2,7 @@
 appended, a stored line for a grid not tuned in this process is taken
 without timing, lines a handle cannot launch and malformed lines are
 ignored, and batches do the same with their shape keys."""
+import numpy as np
 import pytest
 import torch
 
@@ -106,3 +107,31 @@ def test_batch_tuning_file_round_trip(tmp_path, monkeypatch):
     a2 = bt2.adjoint_config()
     assert (a2["tile_x"], a2["tile_y"], a2["zsplit"]) == (32, 12, 3)
     torch.cuda.synchronize()
+
+
+def test_batch_adjoint_line_the_batch_cannot_launch_is_ignored(tmp_path, monkeypatch):
+    """A stored adjoint tiling with a tile FP64 lacks (32x12) is not taken:
+    the model's tiling runs, and the gradient pass completes."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("XFDTD_TUNE_CACHE", str(path))
+    shapes = [(14, 18, 40), (10, 22, 36)]
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.extended_beta_delta(1770 + b)
+        c = O.coeffs_from(beta, delta)
+        boxes.append((to_dev(S.uniform_fields(shape, 1780 + b), torch.float64), 0.9 * O.cfl_dt(c), c))
+    # learn this device's tag from a timed tuning of another shape set
+    probe = pkg.Batch([(to_dev(S.uniform_fields((8, 8, 16), 1790), torch.float64), boxes[0][1], boxes[0][2])],
+                      tune=True)
+    dev = path.read_text().split()[0]
+    del probe
+    key = "f64:40x18x14:36x22x10"
+    path.write_text(f"{dev} batch:{key} 32 8 1 0 1\n{dev} batchadj:{key} 32 12 2 0\n")
+    bt = pkg.Batch(boxes, tune=True)
+    assert bt.tuned_ms == -1.0 and bt.config()["tile_x"] == 32
+    ws = bt.grad_workspaces(4)
+    bt.grad_forward(4, ws)
+    g = bt.grad_backward(4, ws, [[torch.ones_like(x) for x in f] for (f, _, _) in boxes])
+    a = bt.adjoint_config()
+    assert a["tile_x"] == 32 and a["tile_y"] in (4, 8), a
+    assert all(np.isfinite(np.asarray(gi)).all() for gi in g)
