@@ -6,6 +6,8 @@ benchmark times (fused kernel, tiling chosen by the autotuner):
   FP32 to 1e-5 relative L2 both against the oracle run with the FP32 weights
   (FP32 convention of tests/_fp32.py) and against the plain-coefficient
   oracle from FP64 inputs;
+* the same 1000 steps on the FP64 two-step kernel (FP64's non-default
+  kernel), sampled, to 1e-12;
 * 3 steps, full field, against the C oracle;
 * 1000 steps of an exact discrete eigenmode against its closed form;
 * the 1024x256x256 pulse of the sustained run: 100 steps against sampled
@@ -64,6 +66,27 @@ def test_c2_pulse_1000_steps_vs_oracle_samples(dtype, variant, tol):
     err = _rel(got, ref["vals"])
     print(f"c2 {dtype} vs {variant} oracle: sampled rel L2 = {err:.3e} ({lc})")
     assert err < tol
+
+
+def test_c2_pulse_1000_steps_fp64_two_step_kernel_vs_oracle_samples():
+    """The FP64 two-step kernel (24x8 tiles, not FP64's default) over the
+    1000 steps of the pulse workload: 500 launches, sampled outputs against
+    the FP64 oracle to 1e-12."""
+    path = os.path.join(GOLD, "c2_pulse_exact.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    ref = np.load(path)
+    f0, c, dt, sp = W.c2_inputs()
+    t = to_dev(f0, torch.float64)
+    del f0
+    s = pkg.Solver(t, dt, c, spacing=sp)
+    s.set_steps_per_pass(2)
+    s.reset_stats()
+    s.run(int(ref["steps"]))
+    assert s.stats()["two_step_launches"] == int(ref["steps"]) // 2
+    err = _rel(_sampled(t, ref["idx"]), ref["vals"])
+    print(f"c2 FP64 two-step kernel vs oracle: sampled rel L2 = {err:.3e} ({s.launch_config()['two_step']})")
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("dtype,variant,tol", [(torch.float64, "exact", 1e-12),
