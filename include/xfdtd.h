@@ -478,9 +478,10 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     the fastest per step, and caches it per set of box shapes (force = 1
  *     re-times).  It then times the batched adjoint's tilings for the
  *     gradient passes the same way (the state read as lambda and primal E,
- *     the scratch arrays written): the default tile height and, for FP32
- *     32-column tiles, 12; z-split 1-4 and the model's; each box's items
- *     dispatched as one run or in runs of a few tiles.  best_ms (nullable)
+ *     the scratch arrays written): the tile width of the column-count rule
+ *     below and, where that is 32, 64 as well; the default tile height and,
+ *     for FP32 32-column tiles, 12; z-split 1-4 and the model's; each box's
+ *     items dispatched as one run or in runs of a few tiles.  best_ms (nullable)
  *     receives the forward's best time per step (-1 when taken from the
  *     cache; the adjoint's choice is then also taken from the cache if it
  *     holds one, else the model below chooses).  Synchronises the stream.
@@ -533,11 +534,13 @@ int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps);
  * The batched adjoint's launch configuration, chosen by each
  * xfdtd_batch_grad_backward and by xfdtd_batch_tune (all 0 before either):
  * tile_x 32 or 64; tile_y 4, 8, or 12 (FP32 32-column tiles only); zsplit,
- * the z-chunks per box; nslots, its dispatch slots.  The tile height and
- * z-split are the ones xfdtd_batch_tune timed fastest for the batch's shapes
- * (while the adjoint's tile width is the one they were timed with), else
- * those of a list-scheduling model of the work list (tile positions x planes
- * per item).  XFDTD_EINVAL for a null handle.  Host only.
+ * the z-chunks per box; nslots, its dispatch slots.  The tiling is the one
+ * xfdtd_batch_tune timed fastest for the batch's shapes; untuned, the tile
+ * width is 32 where the forward runs 32-column tiles or every box is at most
+ * 96 wide and 32-column tiles load fewer columns in all (64 otherwise), and
+ * the height and z-split those of a
+ * list-scheduling model of the work list (tile positions x planes per item).
+ * XFDTD_EINVAL for a null handle.  Host only.
  */
 int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *nslots);
 

@@ -1176,7 +1176,7 @@ template <typename T>
 int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, void *const *lam, double *grad)
 {
     const int64_t m = b->m;
-    b->atx = pick_adj_tx(b);
+    b->atx = b->apick.tx ? b->apick.tx : pick_adj_tx(b);
     int rc = build_adjoint<T>(b);
     if (rc) return rc;
     const int64_t nck = n > 0 ? (n + seg - 1) / seg : 1;
@@ -1342,18 +1342,25 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
 template <typename T>
 int tune_adjoint_t(xfdtd_batch_t b)
 {
-    b->atx = pick_adj_tx(b);
-    b->apick = AdjPick{};
-    int rc = build_adjoint<T>(b);  // the model's choice
-    if (rc) return rc;
-    std::vector<int> tys = {adj_tile_default(b)};
-    if (b->dtype == XFDTD_F32 && b->atx == 32 && tys[0] != 12) tys.push_back(12);
-    std::vector<int> zss = {1, 2, 3, 4};
-    if (std::find(zss.begin(), zss.end(), b->azs) == zss.end()) zss.push_back(b->azs);
+    const int tx0 = pick_adj_tx(b);
     std::vector<AdjPick> cands;
-    for (int ty : tys)
-        for (int zs : zss)
-            for (int run : {0, 1}) cands.push_back(AdjPick{b->atx, ty, zs, run});
+    // widths: the column-count rule's, and 64 where it chose 32 (the 64-column
+    // kernel does more per cell it computes, which can outweigh idle columns)
+    for (int tx : {tx0, 64}) {
+        if (tx == 64 && tx0 == 64 && !cands.empty()) continue;
+        b->atx = tx;
+        b->apick = AdjPick{};
+        const int rc = build_adjoint<T>(b);  // the model's choice for this width
+        if (rc) return rc;
+        std::vector<int> tys = {adj_tile_default(b)};
+        if (b->dtype == XFDTD_F32 && tx == 32 && tys[0] != 12) tys.push_back(12);
+        std::vector<int> zss = {1, 2, 3, 4};
+        if (std::find(zss.begin(), zss.end(), b->azs) == zss.end()) zss.push_back(b->azs);
+        for (int ty : tys)
+            for (int zs : zss)
+                for (int run : {0, 1}) cands.push_back(AdjPick{tx, ty, zs, run});
+    }
+    int rc = XFDTD_OK;
     struct Ev {
         hipEvent_t e[2] = {nullptr, nullptr};
         ~Ev()
@@ -1369,6 +1376,7 @@ int tune_adjoint_t(xfdtd_batch_t b)
     for (int pass = 0; pass < 2 && !rc; ++pass)
         for (size_t c = 0; c < cands.size() && !rc; ++c) {
             b->apick = cands[c];
+            b->atx = cands[c].tx;
             rc = build_adjoint<T>(b);
             if (rc) break;
             std::vector<AdjDesc<T>> descs;
@@ -1410,12 +1418,14 @@ int tune_adjoint_t(xfdtd_batch_t b)
         }
     if (rc) {
         b->apick = AdjPick{};
+        b->atx = tx0;
         return rc;
     }
     size_t best = 0;
     for (size_t c = 1; c < cands.size(); ++c)
         if (per[c] < per[best]) best = c;
     b->apick = cands[best];
+    b->atx = b->apick.tx;
     xlog("batched adjoint tune: %zu candidates, best %dx%d tiles, z-split %d, %s runs, %.2f us per step",
          cands.size(), b->apick.tx, b->apick.ty, b->apick.zs, b->apick.boxrun ? "whole-box" : "short",
          per[best] * 1e3);
@@ -1439,11 +1449,16 @@ int tune_adjoint(xfdtd_batch_t b, bool lookup)
         std::vector<int> v;
         if (it != g_acache.end()) {
             b->apick = it->second;
-        } else if (tune_cache_lookup("batchadj:" + b->key, v) && v.size() == 4 && v[0] == b->atx &&
+        } else if (tune_cache_lookup("batchadj:" + b->key, v) && v.size() == 4 && (v[0] == 32 || v[0] == 64) &&
                    (v[3] == 0 || v[3] == 1) && v[2] >= 1 && v[2] <= 1024) {
-            b->apick = AdjPick{v[0], v[1], v[2], v[3]};
-            if (!adj_tile_ok(b, v[1])) b->apick = AdjPick{};
-            else g_acache[b->key] = b->apick;
+            const int tx = b->atx;
+            b->atx = v[0];
+            if (adj_tile_ok(b, v[1])) {
+                b->apick = AdjPick{v[0], v[1], v[2], v[3]};
+                g_acache[b->key] = b->apick;
+            } else {
+                b->atx = tx;
+            }
         }
         return XFDTD_OK;
     }
