@@ -149,12 +149,13 @@ def test_default_tile_width(nx, tx):
 
 
 @pytest.mark.parametrize("shape", [(96, 96, 96), (128, 128, 128), (256, 256, 512), (192, 192, 352), (9, 40, 70),
-                                   (300, 8, 8)])
+                                   (300, 8, 8), (32, 32, 32), (64, 64, 64)])
 def test_default_zchunk_minimises_round_cost(shape):
     """Without a device the library assumes 256 CUs with one resident
-    workgroup each; the default z-chunk then minimises rounds x (z + 3) over
-    the balanced chunk lengths ceil(nz / c) >= 4 (or nz), checked by brute
-    force over every chunk count c."""
+    workgroup each; the default z-chunk of the one-step kernel then minimises
+    rounds x (z + 3) over the balanced chunk lengths ceil(nz / c), down to
+    one plane (a box too small to fill the CUs takes short chunks), checked
+    by brute force over every chunk count c."""
     rc, h = _create(shape=shape)
     assert rc == 0
     v = [ctypes.c_int() for _ in range(4)]
@@ -168,7 +169,6 @@ def test_default_zchunk_minimises_round_cost(shape):
         return -(-tiles * -(-nz // z) // 256) * (z + 3)
 
     zs = [-(-nz // c) for c in range(1, nz + 1)]
-    zs = [z for z in zs if z >= 4 or z == nz]
     assert cost(zc) == min(cost(z) for z in zs)
 
 
