@@ -57,7 +57,7 @@ def test_adjoint_tilings_agree_fp32(monkeypatch, shape):
     outs, grads = [], []
     for tx in ("64", "32"):
         for ty in ("4", "8"):
-            for zc in ("3", "64"):
+            for zc in ("1", "2", "3", "64"):
                 monkeypatch.setenv("XFDTD_ADJ_TILE_X", tx)
                 monkeypatch.setenv("XFDTD_ADJ_TILE_Y", ty)
                 monkeypatch.setenv("XFDTD_ADJ_ZCHUNK", zc)
