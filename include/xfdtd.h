@@ -215,8 +215,12 @@ int xfdtd_launch_config(xfdtd_t h, int *tile_x, int *tile_y, int *zchunk, int *w
  * the fused step's tile widths 64 and 32, tile heights 8 and 16 (FP32; 4 and
  * 8 for FP64) and the two-step kernel's tiles (32 x 8 and 32 x 16 in FP32,
  * 24 x 8 in FP64),
- * each with a few z-chunk lengths, with launches that read the bound fields
- * and write only the scratch arrays (the state is unchanged); keeps the
+ * each with a few z-chunk lengths, with launches that alternate between the
+ * scratch arrays and a temporary copy of the state (allocated for the call
+ * and freed before it returns; the memory pattern of xfdtd_run, whose every
+ * launch reads what the previous one wrote), or that read the bound fields
+ * and write the scratch arrays when that copy cannot be allocated (the state
+ * is unchanged either way); keeps the
  * fastest per step (setting the steps per pass) and caches it per (grid size,
  * dtype, device); force = 1 re-times, otherwise a cached choice is taken.
  * best_ms (nullable) receives the best time per step (-1 when taken from the

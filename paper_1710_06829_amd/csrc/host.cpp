@@ -741,6 +741,39 @@ int tune_t(xfdtd_t h, double *best_ms)
         for (int z : zchunk_candidates(h->g, blocked2_zchunk(h->g, 24, 8, XFDTD_F64)))
             if (fits(24, 8, z)) cands.push_back({2, 24, 8, z});
     }
+    // Launches alternate between the scratch arrays and a temporary third
+    // state (a copy of the fields), the memory pattern of xfdtd_run, whose
+    // every launch reads what the previous one wrote: timing launches that
+    // all read the unchanged fields lets a state of about the size of the
+    // last-level cache stay there and favours the wrong kernel (128x256x256
+    // FP32: the one-step kernel timed at 65.7 us per step ran 90.3 us).
+    // Without the temporary (allocation failed) they run fields -> scratch.
+    struct Temp {
+        void *p = nullptr;
+        ~Temp()
+        {
+            if (p) hipFree(p);
+        }
+    } temp;
+    const size_t esz = sizeof(T), fbytes = ((size_t)h->g.nx * h->g.ny * h->g.nz * esz + 255) / 256 * 256;
+    Fields<T> t = s;
+    if (hipMalloc(&temp.p, 6 * fbytes) == hipSuccess) {
+        for (int c = 0; c < 6; ++c) {
+            t.c[c] = (T *)((char *)temp.p + (size_t)c * fbytes);
+            HIP_TRY(hipMemcpyAsync(t.c[c], f.c[c], (size_t)h->g.nx * h->g.ny * h->g.nz * esz,
+                                   hipMemcpyDeviceToDevice, h->stream),
+                    "hipMemcpyAsync");
+        }
+    } else {
+        (void)hipGetLastError();
+        temp.p = nullptr;
+        t = f;
+    }
+    // The temporary is freed once the stream has drained (before Temp goes).
+    struct Drain {
+        hipStream_t s;
+        ~Drain() { hipStreamSynchronize(s); }
+    } drain{h->stream};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     hipError_t he = hipEventCreate(&e1);
@@ -758,9 +791,13 @@ int tune_t(xfdtd_t h, double *best_ms)
             const auto &c = cands[i];
             auto timed = [&](int r, float *ms) {
                 hipError_t e = hipEventRecord(e0, h->stream);
-                for (int q = 0; q < r && e == hipSuccess; ++q)
-                    e = c[0] == 2 ? launch_blocked2<T>(f, s, d, w, c[1], c[2], c[3], h->stream)
-                                  : launch_fused<T>(f, s, d, w, c[1], c[2], c[3], h->stream);
+                for (int q = 0; q < r && e == hipSuccess; ++q) {
+                    // without the temporary, every launch reads the fields
+                    const bool back = temp.p && (q & 1);
+                    const Fields<T> &in = back ? s : t, &out = back ? t : s;
+                    e = c[0] == 2 ? launch_blocked2<T>(in, out, d, w, c[1], c[2], c[3], h->stream)
+                                  : launch_fused<T>(in, out, d, w, c[1], c[2], c[3], h->stream);
+                }
                 if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -785,6 +822,10 @@ int tune_t(xfdtd_t h, double *best_ms)
             bestc = cands[i];
         }
     if (bestc[1] == 0) return fail(XFDTD_EHIP, "no tiling could be timed");
+    if (log_on())
+        for (size_t i = 0; i < cands.size(); ++i)
+            xlog("tune candidate %s %dx%d tiles, z-chunk %d: %.2f us per step", cands[i][0] == 2 ? "two-step" : "one-step",
+                 cands[i][1], cands[i][2], cands[i][3], per[i] * 1e3);
     h->spp = bestc[0];
     if (bestc[0] == 2) {
         h->btile_x = bestc[1];
