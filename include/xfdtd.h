@@ -478,8 +478,10 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     z-split of the step cost model below, persistent grid of 1x/2x the CU
  *     count or one workgroup per work-list slot; for FP32 also the two-step
  *     kernel on 32 x 8 and 32 x 16 tiles with z-split 1, 2 or 0) with
- *     launches that read the state and write only the scratch arrays, keeps
- *     the fastest per step, and caches it per set of box shapes (force = 1
+ *     launches that alternate between the scratch arrays and a temporary
+ *     copy of the state (allocated for the call; without it, launches that
+ *     read the state and write the scratch arrays), keeps the fastest per
+ *     step, and caches it per set of box shapes (force = 1
  *     re-times).  It then times the batched adjoint's tilings for the
  *     gradient passes the same way (the state read as lambda and primal E,
  *     the scratch arrays written): the tile width of the column-count rule

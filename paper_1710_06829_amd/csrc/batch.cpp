@@ -409,25 +409,41 @@ int grid_of(const xfdtd_batch_t b)
     return (g <= 0 || g > b->nitems) ? b->nitems : g;
 }
 
-int launch_step(xfdtd_batch_t b, int parity, hipStream_t s)
+// descs: the descriptor array to launch with (nullptr: the batch's own)
+int launch_step(xfdtd_batch_t b, int parity, hipStream_t s, const void *descs = nullptr)
 {
+    const void *dd = descs ? descs : b->d_boxes;
     hipError_t e;
     if (b->dtype == XFDTD_F32)
-        e = launch_batched<float>((const BoxDesc<float> *)b->d_boxes, b->d_items, b->nitems, parity,
-                                  b->cfg.tile_x, b->cfg.tile_y, grid_of(b), s);
+        e = launch_batched<float>((const BoxDesc<float> *)dd, b->d_items, b->nitems, parity, b->cfg.tile_x,
+                                  b->cfg.tile_y, grid_of(b), s);
     else
-        e = launch_batched<double>((const BoxDesc<double> *)b->d_boxes, b->d_items, b->nitems, parity,
-                                   b->cfg.tile_x, b->cfg.tile_y, grid_of(b), s);
+        e = launch_batched<double>((const BoxDesc<double> *)dd, b->d_items, b->nitems, parity, b->cfg.tile_x,
+                                   b->cfg.tile_y, grid_of(b), s);
     if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched launch: %s", hipGetErrorString(e));
     return XFDTD_OK;
 }
 
 // One two-step launch (cfg.spp == 2): two steps of every box.
-int launch_pair(xfdtd_batch_t b, int parity, hipStream_t s)
+int launch_pair(xfdtd_batch_t b, int parity, hipStream_t s, const void *descs = nullptr)
 {
-    const hipError_t e = launch_batched2<float>((const BoxDesc<float> *)b->d_boxes, b->d_items, b->nitems, parity,
+    const void *dd = descs ? descs : b->d_boxes;
+    const hipError_t e = launch_batched2<float>((const BoxDesc<float> *)dd, b->d_items, b->nitems, parity,
                                                 b->cfg.tile_y, grid_of(b), s);
     if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched two-step launch: %s", hipGetErrorString(e));
+    return XFDTD_OK;
+}
+
+// The batch's descriptors (as last built) with each box's fields replaced by
+// its arrays in `tmp` (6 per box), uploaded to d_out (m descriptors).
+template <typename T>
+int temp_descs_t(xfdtd_batch_t b, const std::vector<void *> &tmp, void *d_out)
+{
+    std::vector<BoxDesc<T>> h((size_t)b->m);
+    BTRY(hipMemcpy(h.data(), b->d_boxes, sizeof(BoxDesc<T>) * h.size(), hipMemcpyDeviceToHost), "hipMemcpy");
+    for (int64_t i = 0; i < b->m; ++i)
+        for (int c = 0; c < 6; ++c) h[(size_t)i].f.c[c] = (T *)tmp[(size_t)(6 * i + c)];
+    BTRY(hipMemcpy(d_out, h.data(), sizeof(BoxDesc<T>) * h.size(), hipMemcpyHostToDevice), "hipMemcpy");
     return XFDTD_OK;
 }
 
@@ -740,15 +756,64 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             return set_error(XFDTD_EHIP, "hipEventCreate failed");
         }
         // Two interleaved passes over the candidates; each timing covers about
-        // 2 ms of steps (f -> s only: the bound state is not modified) and a
-        // candidate keeps its faster pass.
+        // 2 ms of steps and a candidate keeps its faster pass.  The launches
+        // alternate between the scratch arrays and a temporary copy of the
+        // state, as runs alternate between the fields and the scratch arrays
+        // (every launch reads what the previous one wrote; launches that all
+        // read the unchanged fields can keep a state of about the size of the
+        // last-level cache there); without the temporary they run f -> s.  The
+        // bound state is not modified.
+        struct Temp {
+            void *state = nullptr, *descs = nullptr;
+            hipStream_t s;
+            ~Temp()
+            {
+                hipStreamSynchronize(s);
+                if (state) hipFree(state);
+                if (descs) hipFree(descs);
+            }
+        } temp{nullptr, nullptr, b->stream};
+        std::vector<void *> tmp((size_t)(6 * b->m));
+        {
+            const size_t esz = b->dtype == XFDTD_F32 ? 4 : 8;
+            std::vector<size_t> off;
+            size_t total = 0;
+            for (int64_t i = 0; i < b->m; ++i) {
+                const size_t bytes = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
+                for (int c = 0; c < 6; ++c) {
+                    off.push_back(total);
+                    total += (bytes + 255) / 256 * 256;
+                }
+            }
+            const size_t dsz = b->dtype == XFDTD_F32 ? sizeof(BoxDesc<float>) : sizeof(BoxDesc<double>);
+            if (hipMalloc(&temp.state, std::max<size_t>(256, total)) == hipSuccess &&
+                hipMalloc(&temp.descs, dsz * (size_t)b->m) == hipSuccess) {
+                for (int64_t i = 0; i < b->m; ++i) {
+                    const size_t bytes = (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * esz;
+                    for (int c = 0; c < 6; ++c) {
+                        const size_t k = (size_t)(6 * i + c);
+                        tmp[k] = (char *)temp.state + off[k];
+                        BTRY(hipMemcpyAsync(tmp[k], b->f[k], bytes, hipMemcpyDeviceToDevice, b->stream),
+                             "hipMemcpyAsync");
+                    }
+                }
+            } else {
+                (void)hipGetLastError();
+                if (temp.state) hipFree(temp.state);
+                temp.state = nullptr;
+            }
+        }
         std::vector<double> per(cands.size(), INFINITY);
         std::vector<int> reps(cands.size(), 0);
         const Config prev = b->cfg;
         int rc = XFDTD_OK;
         auto timed = [&](int r, float *ms) {
             int q = hipEventRecord(e0, b->stream) == hipSuccess ? XFDTD_OK : set_error(XFDTD_EHIP, "event record");
-            for (int i = 0; i < r && !q; ++i) q = b->cfg.spp == 2 ? launch_pair(b, 0, b->stream) : launch_step(b, 0, b->stream);
+            const void *dd = temp.state ? temp.descs : nullptr;
+            for (int i = 0; i < r && !q; ++i) {
+                const int par = temp.state ? (i & 1) : 0;
+                q = b->cfg.spp == 2 ? launch_pair(b, par, b->stream, dd) : launch_step(b, par, b->stream, dd);
+            }
             if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = set_error(XFDTD_EHIP, "event record");
             if (!q && hipEventSynchronize(e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event synchronize");
             if (!q && hipEventElapsedTime(ms, e0, e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event time");
@@ -758,6 +823,9 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             for (size_t i = 0; i < cands.size() && !rc; ++i) {
                 b->cfg = cands[i];
                 rc = build(b);
+                if (!rc && temp.state)
+                    rc = b->dtype == XFDTD_F32 ? temp_descs_t<float>(b, tmp, temp.descs)
+                                               : temp_descs_t<double>(b, tmp, temp.descs);
                 if (rc) break;
                 float ms = 0.f;
                 if (reps[i] == 0) {  // warm-up step, whose time sizes the repetitions
