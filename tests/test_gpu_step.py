@@ -370,9 +370,10 @@ def test_two_step_kernel_rejects_bad_counts():
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_tuner_keeps_state_and_result(dtype):
-    """Tuning reads the state and writes only scratch; the tuned tiling gives
-    bitwise the same steps as the default one, and a second handle of the same
-    shape takes the cached choice."""
+    """Tuning reads the state and writes only the scratch arrays and its own
+    temporary copy of the state; the tuned tiling gives bitwise the same steps
+    as the default one, and a second handle of the same shape takes the
+    cached choice."""
     shape = (40, 37, 96)
     c = _coeffs(495)
     dt = 0.95 * O.cfl_dt(c)
