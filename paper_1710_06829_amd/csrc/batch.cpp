@@ -844,6 +844,11 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             set_error(rc, "%s", msg.c_str());
             return rc;
         }
+        if (log_on())
+            for (size_t i = 0; i < cands.size(); ++i)
+                xlog("batch tune candidate %s %dx%d tiles, z-split %d, grid %d: %.2f us per step",
+                     cands[i].spp == 2 ? "two-step" : "one-step", cands[i].tile_x, cands[i].tile_y, cands[i].zsplit,
+                     cands[i].grid, per[i] * 1e3);
         double best = INFINITY;
         Config bestc = prev;
         for (size_t i = 0; i < cands.size(); ++i)
