@@ -724,7 +724,11 @@ int tune_t(xfdtd_t h, double *best_ms)
     auto fits = [&](int tx, int ty, int z) {
         return ((d.nx + tx - 1) / tx) * (int64_t)((d.ny + ty - 1) / ty) * ((h->g.nz + z - 1) / z) <= 0x7fffffff;
     };
+    // a box one plane deep: every one-step tiling runs the plane kernel, and
+    // the two-step kernel's warm-up makes it several times slower there
+    if (h->g.nz == 1) cands.push_back({1, 64, sizeof(T) == 4 ? 16 : 8, 1});
     for (int tx : {64, 32}) {
+        if (h->g.nz == 1) break;
         std::vector<int> tys = {sizeof(T) == 4 ? 8 : 4, sizeof(T) == 4 ? 16 : 8};
         // FP32 boxes too small for 4-plane chunks of 8-row tiles: 4-row tiles too
         if (sizeof(T) == 4 && auto_zchunk(h->g, tx, 8, fused_slots(h->dtype, tx, 8), 3, 1) < 4)
@@ -733,7 +737,8 @@ int tune_t(xfdtd_t h, double *best_ms)
             for (int z : zchunk_candidates(h->g, auto_zchunk(h->g, tx, ty, fused_slots(h->dtype, tx, ty), 3, 1)))
                 if (fits(tx, ty, z)) cands.push_back({1, tx, ty, z});
     }
-    if (sizeof(T) == 4) {
+    if (h->g.nz == 1) {
+    } else if (sizeof(T) == 4) {
         for (int ty : {8, 16})
             for (int z : zchunk_candidates(h->g, blocked2_zchunk(h->g, 32, ty)))
                 if (fits(32, ty, z)) cands.push_back({2, 32, ty, z});
@@ -931,17 +936,26 @@ int xfdtd_create(const xfdtd_grid *g, double dt, const double coeffs[12], int dt
         const char *ty = getenv("XFDTD_TILE_Y");
         if (ty && (atoi(ty) == 4 || atoi(ty) == 8 || (atoi(ty) == 16 && dtype == XFDTD_F32))) h->tile_y = atoi(ty);
         h->zchunk = pick_zchunk(*g, h->tile_x, h->tile_y, dtype);
+        // a box one plane deep runs the plane kernel (64x16 tiles in FP32,
+        // 64x8 in FP64) whatever the tiling; report that one
+        if (g->nz == 1) {
+            h->tile_x = 64;
+            h->tile_y = dtype == XFDTD_F32 ? 16 : 8;
+            h->zchunk = 1;
+        }
     // two-step kernel: 32-column tiles (FP32), 24 x 8 (FP64); the default
     // steps per pass can be overridden with XFDTD_STEPS_PER_PASS (1 or 2)
     h->btile_x = dtype == XFDTD_F32 ? 32 : 24;
     h->btile_y = dtype == XFDTD_F32 ? pick_blocked2_tile_y(*g) : 8;
     h->bzchunk = blocked2_zchunk(*g, h->btile_x, h->btile_y, dtype);
-    // Two steps per pass by default for FP32 boxes of at least 2^23 cells;
-    // below that the one-step kernel measured as fast or faster (32^3 ..
-    // 128^3: its shorter z-march warm-up and smaller halo win while the
-    // two-step kernel's halved traffic does not matter; 192^2 x 352 and up:
-    // two-step).  xfdtd_tune decides per box.
-    h->spp = dtype == XFDTD_F32 && (double)g->nx * g->ny * g->nz >= (double)(1 << 23) ? 2 : 1;
+    // Two steps per pass by default for FP32 boxes of at least 2^23 cells and
+    // 32 planes; below that the one-step kernel measured as fast or faster
+    // (32^3 .. 128^3: its shorter z-march warm-up and smaller halo win while
+    // the two-step kernel's halved traffic does not matter; 192^2 x 352 and
+    // up: two-step; boxes a few planes deep pay the two-step kernel's 10
+    // warm-up planes per chunk: 4096^2 x 1, 9.1 Gcell-updates/s against 73
+    // for the plane kernel).  xfdtd_tune decides per box.
+    h->spp = dtype == XFDTD_F32 && (double)g->nx * g->ny * g->nz >= (double)(1 << 23) && g->nz >= 32 ? 2 : 1;
     const char *spp = getenv("XFDTD_STEPS_PER_PASS");
     if (spp && (atoi(spp) == 1 || atoi(spp) == 2)) h->spp = atoi(spp);
     const char *bty = getenv("XFDTD_BLK_TILE_Y");

@@ -518,6 +518,108 @@ __global__ __launch_bounds__(C::THREADS) void fused_step_kernel(Fields<T> in, Fi
     fused_tile<T, C>(in, out, d, w, zchunk, ntx, nty, xcd_order(blockIdx.x, gridDim.x), sm);
 }
 
+// ---------------------------------------------------------------------------
+// plane step: boxes one plane deep (nz = 1, the 2D variant of Sec. 2, k_z = 0)
+// ---------------------------------------------------------------------------
+// A box one plane deep is periodic in z with period one: every z-neighbour of
+// a value is the value itself.  The z-march runs four plane iterations (three
+// of warm-up) per output plane there; this kernel loads the plane once and
+// forms g, B^{n+1/2} and E^{n+1} with the z-march's per-position functions,
+// passing each position's own values as its z-neighbours (E(k+1) = E(k),
+// g(k-1) = g(k+1) = g(k), B^{n+1/2}(k-2) = B^{n+1/2}(k-1)), so that its
+// results are bitwise those of the z-march.  A TX x TY tile spans the
+// positions [-2, TX+2) x [-2, TY+2) in row order, R per thread.
+template <int TX_, int TY_, int THREADS_>
+struct PlaneCfg {
+    static constexpr int TX = TX_, TY = TY_, THREADS = THREADS_;
+    static constexpr int PX = TX_ + 4, PY = TY_ + 4, P = PX * PY;
+    static constexpr int R = (P + THREADS_ - 1) / THREADS_;
+};
+
+template <typename T, int P>
+struct PlaneSmem {
+    T EB[3][P];  // E^n, then B^{n+1/2}
+    T G[6][P];   // g of E^n
+};
+
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void plane_step_kernel(Fields<T> in, Fields<T> out, Dims d, Weights<T> w,
+                                                                int ntx)
+{
+    constexpr int R = C::R, TX = C::TX, TY = C::TY, PX = C::PX, P = C::P;
+    __shared__ PlaneSmem<T, P> sm;
+    const int logical = xcd_order(blockIdx.x, gridDim.x);
+    const int x0 = (logical % ntx) * TX, y0 = (logical / ntx) * TY;
+    const int TXe = min(TX, d.nx - x0), TYe = min(TY, d.ny - y0);
+    gptr<const T> src[6];
+    gptr<T> dst[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        src[c] = (gptr<const T>)in.c[c];
+        dst[c] = (gptr<T>)out.c[c];
+    }
+    T e[R][3], bo[R][3], g[R][6], bn[R][3];
+    int li[R];
+    uint32_t col[R];
+    bool isG[R], isB[R], isO[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int sl = (int)threadIdx.x + r * C::THREADS;
+        const int rx = sl % PX - 2, ry = sl / PX - 2;
+        const bool valid = sl < P && rx < TXe + 2 && ry < TYe + 2;
+        isG[r] = valid && rx < TXe + 1 && ry < TYe + 1;                  // forms g
+        isB[r] = valid && rx >= -1 && rx < TXe && ry >= -1 && ry < TYe;  // B^{n+1/2}
+        isO[r] = valid && rx >= 0 && rx < TXe && ry >= 0 && ry < TYe;    // outputs
+        li[r] = valid ? sl : 0;
+        // idle positions load column 0 (in bounds, value unused)
+        col[r] = valid ? (uint32_t)(wrap(y0 + ry, d.ny) * d.nx + wrap(x0 + rx, d.nx)) : 0u;
+        const uint32_t colb = isB[r] ? col[r] : 0u;  // B^{n-1/2} only where B^{n+1/2} is formed
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            e[r][c] = ld_plane(src[c], col[r]);
+            bo[r][c] = ld_plane(src[3 + c], colb);
+        }
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sm.EB[c][sl] = e[r][c];
+        }
+    }
+    __syncthreads();
+    // g of E^n (positions outside the g region read the neighbours of slot 0)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        form_g<PX>(g[r], e[r], e[r], sm.EB[0], sm.EB[1], sm.EB[2], isG[r] ? li[r] : 0);
+        if (isG[r]) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) sm.G[m][li[r]] = g[r][m];
+        }
+    }
+    __syncthreads();  // E^n is no longer read from LDS
+    // B^{n+1/2}: stars of g with g itself as both z-neighbours
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        bn[r][0] = bn[r][1] = bn[r][2] = T(0);
+        if (isB[r]) {
+            faraday_stars<PX, P>(bn[r], bo[r], g[r], g[r], g[r], sm.G, li[r], w);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sm.EB[c][li[r]] = bn[r][c];
+        }
+    }
+    __syncthreads();
+    // E^{n+1} from B^{n+1/2} (own value also as its z-neighbour); both stored
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!isO[r]) continue;
+        const T b2[2] = {bn[r][0], bn[r][1]};
+        T en[3];
+        ampere3<PX, P>(en, e[r], bn[r], b2, sm.EB, li[r], w);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st_plane(dst[c], col[r], en[c]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st_plane(dst[3 + c], col[r], bn[r][c]);
+    }
+}
+
 // Batched step: every box of a batch advances one step.  Work item i is tile
 // items[i].y of box items[i].x (box -1: no work); workgroup w takes items w,
 // w + gridDim.x, ...  The host orders the list for the XCD each slot lands
@@ -953,10 +1055,28 @@ hipError_t launch_ampere(const Fields<T> &f, Dims d, const Weights<T> &w, hipStr
     return hipGetLastError();
 }
 
+// Plane-kernel tilings: 64x16 outputs in FP32 (1360 positions, 49 KB of
+// LDS), 64x8 in FP64 (816 positions, 59 KB), 256 threads.
+template <typename T>
+using PlaneTile = std::conditional_t<sizeof(T) == 4, PlaneCfg<64, 16, 256>, PlaneCfg<64, 8, 256>>;
+
+template <typename T>
+hipError_t launch_plane(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, hipStream_t s)
+{
+    using C = PlaneTile<T>;
+    const int ntx = (d.nx + C::TX - 1) / C::TX, nty = (d.ny + C::TY - 1) / C::TY;
+    const int64_t nb = (int64_t)ntx * nty;
+    if (d.nz != 1 || nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((plane_step_kernel<T, C>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, in, out, d, w, ntx);
+    return hipGetLastError();
+}
+
+// Boxes one plane deep run the plane kernel whatever the tiling asked for.
 template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
                         int tile_y, int zchunk, hipStream_t s)
 {
+    if (d.nz == 1) return launch_plane<T>(in, out, d, w, s);
     if (tile_x != 64 && tile_x != 32) return hipErrorInvalidValue;
     const int ntx = (d.nx + tile_x - 1) / tile_x;
     const int nty = (d.ny + tile_y - 1) / tile_y;

@@ -114,6 +114,42 @@ def test_fp32_against_fp64_oracle(shape, scratch):
     assert rel_l2(to_host(t), exp) < 2e-6
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_plane_kernel_equals_z_march_and_oracle(dtype):
+    """A box one plane deep (nz = 1) runs the plane kernel: several tiles with
+    ragged tails in x and y, bitwise equal to the z-marching kernels (the
+    two-step kernel and a one-box batch, which march the periodic plane) and
+    to the oracle within its bar."""
+    shape = (1, 45, 150)
+    c = _coeffs(455)
+    sp = (1.0, 0.8, 1.3)
+    dt = 0.95 * O.cfl_dt(c, sp)
+    f0 = S.uniform_fields(shape, 456)
+    n = 7
+    a = to_dev(f0, dtype)
+    sa = pkg.Solver(a, dt, c, spacing=sp)
+    assert sa.launch_config()["steps_per_pass"] == 1
+    sa.run(n)
+    b = to_dev(f0, dtype)
+    sb = pkg.Solver(b, dt, c, spacing=sp)
+    sb.set_steps_per_pass(2)
+    sb.run(n - 1)
+    assert sb.stats()["two_step_launches"] > 0
+    sb.set_steps_per_pass(1)
+    sb.run(1)
+    bt_f = to_dev(f0, dtype)
+    bt = pkg.Batch([(bt_f, dt, c, sp)], tune=False)
+    bt.run(n)
+    torch.cuda.synchronize()
+    for x, y, z in zip(a, b, bt_f):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    if dtype == torch.float64:
+        assert rel_l2(to_host(a), oracle.c_run(f0, n, c, dt, sp)) < 1e-13
+    else:
+        ce, spe = _fp32.effective(c, dt, sp)
+        assert rel_l2(to_host(a), oracle.c_run(_fp32.round_fields(f0), n, ce, dt, spe)) < 2e-6
+
+
 @pytest.mark.parametrize("kind", ["yee", "extended"])
 def test_config1_plane_wave(kind):
     """32^3 FP64, 100 steps: equal to the oracle and to the exact eigenmode."""
