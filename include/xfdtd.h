@@ -508,6 +508,10 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     default: tile_x 32 only when every box has nx <= 32, tile_y 8, the
  *     z-split minimising max(total plane iterations / resident workgroups,
  *     longest work item), grid 0, one step per launch.
+ * A batch whose boxes are all one plane deep (nz = 1) steps on plane
+ *     kernels (64 x 16 tiles in FP32, 64 x 8 in FP64, one step per launch)
+ *     whatever the tiling and steps per pass set; get_config and
+ *     get_steps_per_pass report those, and the tuner times only the grid.
  * xfdtd_batch_run: n >= 0 steps of every box through the cached graph (the
  *     graph is re-captured when n or the configuration changes); the result
  *     is in the bound fields when the queued work completes.

@@ -70,6 +70,9 @@ struct xfdtd_batch_s {
     hipStream_t aux = nullptr;  // recompute stream of the gradient's backward pass
     Config cfg;
     bool cfg_set = false;
+    // every box one plane deep: the forward steps run the plane kernel on its
+    // own tiles, one step per launch, whatever cfg asks for
+    bool plane = false;
     void *d_boxes = nullptr;
     int2 *d_items = nullptr;
     int nitems = 0;
@@ -108,6 +111,12 @@ int cus()
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
     return n > 0 ? n : 256;
 }
+
+// The forward kernels' tile and steps per launch: the plane kernel's for a
+// batch of boxes one plane deep, else the configured ones.
+int fwd_tx(const xfdtd_batch_s *b) { return b->plane ? plane_tile_x() : b->cfg.tile_x; }
+int fwd_ty(const xfdtd_batch_s *b) { return b->plane ? plane_tile_y(b->dtype) : b->cfg.tile_y; }
+int fwd_spp(const xfdtd_batch_s *b) { return b->plane ? 1 : b->cfg.spp; }
 
 // z-chunk length of a box under a z-split (at least 4 planes, or the depth)
 int64_t box_zchunk(const xfdtd_grid &g, int zsplit)
@@ -274,7 +283,7 @@ std::pair<double, int> simulate_finish(const std::vector<int> &order, const std:
 bool forward_list(const xfdtd_batch_s *b, const std::vector<int> &zc, int warm, std::vector<int2> &all,
                   std::vector<double> &cost, std::vector<int> &order)
 {
-    const int tx = b->cfg.tile_x, ty = b->cfg.tile_y;
+    const int tx = fwd_tx(b), ty = fwd_ty(b);
     all.clear();
     cost.clear();
     std::vector<int> run;
@@ -344,11 +353,14 @@ std::vector<int> model_chunks(const xfdtd_batch_s *b, int warm, int per_xcd)
 template <typename T>
 int build_t(xfdtd_batch_t b)
 {
-    const int ty = b->cfg.tile_y;
-    // warm-up planes of a z-chunk: 3 for the one-step march, 10 for two steps
-    const int warm = b->cfg.spp == 2 ? 10 : 3;
+    const int tx = fwd_tx(b), ty = fwd_ty(b);
+    // warm-up planes of a z-chunk: 3 for the one-step march, 10 for two steps,
+    // none for the plane kernel
+    const int warm = b->plane ? 0 : b->cfg.spp == 2 ? 10 : 3;
     std::vector<int> zc(b->g.size());
-    if (b->cfg.zsplit == 0) {
+    if (b->plane) {
+        for (size_t i = 0; i < b->g.size(); ++i) zc[i] = 1;
+    } else if (b->cfg.zsplit == 0) {
         const int occ = b->cfg.spp == 2 ? blocked2_occupancy<T>(b->cfg.tile_x, ty)
                                         : fused_occupancy<T>(b->cfg.tile_x, ty);
         zc = model_chunks(b, warm, std::max(1, cus() / 8) * std::max(1, occ));
@@ -368,7 +380,7 @@ int build_t(xfdtd_batch_t b)
         const double sp[3] = {g.dx, g.dy, g.dz};
         d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
         d.zchunk = zc[(size_t)i];
-        d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
+        d.ntx = (int)((g.nx + tx - 1) / tx);
         d.nty = (int)((g.ny + ty - 1) / ty);
         d.pad = 0;
     }
@@ -379,7 +391,7 @@ int build_t(xfdtd_batch_t b)
     std::vector<int2> items;
     for (int j : order) items.push_back(j < 0 ? make_int2(-1, -1) : all[j]);
     xlog("batch of %lld boxes: %s %dx%d tiles, z-split %d, %zu items in %zu slots, grid %d",
-         (long long)b->m, b->cfg.spp == 2 ? "two-step" : "one-step", b->cfg.tile_x, ty, b->cfg.zsplit, all.size(),
+         (long long)b->m, b->plane ? "plane" : b->cfg.spp == 2 ? "two-step" : "one-step", tx, ty, b->cfg.zsplit, all.size(),
          order.size(), b->cfg.grid);
     if (items.size() > 0x7fffffff) return set_error(XFDTD_EINVAL, "too many work items");
     if (b->d_boxes) hipFree(b->d_boxes);
@@ -414,7 +426,11 @@ int launch_step(xfdtd_batch_t b, int parity, hipStream_t s, const void *descs = 
 {
     const void *dd = descs ? descs : b->d_boxes;
     hipError_t e;
-    if (b->dtype == XFDTD_F32)
+    if (b->plane && b->dtype == XFDTD_F32)
+        e = launch_batched_plane<float>((const BoxDesc<float> *)dd, b->d_items, b->nitems, parity, grid_of(b), s);
+    else if (b->plane)
+        e = launch_batched_plane<double>((const BoxDesc<double> *)dd, b->d_items, b->nitems, parity, grid_of(b), s);
+    else if (b->dtype == XFDTD_F32)
         e = launch_batched<float>((const BoxDesc<float> *)dd, b->d_items, b->nitems, parity, b->cfg.tile_x,
                                   b->cfg.tile_y, grid_of(b), s);
     else
@@ -478,7 +494,7 @@ int launch_steps(xfdtd_batch_t b, int64_t n, hipStream_t s)
         rc = b->dtype == XFDTD_F32 ? unfused_all<float>(b, s) : unfused_all<double>(b, s);
         --left;
     }
-    if (b->cfg.spp == 2) {
+    if (fwd_spp(b) == 2) {
         int64_t pairs = left / 2;
         if (pairs & 1) {
             for (int p = 0; p < 2 && !rc; ++p) rc = launch_step(b, p, s);
@@ -562,6 +578,9 @@ int xfdtd_batch_create(const xfdtd_grid *grids, const double *dts, const double 
         b->cfg.tile_x = prefer_narrow(b) ? 32 : 64;
         b->cfg.tile_y = 8;
         b->cfg.zsplit = model_zsplit(b, b->cfg.tile_x, b->cfg.tile_y);
+        b->plane = true;
+        for (const xfdtd_grid &g : b->g)
+            if (g.nz != 1) b->plane = false;
         b->key = shape_key(b);
         *out = hold.release();
         return XFDTD_OK;
@@ -654,7 +673,7 @@ int xfdtd_batch_set_steps_per_pass(xfdtd_batch_t b, int steps)
 int xfdtd_batch_get_steps_per_pass(xfdtd_batch_t b, int *steps)
 {
     if (!b || !steps) return set_error(XFDTD_EINVAL, "null argument");
-    *steps = b->cfg.spp;
+    *steps = fwd_spp(b);
     return XFDTD_OK;
 }
 
@@ -672,8 +691,8 @@ int xfdtd_batch_get_adjoint_config(xfdtd_batch_t b, int *tile_x, int *tile_y, in
 int xfdtd_batch_get_config(xfdtd_batch_t b, int *tile_x, int *tile_y, int *zsplit, int *grid, int *nitems)
 {
     if (!b) return set_error(XFDTD_EINVAL, "null handle");
-    if (tile_x) *tile_x = b->cfg.tile_x;
-    if (tile_y) *tile_y = b->cfg.tile_y;
+    if (tile_x) *tile_x = fwd_tx(b);
+    if (tile_y) *tile_y = fwd_ty(b);
     if (zsplit) *zsplit = b->cfg.zsplit;
     if (grid) *grid = b->bound ? grid_of(b) : b->cfg.grid;
     if (nitems) *nitems = b->nitems;
@@ -716,7 +735,17 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         bool narrow = false;  // 32-column candidates where some box leaves 64-wide tiles part idle
         for (const xfdtd_grid &g : b->g)
             if (g.nx % 64 != 0 && g.nx % 64 <= 32) narrow = true;
+        // a batch of boxes one plane deep runs the plane kernel whatever the
+        // tiling: only its grid is a choice
+        if (b->plane)
+            for (int gm : {0, 1, 2}) {
+                Config c = b->cfg;
+                c.spp = 1;
+                c.grid = gm == 0 ? 0 : gm * ncu;
+                cands.push_back(c);
+            }
         for (int tx : {64, 32}) {
+            if (b->plane) break;
             if (tx == 32 && !narrow) continue;
             for (int ty : tys) {
                 if (b->dtype == XFDTD_F64 && ty == 16) continue;
@@ -737,7 +766,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
         // FP32: the two-step kernel on 32-column tiles, whole-depth or split
         // z-marches (its chunks start with 10 warm-up planes), or per-box
         // chunks from the schedule model (z-split 0)
-        if (b->dtype == XFDTD_F32)
+        if (b->dtype == XFDTD_F32 && !b->plane)
             for (int ty : {8, 16})
                 for (int zs : {1, 2, 0})
                     for (int gm : {0, 1}) {
@@ -812,7 +841,7 @@ int xfdtd_batch_tune(xfdtd_batch_t b, int force, double *best_ms)
             const void *dd = temp.state ? temp.descs : nullptr;
             for (int i = 0; i < r && !q; ++i) {
                 const int par = temp.state ? (i & 1) : 0;
-                q = b->cfg.spp == 2 ? launch_pair(b, par, b->stream, dd) : launch_step(b, par, b->stream, dd);
+                q = fwd_spp(b) == 2 ? launch_pair(b, par, b->stream, dd) : launch_step(b, par, b->stream, dd);
             }
             if (!q && hipEventRecord(e1, b->stream) != hipSuccess) q = set_error(XFDTD_EHIP, "event record");
             if (!q && hipEventSynchronize(e1) != hipSuccess) q = set_error(XFDTD_EHIP, "event synchronize");
@@ -977,9 +1006,11 @@ BoxDesc<T> fwd_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &in, cons
     d.d = Dims{(int)g.nx, (int)g.ny, (int)g.nz};
     const double sp[3] = {g.dx, g.dy, g.dz};
     d.w = fold_weights<T>(b->dt[i], &b->coeffs[12 * i], sp, nullptr);
-    d.zchunk = b->fzc.size() == b->g.size() ? b->fzc[(size_t)i] : (int)box_zchunk(g, std::max(1, b->cfg.zsplit));
-    d.ntx = (int)((g.nx + b->cfg.tile_x - 1) / b->cfg.tile_x);
-    d.nty = (int)((g.ny + b->cfg.tile_y - 1) / b->cfg.tile_y);
+    d.zchunk = b->plane ? 1
+                        : b->fzc.size() == b->g.size() ? b->fzc[(size_t)i]
+                                                       : (int)box_zchunk(g, std::max(1, b->cfg.zsplit));
+    d.ntx = (int)((g.nx + fwd_tx(b) - 1) / fwd_tx(b));
+    d.nty = (int)((g.ny + fwd_ty(b) - 1) / fwd_ty(b));
     d.pad = 0;
     return d;
 }
@@ -1229,8 +1260,10 @@ int bgrad_forward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws)
     int rc = upload(descs, &d_descs);
     if (rc) return rc;
     for (int64_t s = 0; s < n && !rc; ++s) {
-        hipError_t e = launch_batched<T>(d_descs + off[(size_t)s], b->d_items, b->nitems, 0, b->cfg.tile_x,
-                                         b->cfg.tile_y, grid_of(b), b->stream);
+        hipError_t e = b->plane ? launch_batched_plane<T>(d_descs + off[(size_t)s], b->d_items, b->nitems, 0,
+                                                          grid_of(b), b->stream)
+                                : launch_batched<T>(d_descs + off[(size_t)s], b->d_items, b->nitems, 0,
+                                                    b->cfg.tile_x, b->cfg.tile_y, grid_of(b), b->stream);
         if (e != hipSuccess) rc = set_error(XFDTD_EHIP, "batched launch: %s", hipGetErrorString(e));
     }
     hipStreamSynchronize(b->stream);
@@ -1364,8 +1397,10 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
     BTRY(hipStreamWaitEvent(aux, evs.ev[0], 0), "hipStreamWaitEvent");
     auto recompute = [&](int64_t k) -> int {
         for (int64_t l = rl[k]; l < rl[k + 1]; ++l) {
-            hipError_t e = launch_batched<T>(d_r + roff[(size_t)l], b->d_items, b->nitems, 0, b->cfg.tile_x,
-                                             b->cfg.tile_y, grid_of(b), aux);
+            hipError_t e = b->plane ? launch_batched_plane<T>(d_r + roff[(size_t)l], b->d_items, b->nitems, 0,
+                                                              grid_of(b), aux)
+                                    : launch_batched<T>(d_r + roff[(size_t)l], b->d_items, b->nitems, 0,
+                                                        b->cfg.tile_x, b->cfg.tile_y, grid_of(b), aux);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
         }
         BTRY(hipEventRecord(ev_rec(k), aux), "hipEventRecord");

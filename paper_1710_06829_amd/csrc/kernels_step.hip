@@ -542,13 +542,12 @@ struct PlaneSmem {
     T G[6][P];   // g of E^n
 };
 
+// Tile `logical` (x fastest) of a plane box with ntx tiles per row.
 template <typename T, typename C>
-__global__ __launch_bounds__(C::THREADS) void plane_step_kernel(Fields<T> in, Fields<T> out, Dims d, Weights<T> w,
-                                                                int ntx)
+__device__ __forceinline__ void plane_tile(const Fields<T> &in, const Fields<T> &out, const Dims &d,
+                                           const Weights<T> &w, int ntx, int logical, PlaneSmem<T, C::P> &sm)
 {
     constexpr int R = C::R, TX = C::TX, TY = C::TY, PX = C::PX, P = C::P;
-    __shared__ PlaneSmem<T, P> sm;
-    const int logical = xcd_order(blockIdx.x, gridDim.x);
     const int x0 = (logical % ntx) * TX, y0 = (logical / ntx) * TY;
     const int TXe = min(TX, d.nx - x0), TYe = min(TY, d.ny - y0);
     gptr<const T> src[6];
@@ -617,6 +616,32 @@ __global__ __launch_bounds__(C::THREADS) void plane_step_kernel(Fields<T> in, Fi
         for (int c = 0; c < 3; ++c) st_plane(dst[c], col[r], en[c]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) st_plane(dst[3 + c], col[r], bn[r][c]);
+    }
+}
+
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void plane_step_kernel(Fields<T> in, Fields<T> out, Dims d, Weights<T> w,
+                                                                int ntx)
+{
+    __shared__ PlaneSmem<T, C::P> sm;
+    plane_tile<T, C>(in, out, d, w, ntx, xcd_order(blockIdx.x, gridDim.x), sm);
+}
+
+// Batched plane step (every box of the batch one plane deep): work item i is
+// plane tile items[i].y of box items[i].x (box -1: no work), as in
+// batched_step_kernel; parity 0: f -> s, 1: s -> f.
+template <typename T, typename C>
+__global__ __launch_bounds__(C::THREADS) void batched_plane_kernel(const BoxDesc<T> *__restrict__ boxes,
+                                                                   const int2 *__restrict__ items, int nitems,
+                                                                   int parity)
+{
+    __shared__ PlaneSmem<T, C::P> sm;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        if (it.x < 0) continue;
+        const BoxDesc<T> &b = boxes[it.x];
+        plane_tile<T, C>(parity ? b.s : b.f, parity ? b.f : b.s, b.d, b.w, b.ntx, it.y, sm);
+        __syncthreads();  // LDS is reused by the next item
     }
 }
 
@@ -1074,6 +1099,21 @@ hipError_t launch_plane(const Fields<T> &in, const Fields<T> &out, Dims d, const
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_batched_plane(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int grid,
+                                hipStream_t s)
+{
+    using C = PlaneTile<T>;
+    if (nitems <= 0) return hipSuccess;
+    if (grid <= 0 || grid > nitems) grid = nitems;
+    hipLaunchKernelGGL((batched_plane_kernel<T, C>), dim3(grid), dim3(C::THREADS), 0, s, boxes, items, nitems,
+                       parity);
+    return hipGetLastError();
+}
+
+int plane_tile_x() { return 64; }
+int plane_tile_y(int dtype) { return dtype == XFDTD_F32 ? PlaneTile<float>::TY : PlaneTile<double>::TY; }
+
 // Boxes one plane deep run the plane kernel whatever the tiling asked for.
 template <typename T>
 hipError_t launch_fused(const Fields<T> &in, const Fields<T> &out, Dims d, const Weights<T> &w, int tile_x,
@@ -1190,6 +1230,8 @@ template hipError_t launch_batched<float>(const BoxDesc<float> *, const int2 *, 
                                           hipStream_t);
 template hipError_t launch_batched<double>(const BoxDesc<double> *, const int2 *, int, int, int, int, int,
                                            hipStream_t);
+template hipError_t launch_batched_plane<float>(const BoxDesc<float> *, const int2 *, int, int, int, hipStream_t);
+template hipError_t launch_batched_plane<double>(const BoxDesc<double> *, const int2 *, int, int, int, hipStream_t);
 template hipError_t launch_faraday<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t);
 template hipError_t launch_faraday<double>(const Fields<double> &, Dims, const Weights<double> &, hipStream_t);
 template hipError_t launch_ampere<float>(const Fields<float> &, Dims, const Weights<float> &, hipStream_t,

@@ -105,6 +105,14 @@ template <typename T>
 hipError_t launch_batched(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int tile_x,
                           int tile_y, int grid, hipStream_t s);
 
+// Batched plane step (every box one plane deep): the boxes' ntx / nty count
+// plane tiles (plane_tile_x() x plane_tile_y(dtype) cells).
+template <typename T>
+hipError_t launch_batched_plane(const BoxDesc<T> *boxes, const int2 *items, int nitems, int parity, int grid,
+                                hipStream_t s);
+int plane_tile_x();
+int plane_tile_y(int dtype);
+
 // Batched two-step launch (FP32): every box advances two steps; the boxes'
 // tilings must be 32 x tile_y (tile_y 8 or 16).  hipErrorInvalidValue for
 // other tilings or dtypes.

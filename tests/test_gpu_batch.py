@@ -146,3 +146,36 @@ def test_batch_with_largest_plane_box_equals_single_runs_fp32():
     torch.cuda.synchronize()
     for (f, _, _), t in zip(boxes, single):
         assert all(torch.equal(a, b) for a, b in zip(f, t))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("tune", [False, True])
+def test_batch_of_plane_boxes_equals_single_runs(dtype, tune):
+    """Every box one plane deep (the 2D variant): the batch runs the plane
+    kernel (tiles of 64 columns, no z-march), bitwise equal to single-box
+    runs of the same boxes, and in FP64 equal to the oracle; 7 steps (an odd
+    count: one in-place step) and 12."""
+    shapes = [(1, 45, 150), (1, 17, 64), (1, 1, 5), (1, 33, 33)]
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.extended_beta_delta(1850 + b)
+        c = O.coeffs_from(beta, delta)
+        sp = (1.0, 0.9 + 0.1 * b, 1.0)
+        boxes.append((shape, S.uniform_fields(shape, 1860 + b), c, 0.95 * O.cfl_dt(c, sp), sp))
+    t = [to_dev(f, dtype) for (_, f, _, _, _) in boxes]
+    bt = pkg.Batch([(t[i], dt, c, sp) for i, (_, _, c, dt, sp) in enumerate(boxes)], tune=tune)
+    cfg = bt.config()
+    assert cfg["tile_x"] == 64 and cfg["steps_per_pass"] == 1, cfg
+    for n in (7, 12):
+        bt.run(n)
+        torch.cuda.synchronize()
+    for i, (shape, f0, c, dt, sp) in enumerate(boxes):
+        ref = to_dev(f0, dtype)
+        s = pkg.Solver(ref, dt, c, spacing=sp)
+        s.run(7)
+        s.run(12)
+        torch.cuda.synchronize()
+        for a, b in zip(t[i], ref):
+            assert torch.equal(a, b), (i, shape)
+        if dtype == torch.float64:
+            assert rel_l2(to_host(t[i]), oracle.c_run(f0, 19, c, dt, sp)) < 1e-13, (i, shape)

@@ -253,3 +253,47 @@ def test_batch_grad_backward_consumes_the_forward():
     for b in range(2):
         for a in range(6):
             assert torch.equal(l1[b][a], l2[b][a]), (b, a)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_grad_of_plane_boxes(dtype):
+    """A batch of boxes one plane deep (forward and recompute on the plane
+    kernel): FP64 against the oracle's adjoint; FP32 bitwise (states, adjoint
+    fields) against single-box gradient runs, coefficient gradients up to the
+    order of the FP64 sums."""
+    shapes = [(1, 45, 150), (1, 17, 64), (1, 1, 5)]
+    n, seg = 9, 3
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.distinct_beta_delta(1870 + b)
+        c = O.coeffs_from(beta, delta)
+        sp = (1.0, 1.0 + 0.1 * b, 1.0)
+        boxes.append((shape, S.uniform_fields(shape, 1880 + b), c, 0.95 * O.cfl_dt(c, sp), sp,
+                      S.uniform_fields(shape, 1890 + b)))
+    t = [to_dev(f, dtype) for (_, f, _, _, _, _) in boxes]
+    bt = pkg.Batch([(t[i], dt, c, sp) for i, (_, _, c, dt, sp, _) in enumerate(boxes)], tune=False)
+    assert bt.config()["tile_x"] == 64
+    ws = bt.grad_workspaces(n, seg)
+    bt.grad_forward(n, ws, seg)
+    lams = [to_dev(lamN, dtype) for (*_, lamN) in boxes]
+    g = bt.grad_backward(n, ws, lams, seg)
+    torch.cuda.synchronize()
+    for i, (shape, f0, c, dt, sp, lamN) in enumerate(boxes):
+        if dtype == torch.float64:
+            fN, g0, gc = O.run_with_adjoint(f0, n, c, dt, sp, lambda f, l=lamN: l)
+            assert rel_l2(to_host(t[i]), fN) < 1e-13, (i, shape)
+            assert rel_l2(to_host(lams[i]), g0) < 1e-12, (i, shape)
+            assert np.abs(np.asarray(g[i]) - gc).max() <= 1e-11 * np.abs(gc).max(), (i, shape)
+        else:
+            ts = to_dev(f0, dtype)
+            s = pkg.Solver(ts, dt, c, spacing=sp, scratch=False)
+            w1 = torch.empty(s.grad_workspace_bytes(n, seg), dtype=torch.uint8, device=DEV)
+            s.grad_forward(n, w1, seg)
+            ls = to_dev(lamN, dtype)
+            gs = np.asarray(s.grad_backward(n, w1, ls, seg))
+            torch.cuda.synchronize()
+            for a, b in zip(t[i], ts):
+                assert torch.equal(a, b), (i, shape)
+            for a, b in zip(lams[i], ls):
+                assert torch.equal(a, b), (i, shape)
+            assert np.abs(np.asarray(g[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
