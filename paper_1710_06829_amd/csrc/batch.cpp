@@ -1413,7 +1413,8 @@ int bgrad_backward_t(xfdtd_batch_t b, int64_t n, int64_t seg, void *const *ws, v
         if (k < nck - 2) BTRY(hipStreamWaitEvent(mainS, ev_rec(k), 0), "hipStreamWaitEvent");
         for (int64_t l = al[k]; l < aend(k); ++l) {
             hipError_t e = launch_batched_adjoint<T>(d_a + aoff[(size_t)l], b->d_aitems, b->d_aorder, b->naslots,
-                                                     b->d_apart, first ? 0 : 1, b->atx, adj_tile(b), ga, mainS);
+                                                     b->d_apart, first ? 0 : 1, b->atx, adj_tile(b), ga, mainS,
+                                                     b->plane);
             if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched gradient launch: %s", hipGetErrorString(e));
             first = false;
         }
@@ -1506,7 +1507,7 @@ int tune_adjoint_t(xfdtd_batch_t b)
                 for (int i = 0; i < r; ++i) {
                     const hipError_t e = launch_batched_adjoint<T>(d, b->d_aitems, b->d_aorder, b->naslots,
                                                                    b->d_apart, 0, b->atx, adj_tile(b),
-                                                                   b->naslots, b->stream);
+                                                                   b->naslots, b->stream, b->plane);
                     if (e != hipSuccess) return set_error(XFDTD_EHIP, "batched adjoint launch: %s", hipGetErrorString(e));
                 }
                 BTRY(hipEventRecord(ev.e[1], b->stream), "hipEventRecord");

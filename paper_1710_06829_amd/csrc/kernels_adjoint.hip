@@ -99,14 +99,126 @@ struct AdjSmem {
     double red[12][C::WAVES];
 };
 
-// One tile (number `logical`) of the adjoint step.  slot: this tile's 12
-// gradient sums (written, or added to when accumulate != 0).
+// Shared storage of the one-plane pass: one plane each of lE', mu, the six
+// stars and the primal E (15 planes, half of AdjSmem's double buffers) and the
+// reduction slots, so that two workgroups share a CU.
 template <typename T, typename C>
+struct PlaneAdjStore {
+    T planes[15][AdjSmem<T, C>::P];
+    double red[12][C::WAVES];
+};
+
+// Per-position pieces of the reverse step, shared by the z-march and the
+// one-plane pass (which passes a position's own values as its z-neighbours).
+//
+// mu = lB' + L^T lE' at a position: l1 = lE'(k+1) and l2 = lE'(k+2) of the
+// position, Lx, Ly, Lz the LDS planes of lE'(k+1), lg its index there (slot 0
+// outside the mu region: in bounds, value unused).
+template <int PX, typename T>
+__device__ __forceinline__ void adj_mu(T mu[3], const T bo[3], const T l1[3], const T l2[3], const T *Lx,
+                                       const T *Ly, const T *Lz, int lg, const Weights<T> &w)
+{
+    const T fzy = l2[1] - l1[1], fzx = l2[0] - l1[0];
+    const T fyz = Lz[lg + PX] - l1[2], fyx = Lx[lg + PX] - l1[0];
+    const T fxz = Lz[lg + 1] - l1[2], fxy = Ly[lg + 1] - l1[1];
+    mu[0] = bo[0] + (w.wa[1] * fyz - w.wa[2] * fzy);
+    mu[1] = bo[1] + (w.wa[2] * fzx - w.wa[0] * fxz);
+    mu[2] = bo[2] + (w.wa[0] * fxy - w.wa[1] * fyx);
+}
+
+// The six stars of mu at a position from its centre mc and its neighbour
+// sums along x (px), y (py) and z (pz).
+template <typename T>
+__device__ __forceinline__ void adj_stars(T s[6], const T mc[3], const T px[3], const T py[3], const T pz[3],
+                                          const Weights<T> &w)
+{
+    s[0] = w.wc[2] * mc[0] + w.wd[2] * pz[0] + w.wb[2][0] * px[0] + w.wb[2][1] * py[0];  // S_z mu_x
+    s[1] = w.wc[1] * mc[0] + w.wd[1] * py[0] + w.wb[1][0] * px[0] + w.wb[1][1] * pz[0];  // S_y mu_x
+    s[2] = w.wc[0] * mc[1] + w.wd[0] * px[1] + w.wb[0][0] * py[1] + w.wb[0][1] * pz[1];  // S_x mu_y
+    s[3] = w.wc[2] * mc[1] + w.wd[2] * pz[1] + w.wb[2][0] * px[1] + w.wb[2][1] * py[1];  // S_z mu_y
+    s[4] = w.wc[1] * mc[2] + w.wd[1] * py[2] + w.wb[1][0] * px[2] + w.wb[1][1] * pz[2];  // S_y mu_z
+    s[5] = w.wc[0] * mc[2] + w.wd[0] * px[2] + w.wb[0][0] * py[2] + w.wb[0][1] * pz[2];  // S_x mu_z
+}
+
+// The coefficient-gradient sums of an output position at plane k: forward
+// differences of the primal E(k) (n0; n1 = E(k+1); x+1 / y+1 neighbours from
+// the LDS planes Ex, Ey, Ez at index li) against mu and its neighbour sums.
+template <int PX, typename T>
+__device__ __forceinline__ void adj_grad(double acc[12], const T n0[3], const T n1[3], const T *Ex, const T *Ey,
+                                         const T *Ez, int li, const T mc[3], const T px[3], const T py[3],
+                                         const T pz[3])
+{
+    const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
+    const T gxEz = Ez[li + 1] - n0[2], gxEy = Ey[li + 1] - n0[1];
+    const T gyEz = Ez[li + PX] - n0[2], gyEx = Ex[li + PX] - n0[0];
+    // axis x (slots 0..3): +g_x[Ez] with mu_y, -g_x[Ey] with mu_z
+    acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
+    acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
+    acc[2] += (double)(gxEz * pz[1] - gxEy * pz[2]);
+    acc[3] += (double)(gxEz * px[1] - gxEy * px[2]);
+    // axis y (slots 4..7): -g_y[Ez] with mu_x, +g_y[Ex] with mu_z
+    acc[4] += (double)(gyEx * mc[2] - gyEz * mc[0]);
+    acc[5] += (double)(gyEx * px[2] - gyEz * px[0]);
+    acc[6] += (double)(gyEx * pz[2] - gyEz * pz[0]);
+    acc[7] += (double)(gyEx * py[2] - gyEz * py[0]);
+    // axis z (slots 8..11): +g_z[Ey] with mu_x, -g_z[Ex] with mu_y
+    acc[8] += (double)(gzEy * mc[0] - gzEx * mc[1]);
+    acc[9] += (double)(gzEy * px[0] - gzEx * px[1]);
+    acc[10] += (double)(gzEy * py[0] - gzEx * py[1]);
+    acc[11] += (double)(gzEy * pz[0] - gzEx * pz[1]);
+}
+
+// lE = lE' + backward differences of the stars at an output position of plane
+// k-1: la = lE'(k-1); stars 3 and 0 at k-1 (s3a, s0a) and k-2 (s3b, s0b)
+// from registers, stars 1, 2, 4, 5 of plane k-1 from the LDS planes Sp.
+template <int PX, int P, typename T>
+__device__ __forceinline__ void adj_out(T le[3], const T la[3], T s3a, T s3b, T s0a, T s0b, const T (*Sp)[P], int li)
+{
+    le[0] = la[0] + ((s3a - s3b) - (Sp[4][li] - Sp[4][li - PX]));
+    le[1] = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (s0a - s0b));
+    le[2] = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
+}
+
+// The workgroup's 12 gradient sums (FP64, fixed order) into slot: written,
+// or added to when accumulate != 0.
+template <typename C>
+__device__ __forceinline__ void adj_reduce(double acc[12], double (&red)[12][C::WAVES], double *__restrict__ slot,
+                                           int accumulate, int wave, int lane)
+{
+    // delta_a: the centre term (that of alpha_a) plus the along-axis
+    // neighbours, which are all the delta slots accumulate per plane
+    acc[3] += acc[0];
+    acc[7] += acc[4];
+    acc[11] += acc[8];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        double v = acc[j];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[j][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double v = 0.0;
+        for (int wv = 0; wv < C::WAVES; ++wv) v += red[threadIdx.x][wv];
+        slot[threadIdx.x] = accumulate ? slot[threadIdx.x] + v : v;
+    }
+}
+
+// One tile (number `logical`) of the adjoint step.  slot: this tile's 12
+// gradient sums (written, or added to when accumulate != 0).  PLANE: the box
+// is one plane deep (nz = 1, periodic in z with period one), and one pass
+// with every z-neighbour the position's own value replaces the z-march's five
+// iterations (three of warm-up and one past the plane): the same values, the
+// same per-position functions, bitwise the z-march's adjoint fields; its
+// gradient products are added to the lane's plane_acc, which the caller
+// reduces (for several tiles at once: a tile of one plane is too little work
+// to carry a workgroup reduction of its own).
+template <typename T, typename C, bool PLANE = false>
 __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<T> &lout,
                                              const T *__restrict__ en_x, const T *__restrict__ en_y,
                                              const T *__restrict__ en_z, const Dims &d, const Weights<T> &w,
                                              int zchunk, int ntx, int nty, int logical, AdjSmem<T, C> &sm,
-                                             double *__restrict__ slot, int accumulate)
+                                             double *__restrict__ slot, int accumulate, double *plane_acc = nullptr)
 {
     constexpr int TX = C::TX, TY = C::TY;
     constexpr int PX = AdjSmem<T, C>::PX;
@@ -160,6 +272,62 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     for (int c = 0; c < 6; ++c) {
         src[c] = (gptr_a<const T>)lin.c[c];
         dst[c] = (gptr_a<T>)lout.c[c];
+    }
+
+    if constexpr (PLANE) {
+        // sm is the kernel's PlaneAdjStore: planes 0-2 lE', 3-5 mu, 6-11 the
+        // stars, 12-14 the primal E
+        PlaneAdjStore<T, C> &st = reinterpret_cast<PlaneAdjStore<T, C> &>(sm);
+        T(*PL)[P] = st.planes;
+        T(*LEp)[P] = PL, (*Mp)[P] = PL + 3, (*Sq)[P] = PL + 6, (*Ep)[P] = PL + 12;
+        double *acc = plane_acc;
+        T le[3], bo[3], e0[3], mu[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            le[c] = src[c][col];
+            bo[c] = src[3 + c][colb];
+            e0[c] = en[c][coln];
+        }
+        if (isE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                LEp[c][li] = le[c];
+                Ep[c][li] = e0[c];
+            }
+        }
+        __syncthreads();
+        adj_mu<PX>(mu, bo, le, le, LEp[0], LEp[1], LEp[2], isG ? li : 0, w);
+        if (isG) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Mp[c][li] = mu[c];
+        }
+        __syncthreads();
+        T s[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        if (isB) {
+            T px[3], py[3], pz[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T *M = Mp[c];
+                px[c] = M[li + 1] + M[li - 1];
+                py[c] = M[li + PX] + M[li - PX];
+                pz[c] = mu[c] + mu[c];
+            }
+            adj_stars(s, mu, px, py, pz, w);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) Sq[m][li] = s[m];
+            if (isO) adj_grad<PX>(acc, e0, e0, Ep[0], Ep[1], Ep[2], li, mu, px, py, pz);
+        }
+        __syncthreads();
+        if (isO) {
+            T lo[3];
+            adj_out<PX, P>(lo, le, s[3], s[3], s[0], s[0], Sq, li);
+            const uint32_t oc = col;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st_plane_a(dst[c], oc, lo[c]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st_plane_a(dst[3 + c], oc, mu[c]);
+        }
+        return;
     }
 
     // Values a lane keeps along z live in rings of four register slots: the
@@ -253,17 +421,7 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
 
         // mu(k+1) = lB'(k+1) + L^T lE' (lanes outside the mu region read the
         // neighbours of slot 0: in bounds, value unused)
-        {
-            const int lg = isG ? li : 0;
-            const T *Lx = LEbuf[eb][0], *Ly = LEbuf[eb][1], *Lz = LEbuf[eb][2];
-            const T *l1 = LE[p1], *l2 = LE[p2];
-            const T fzy = l2[1] - l1[1], fzx = l2[0] - l1[0];
-            const T fyz = Lz[lg + PX] - l1[2], fyx = Lx[lg + PX] - l1[0];
-            const T fxz = Lz[lg + 1] - l1[2], fxy = Ly[lg + 1] - l1[1];
-            MU[p1][0] = bo[0] + (w.wa[1] * fyz - w.wa[2] * fzy);
-            MU[p1][1] = bo[1] + (w.wa[2] * fzx - w.wa[0] * fxz);
-            MU[p1][2] = bo[2] + (w.wa[0] * fxy - w.wa[1] * fyx);
-        }
+        adj_mu<PX>(MU[p1], bo, LE[p1], LE[p2], LEbuf[eb][0], LEbuf[eb][1], LEbuf[eb][2], isG ? li : 0, w);
         if (isG) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) Mbuf[mb ^ 1][c][li] = MU[p1][c];
@@ -281,36 +439,11 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
                 py[c] = M[li + PX] + M[li - PX];
                 pz[c] = mn[c] + mm[c];
             }
-            s[0] = w.wc[2] * mc[0] + w.wd[2] * pz[0] + w.wb[2][0] * px[0] + w.wb[2][1] * py[0];  // S_z mu_x
-            s[1] = w.wc[1] * mc[0] + w.wd[1] * py[0] + w.wb[1][0] * px[0] + w.wb[1][1] * pz[0];  // S_y mu_x
-            s[2] = w.wc[0] * mc[1] + w.wd[0] * px[1] + w.wb[0][0] * py[1] + w.wb[0][1] * pz[1];  // S_x mu_y
-            s[3] = w.wc[2] * mc[1] + w.wd[2] * pz[1] + w.wb[2][0] * px[1] + w.wb[2][1] * py[1];  // S_z mu_y
-            s[4] = w.wc[1] * mc[2] + w.wd[1] * py[2] + w.wb[1][0] * px[2] + w.wb[1][1] * pz[2];  // S_y mu_z
-            s[5] = w.wc[0] * mc[2] + w.wd[0] * px[2] + w.wb[0][0] * py[2] + w.wb[0][1] * pz[2];  // S_x mu_z
+            adj_stars(s, mc, px, py, pz, w);
 #pragma unroll
             for (int m = 0; m < 6; ++m) Sbuf[sb][m][li] = s[m];
-            if (isO && k >= k0) {
-                // coefficient gradient at plane k: forward differences of E(k)
-                const T *n0 = EN[s0], *n1 = EN[p1];
-                const T gzEy = n1[1] - n0[1], gzEx = n1[0] - n0[0];
-                const T gxEz = Ebuf[eb][2][li + 1] - n0[2], gxEy = Ebuf[eb][1][li + 1] - n0[1];
-                const T gyEz = Ebuf[eb][2][li + PX] - n0[2], gyEx = Ebuf[eb][0][li + PX] - n0[0];
-                // axis x (slots 0..3): +g_x[Ez] with mu_y, -g_x[Ey] with mu_z
-                acc[0] += (double)(gxEz * mc[1] - gxEy * mc[2]);
-                acc[1] += (double)(gxEz * py[1] - gxEy * py[2]);
-                acc[2] += (double)(gxEz * pz[1] - gxEy * pz[2]);
-                acc[3] += (double)(gxEz * px[1] - gxEy * px[2]);
-                // axis y (slots 4..7): -g_y[Ez] with mu_x, +g_y[Ex] with mu_z
-                acc[4] += (double)(gyEx * mc[2] - gyEz * mc[0]);
-                acc[5] += (double)(gyEx * px[2] - gyEz * px[0]);
-                acc[6] += (double)(gyEx * pz[2] - gyEz * pz[0]);
-                acc[7] += (double)(gyEx * py[2] - gyEz * py[0]);
-                // axis z (slots 8..11): +g_z[Ey] with mu_x, -g_z[Ex] with mu_y
-                acc[8] += (double)(gzEy * mc[0] - gzEx * mc[1]);
-                acc[9] += (double)(gzEy * px[0] - gzEx * px[1]);
-                acc[10] += (double)(gzEy * py[0] - gzEx * py[1]);
-                acc[11] += (double)(gzEy * pz[0] - gzEx * pz[1]);
-            }
+            if (isO && k >= k0)  // coefficient gradient at plane k
+                adj_grad<PX>(acc, EN[s0], EN[p1], Ebuf[eb][0], Ebuf[eb][1], Ebuf[eb][2], li, mc, px, py, pz);
         }
         S0[s0] = s[0];
         S3[s0] = s[3];
@@ -320,13 +453,11 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         if (isO && k - 1 >= k0) {
             const T(*Sp)[P] = Sbuf[sb ^ 1];
             const uint64_t po = (uint64_t)(uint32_t)wm * nxy;
-            const T *la = LE[m1];
-            const T lx = la[0] + ((S3[m1] - S3[p2]) - (Sp[4][li] - Sp[4][li - PX]));
-            const T ly = la[1] + ((Sp[5][li] - Sp[5][li - 1]) - (S0[m1] - S0[p2]));
-            const T lz = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
-            st_plane_a(dst[0] + po, oc, lx);
-            st_plane_a(dst[1] + po, oc, ly);
-            st_plane_a(dst[2] + po, oc, lz);
+            T le[3];
+            adj_out<PX, P>(le, LE[m1], S3[m1], S3[p2], S0[m1], S0[p2], Sp, li);
+            st_plane_a(dst[0] + po, oc, le[0]);
+            st_plane_a(dst[1] + po, oc, le[1]);
+            st_plane_a(dst[2] + po, oc, le[2]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) st_plane_a(dst[3 + c] + po, oc, mm[c]);
         }
@@ -348,39 +479,51 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
         if (k + 4 > klast + 1) break;
     }
 
-    // delta_a: the centre term (that of alpha_a) plus the along-axis
-    // neighbours, which are all the delta slots accumulate per plane
-    acc[3] += acc[0];
-    acc[7] += acc[4];
-    acc[11] += acc[8];
-
     // workgroup reduction of the 12 gradient sums (FP64)
-#pragma unroll
-    for (int j = 0; j < 12; ++j) {
-        double v = acc[j];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[j][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 12) {
-        double v = 0.0;
-        for (int wv = 0; wv < C::WAVES; ++wv) v += red[threadIdx.x][wv];
-        slot[threadIdx.x] = accumulate ? slot[threadIdx.x] + v : v;
-    }
+    adj_reduce<C>(acc, red, slot, accumulate, wave, lane);
 }
 
-template <typename T, typename C>
-__global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void adjoint_step_kernel(
+// Tiles per workgroup of the single-box one-plane pass (one reduction each).
+constexpr int kPlaneAdjTiles = 8;
+
+// Shared storage of a workgroup: the z-march's, or the one-plane pass's.
+template <typename T, typename C, bool PLANE>
+using AdjStore = std::conditional_t<PLANE, PlaneAdjStore<T, C>, AdjSmem<T, C>>;
+// waves per SIMD to leave room for: two 13-wave workgroups of the one-plane
+// pass share a CU
+template <typename C, bool PLANE>
+constexpr int adj_min_waves() { return PLANE ? 7 : C::MIN_WAVES; }
+
+template <typename T, typename C, bool PLANE = false>
+__global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void adjoint_step_kernel(
     Fields<T> lin, Fields<T> lout, const T *__restrict__ en_x, const T *__restrict__ en_y,
     const T *__restrict__ en_z, Dims d, Weights<T> w, int zchunk, int ntx, int nty,
     double *__restrict__ partials, int accumulate)
 {
-    __shared__ AdjSmem<T, C> sm;
+    __shared__ AdjStore<T, C, PLANE> store;
+    AdjSmem<T, C> &sm = reinterpret_cast<AdjSmem<T, C> &>(store);
+    if constexpr (PLANE) {
+        // kPlaneAdjTiles consecutive tiles, one reduction into the first
+        // one's slot; the others' slots hold zero
+        double acc[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+        const int ntiles = ntx * nty;
+        const int t0 = (int)blockIdx.x * kPlaneAdjTiles, t1 = min(t0 + kPlaneAdjTiles, ntiles);
+        for (int t = t0; t < t1; ++t) {
+            adjoint_tile<T, C, true>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, t, sm, nullptr, 0, acc);
+            __syncthreads();  // LDS is reused by the next tile
+        }
+        adj_reduce<C>(acc, store.red, partials + (int64_t)t0 * 12, accumulate, threadIdx.x >> 6, threadIdx.x & 63);
+        if (!accumulate && threadIdx.x < 12)
+            for (int t = t0 + 1; t < t1; ++t) partials[(int64_t)t * 12 + threadIdx.x] = 0.0;
+        return;
+    }
     const int nb = gridDim.x, bid = blockIdx.x;
     const int q = nb >> 3, r = nb & 7, xcd = bid & 7;
     const int logical = xcd * q + min(xcd, r) + (bid >> 3);
-    adjoint_tile<T, C>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, logical, sm,
-                       partials + (int64_t)blockIdx.x * 12, accumulate);
+    adjoint_tile<T, C, PLANE>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, logical, sm,
+                              partials + (int64_t)blockIdx.x * 12, accumulate);
 }
 
 // Batched adjoint step: work item j is tile items[j].y of box items[j].x
@@ -390,22 +533,34 @@ __global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void adjoint_step_kernel(
 // holds item numbers in the host's dispatch order (-1: no work).
 // ONE: one workgroup per slot (gridDim.x == nslots), no slot loop: nothing
 // stays live from one item to the next (the looping variant of the 32x12 tile
-// spills at the register budget of five waves per SIMD).
-template <typename T, typename C, bool ONE>
-__global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
+// spills at the register budget of five waves per SIMD).  PLANE: every box is
+// one plane deep (the one-plane pass of adjoint_tile).
+template <typename T, typename C, bool ONE, bool PLANE = false>
+__global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void batched_adjoint_kernel(const AdjDesc<T> *__restrict__ boxes,
                                                                      const int2 *__restrict__ items,
                                                                      const int *__restrict__ order, int nslots,
                                                                      double *__restrict__ partials,
                                                                      int accumulate)
 {
-    __shared__ AdjSmem<T, C> sm;
+    __shared__ AdjStore<T, C, PLANE> store;
+    AdjSmem<T, C> &sm = reinterpret_cast<AdjSmem<T, C> &>(store);
     if constexpr (ONE) {
         const int j = order[blockIdx.x];
         if (j < 0) return;
         const int2 it = items[j];
         const AdjDesc<T> &b = boxes[it.x];
-        adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
-                           partials + (int64_t)j * 12, accumulate);
+        if constexpr (PLANE) {
+            double acc[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+            adjoint_tile<T, C, true>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty,
+                                     it.y, sm, nullptr, 0, acc);
+            adj_reduce<C>(acc, store.red, partials + (int64_t)j * 12, accumulate, threadIdx.x >> 6,
+                          threadIdx.x & 63);
+        } else {
+            adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y,
+                               sm, partials + (int64_t)j * 12, accumulate);
+        }
         return;
     }
     for (int i = blockIdx.x; i < nslots; i += gridDim.x) {
@@ -413,8 +568,8 @@ __global__ __launch_bounds__(C::THREADS, C::MIN_WAVES) void batched_adjoint_kern
         if (j < 0) continue;
         const int2 it = items[j];
         const AdjDesc<T> &b = boxes[it.x];
-        adjoint_tile<T, C>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y, sm,
-                           partials + (int64_t)j * 12, accumulate);
+        adjoint_tile<T, C, PLANE>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty, it.y,
+                                  sm, partials + (int64_t)j * 12, accumulate);
         __syncthreads();
     }
 }
@@ -503,8 +658,13 @@ hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *
     const int nb = adjoint_blocks(d, tile_x, tile_y, zchunk);
     return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
-        hipLaunchKernelGGL((adjoint_step_kernel<T, C>), dim3(nb), dim3(C::THREADS), 0, s, lin, lout, en[0],
-                           en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
+        if (d.nz == 1)  // one plane: the one-plane pass, kPlaneAdjTiles tiles per workgroup (same partial slots)
+            hipLaunchKernelGGL((adjoint_step_kernel<T, C, true>), dim3((nb + kPlaneAdjTiles - 1) / kPlaneAdjTiles),
+                               dim3(C::THREADS), 0, s, lin, lout, en[0], en[1], en[2], d, w, zchunk, ntx, nty,
+                               partials, accumulate);
+        else
+            hipLaunchKernelGGL((adjoint_step_kernel<T, C>), dim3(nb), dim3(C::THREADS), 0, s, lin, lout, en[0],
+                               en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
         return hipGetLastError();
     });
 }
@@ -536,13 +696,17 @@ hipError_t launch_reduce_partials(const double *partials, int nblocks, const Sca
 
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, const int *order, int nslots,
-                                 double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s)
+                                 double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s,
+                                 bool plane)
 {
     if (nslots <= 0) return hipSuccess;
     if (grid <= 0 || grid > nslots) grid = nslots;
     return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
-        if (grid == nslots)
+        if (plane)  // every box one plane deep: one workgroup per slot
+            hipLaunchKernelGGL((batched_adjoint_kernel<T, C, true, true>), dim3(nslots), dim3(C::THREADS), 0, s,
+                               boxes, items, order, nslots, partials, accumulate);
+        else if (grid == nslots)
             hipLaunchKernelGGL((batched_adjoint_kernel<T, C, true>), dim3(grid), dim3(C::THREADS), 0, s, boxes,
                                items, order, nslots, partials, accumulate);
         else
@@ -560,9 +724,9 @@ hipError_t launch_reduce_boxes(const double *partials, const int *first, int nbo
 }
 
 template hipError_t launch_batched_adjoint<float>(const AdjDesc<float> *, const int2 *, const int *, int, double *,
-                                                  int, int, int, int, hipStream_t);
+                                                  int, int, int, int, hipStream_t, bool);
 template hipError_t launch_batched_adjoint<double>(const AdjDesc<double> *, const int2 *, const int *, int,
-                                                   double *, int, int, int, int, hipStream_t);
+                                                   double *, int, int, int, int, hipStream_t, bool);
 template hipError_t launch_adjoint<float>(const Fields<float> &, const Fields<float> &, const float *const[3],
                                           Dims, const Weights<float> &, int, int, int, double *, int, hipStream_t);
 template hipError_t launch_adjoint<double>(const Fields<double> &, const Fields<double> &,

@@ -147,7 +147,8 @@ struct AdjDesc {
 };
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, const int *order, int nslots,
-                                 double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s);
+                                 double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s,
+                                 bool plane = false);  // plane: every box one plane deep
 // grad[12b + j] += scale[12b + j] * sum_{i in [first[b], first[b+1])} partials[12i + j]
 hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
                                double *grad, hipStream_t s);

@@ -297,3 +297,46 @@ def test_batch_grad_of_plane_boxes(dtype):
             for a, b in zip(lams[i], ls):
                 assert torch.equal(a, b), (i, shape)
             assert np.abs(np.asarray(g[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
+
+
+@pytest.mark.parametrize("plane", [(1, 45, 150), (1, 203, 330)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_one_plane_adjoint_pass_equals_the_z_march(dtype, plane):
+    """A single box one plane deep takes the adjoint's one-plane pass (several
+    tiles per workgroup, one gradient reduction each; the larger plane leaves
+    a ragged last workgroup); the same box in a batch with a deeper box is
+    marched.  States and adjoint fields bitwise equal, coefficient gradients
+    up to the order of the FP64 sums; FP64 also against the oracle's
+    adjoint."""
+    shapes = [plane, (12, 20, 40)]
+    n, seg = 7, 3
+    boxes = []
+    for b, shape in enumerate(shapes):
+        beta, delta = S.distinct_beta_delta(1900 + b)
+        c = O.coeffs_from(beta, delta)
+        sp = (1.0, 0.9, 1.2)
+        boxes.append((shape, S.uniform_fields(shape, 1910 + b), c, 0.95 * O.cfl_dt(c, sp), sp,
+                      S.uniform_fields(shape, 1920 + b)))
+    t = [to_dev(f, dtype) for (_, f, _, _, _, _) in boxes]
+    bt = pkg.Batch([(t[i], dt, c, sp) for i, (_, _, c, dt, sp, _) in enumerate(boxes)], tune=False)
+    ws = bt.grad_workspaces(n, seg)
+    bt.grad_forward(n, ws, seg)
+    lams = [to_dev(lamN, dtype) for (*_, lamN) in boxes]
+    gb = bt.grad_backward(n, ws, lams, seg)
+    shape, f0, c, dt, sp, lamN = boxes[0]
+    ts = to_dev(f0, dtype)
+    s = pkg.Solver(ts, dt, c, spacing=sp, scratch=False)
+    w1 = torch.empty(s.grad_workspace_bytes(n, seg), dtype=torch.uint8, device=DEV)
+    s.grad_forward(n, w1, seg)
+    ls = to_dev(lamN, dtype)
+    gs = np.asarray(s.grad_backward(n, w1, ls, seg))
+    torch.cuda.synchronize()
+    for a, b in zip(t[0], ts):
+        assert torch.equal(a, b)
+    for a, b in zip(lams[0], ls):
+        assert torch.equal(a, b)
+    assert np.abs(np.asarray(gb[0]) - gs).max() <= 1e-12 * np.abs(gs).max()
+    if dtype == torch.float64:
+        fN, g0, gc = O.run_with_adjoint(f0, n, c, dt, sp, lambda f, l=lamN: l)
+        assert rel_l2(to_host(ls), g0) < 1e-12
+        assert np.abs(gs - gc).max() <= 1e-11 * np.abs(gc).max()
