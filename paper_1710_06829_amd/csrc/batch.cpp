@@ -1480,6 +1480,43 @@ int tune_adjoint_t(xfdtd_batch_t b)
     } ev;
     BTRY(hipEventCreate(&ev.e[0]), "hipEventCreate");
     BTRY(hipEventCreate(&ev.e[1]), "hipEventCreate");
+    // the primal E of the timed launches: a copy of the bound E, so that a
+    // launch reads as many distinct bytes as in a backward pass (without a
+    // copy, E^n is the adjoint input's first three arrays)
+    struct TempE {
+        void *p = nullptr;
+        hipStream_t s;
+        ~TempE()
+        {
+            hipStreamSynchronize(s);
+            if (p) hipFree(p);
+        }
+    } tempE{nullptr, b->stream};
+    std::vector<T *> ecopy((size_t)(3 * b->m), nullptr);
+    {
+        std::vector<size_t> off;
+        size_t total = 0;
+        for (int64_t i = 0; i < b->m; ++i)
+            for (int c = 0; c < 3; ++c) {
+                off.push_back(total);
+                total += ((size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * sizeof(T) + 255) / 256 * 256;
+            }
+        if (hipMalloc(&tempE.p, std::max<size_t>(256, total)) == hipSuccess) {
+            for (int64_t i = 0; i < b->m; ++i)
+                for (int c = 0; c < 3; ++c) {
+                    const size_t k = (size_t)(3 * i + c);
+                    ecopy[k] = (T *)((char *)tempE.p + off[k]);
+                    BTRY(hipMemcpyAsync(ecopy[k], b->f[(size_t)(6 * i + c)],
+                                        (size_t)b->g[i].nx * b->g[i].ny * b->g[i].nz * sizeof(T),
+                                        hipMemcpyDeviceToDevice, b->stream),
+                         "hipMemcpyAsync");
+                }
+        } else {
+            (void)hipGetLastError();
+            tempE.p = nullptr;
+            std::fill(ecopy.begin(), ecopy.end(), nullptr);
+        }
+    }
     std::vector<double> per(cands.size(), INFINITY);
     std::vector<int> reps(cands.size(), 0);
     for (int pass = 0; pass < 2 && !rc; ++pass)
@@ -1496,7 +1533,7 @@ int tune_adjoint_t(xfdtd_batch_t b)
                     fin.c[k] = (T *)b->f[(size_t)(6 * i + k)];
                     fout.c[k] = (T *)b->s[(size_t)(6 * i + k)];
                 }
-                for (int k = 0; k < 3; ++k) en[k] = fin.c[k];
+                for (int k = 0; k < 3; ++k) en[k] = ecopy[(size_t)(3 * i + k)] ? ecopy[(size_t)(3 * i + k)] : fin.c[k];
                 descs.push_back(adj_desc<T>(b, i, fin, fout, en));
             }
             AdjDesc<T> *d = nullptr;
@@ -1531,8 +1568,11 @@ int tune_adjoint_t(xfdtd_batch_t b)
         return rc;
     }
     size_t best = 0;
-    for (size_t c = 1; c < cands.size(); ++c)
+    for (size_t c = 0; c < cands.size(); ++c) {
+        xlog("batched adjoint tune candidate %dx%d tiles, z-split %d, %s runs: %.2f us per step", cands[c].tx,
+             cands[c].ty, cands[c].zs, cands[c].boxrun ? "whole-box" : "short", per[c] * 1e3);
         if (per[c] < per[best]) best = c;
+    }
     b->apick = cands[best];
     b->atx = b->apick.tx;
     xlog("batched adjoint tune: %zu candidates, best %dx%d tiles, z-split %d, %s runs, %.2f us per step",
