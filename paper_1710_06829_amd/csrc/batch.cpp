@@ -237,6 +237,20 @@ void box_items(int box, int ntx, int nty, int nz, int zchunk, int warm, int run_
     }
 }
 
+// Adjoint work items of a box one plane deep: groups of kPlaneAdjTiles of
+// its `tiles` tiles (item y = group number), costed by their tile count.
+void plane_items(int box, int tiles, int run_len, std::vector<int2> &items, std::vector<double> &cost,
+                 std::vector<int> &run)
+{
+    const int ng = (tiles + kPlaneAdjTiles - 1) / kPlaneAdjTiles;
+    for (int g = 0; g < ng; ++g) {
+        if (g % run_len == 0) run.push_back(run.empty() ? 0 : run.back() + 1);
+        else run.push_back(run.back());
+        items.push_back(make_int2(box, g));
+        cost.push_back((double)std::min(kPlaneAdjTiles, tiles - g * kPlaneAdjTiles));
+    }
+}
+
 // Run length of a work list: about 1/16 of an XCD's share of the plane
 // iterations, in items of the typical cost.
 int run_length(double total_cost, double items)
@@ -1100,6 +1114,11 @@ int build_adjoint(xfdtd_batch_t b)
             b->azc[(size_t)i] = zc;
             const double tiles = (double)((g.nx + b->atx - 1) / b->atx) * (double)((g.ny + aty - 1) / aty);
             const int nzc = (int)((g.nz + zc - 1) / zc);
+            if (b->plane) {  // items of kPlaneAdjTiles tiles, one pass each
+                total += tiles;
+                count += ceil(tiles / kPlaneAdjTiles);
+                continue;
+            }
             total += tiles * ((double)g.nz + (double)nzc * warm);
             count += tiles * nzc;
         }
@@ -1108,8 +1127,12 @@ int build_adjoint(xfdtd_batch_t b)
         for (int64_t i = 0; i < b->m; ++i) {
             const xfdtd_grid &g = b->g[i];
             const size_t r0 = run.size();
-            box_items((int)i, (int)((g.nx + b->atx - 1) / b->atx), (int)((g.ny + aty - 1) / aty), (int)g.nz,
-                      b->azc[(size_t)i], warm, run_len, items, cost, run);
+            if (b->plane)
+                plane_items((int)i, (int)((g.nx + b->atx - 1) / b->atx) * (int)((g.ny + aty - 1) / aty), run_len,
+                            items, cost, run);
+            else
+                box_items((int)i, (int)((g.nx + b->atx - 1) / b->atx), (int)((g.ny + aty - 1) / aty), (int)g.nz,
+                          b->azc[(size_t)i], warm, run_len, items, cost, run);
             if (boxrun)
                 for (size_t j = r0; j < run.size(); ++j) run[j] = (int)i;
         }

@@ -483,9 +483,6 @@ __device__ __forceinline__ void adjoint_tile(const Fields<T> &lin, const Fields<
     adj_reduce<C>(acc, red, slot, accumulate, wave, lane);
 }
 
-// Tiles per workgroup of the single-box one-plane pass (one reduction each).
-constexpr int kPlaneAdjTiles = 8;
-
 // Shared storage of a workgroup: the z-march's, or the one-plane pass's.
 template <typename T, typename C, bool PLANE>
 using AdjStore = std::conditional_t<PLANE, PlaneAdjStore<T, C>, AdjSmem<T, C>>;
@@ -549,12 +546,16 @@ __global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void batch
         if (j < 0) return;
         const int2 it = items[j];
         const AdjDesc<T> &b = boxes[it.x];
-        if constexpr (PLANE) {
+        if constexpr (PLANE) {  // it.y: a group of kPlaneAdjTiles tiles
             double acc[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) acc[q] = 0.0;
-            adjoint_tile<T, C, true>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty,
-                                     it.y, sm, nullptr, 0, acc);
+            const int t0 = it.y * kPlaneAdjTiles, t1 = min(t0 + kPlaneAdjTiles, b.ntx * b.nty);
+            for (int t = t0; t < t1; ++t) {
+                adjoint_tile<T, C, true>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty,
+                                         t, sm, nullptr, 0, acc);
+                __syncthreads();  // LDS is reused by the next tile
+            }
             adj_reduce<C>(acc, store.red, partials + (int64_t)j * 12, accumulate, threadIdx.x >> 6,
                           threadIdx.x & 63);
         } else {

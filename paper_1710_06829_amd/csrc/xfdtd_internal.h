@@ -145,10 +145,15 @@ struct AdjDesc {
     Weights<T> w;
     int zchunk, ntx, nty, pad;
 };
+// Tiles of one plane per workgroup of the adjoint's one-plane pass (boxes
+// one plane deep): they share one gradient reduction.
+constexpr int kPlaneAdjTiles = 8;
+// plane: every box is one plane deep, and work item (b, g) is the tiles
+// [g kPlaneAdjTiles, (g + 1) kPlaneAdjTiles) of box b (fewer at its end).
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, const int *order, int nslots,
                                  double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s,
-                                 bool plane = false);  // plane: every box one plane deep
+                                 bool plane = false);
 // grad[12b + j] += scale[12b + j] * sum_{i in [first[b], first[b+1])} partials[12i + j]
 hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
                                double *grad, hipStream_t s);

@@ -258,9 +258,10 @@ def test_batch_grad_backward_consumes_the_forward():
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_grad_of_plane_boxes(dtype):
     """A batch of boxes one plane deep (forward and recompute on the plane
-    kernel): FP64 against the oracle's adjoint; FP32 bitwise (states, adjoint
-    fields) against single-box gradient runs, coefficient gradients up to the
-    order of the FP64 sums."""
+    kernel; adjoint work items of up to 8 tiles: 45x150 in 64x8 tiles makes
+    groups of 8, 8 and 2): FP64 against the oracle's adjoint; FP32 bitwise
+    (states, adjoint fields) against single-box gradient runs, coefficient
+    gradients up to the order of the FP64 sums."""
     shapes = [(1, 45, 150), (1, 17, 64), (1, 1, 5)]
     n, seg = 9, 3
     boxes = []
