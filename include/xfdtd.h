@@ -359,9 +359,9 @@ int xfdtd_run_checked(xfdtd_t h, int64_t n, int64_t every, int64_t *done);
  * XFDTD_ADJ_ZCHUNK; lam_out is bitwise the same for every tiling, the
  * gradient up to the summation order of its FP64 partial sums.  A box one
  * plane deep (nz = 1) takes a one-pass kernel instead of the z-march (same
- * lam_out bitwise), whose workgroups each cover 8 tiles and sum their
- * gradient terms once (the workgroup count is unchanged for the partial
- * sums: each launch writes every slot, the other 7 of a group as zero).
+ * lam_out bitwise), whose workgroups each cover up to 16 tiles and sum
+ * their gradient terms once (the partial-sum slots stay one per tile: each
+ * launch writes every slot, the others of a workgroup as zero).
  */
 int xfdtd_adjoint_step(xfdtd_t h, void *const lam_in[6], void *const lam_out[6],
                        const void *const e_n[3], double *grad);
@@ -516,7 +516,7 @@ int xfdtd_reset_stats(xfdtd_t h, int timing);
  *     kernels (64 x 16 tiles in FP32, 64 x 8 in FP64, one step per launch)
  *     whatever the tiling and steps per pass set; get_config and
  *     get_steps_per_pass report those, and the tuner times only the grid.
- *     Its adjoint takes the one-pass kernel, a work item being up to 8
+ *     Its adjoint takes the one-pass kernel, a work item being up to 16
  *     tiles of one box.
  * xfdtd_batch_run: n >= 0 steps of every box through the cached graph (the
  *     graph is re-captured when n or the configuration changes); the result

@@ -92,6 +92,7 @@ struct xfdtd_batch_s {
     double *d_scale = nullptr, *d_grad = nullptr;
     int atx = 64;  // adjoint tile width, height and z-split, chosen when the work list is built
     int aty = 8, azs = 0;
+    int agroup = 1;  // tiles per adjoint work item when every box is one plane deep
     AdjPick apick;  // timed adjoint tiling, used while its tile width is the batch's
     // Workspace lists filled by a forward pass and not yet consumed by a
     // backward pass (which overwrites their E snapshots).
@@ -237,17 +238,17 @@ void box_items(int box, int ntx, int nty, int nz, int zchunk, int warm, int run_
     }
 }
 
-// Adjoint work items of a box one plane deep: groups of kPlaneAdjTiles of
-// its `tiles` tiles (item y = group number), costed by their tile count.
-void plane_items(int box, int tiles, int run_len, std::vector<int2> &items, std::vector<double> &cost,
+// Adjoint work items of a box one plane deep: groups of `group` of its
+// `tiles` tiles (item y = group number), costed by their tile count.
+void plane_items(int box, int tiles, int group, int run_len, std::vector<int2> &items, std::vector<double> &cost,
                  std::vector<int> &run)
 {
-    const int ng = (tiles + kPlaneAdjTiles - 1) / kPlaneAdjTiles;
+    const int ng = (tiles + group - 1) / group;
     for (int g = 0; g < ng; ++g) {
         if (g % run_len == 0) run.push_back(run.empty() ? 0 : run.back() + 1);
         else run.push_back(run.back());
         items.push_back(make_int2(box, g));
-        cost.push_back((double)std::min(kPlaneAdjTiles, tiles - g * kPlaneAdjTiles));
+        cost.push_back((double)std::min(group, tiles - g * group));
     }
 }
 
@@ -1075,7 +1076,7 @@ AdjDesc<T> adj_desc(const xfdtd_batch_s *b, int64_t i, const Fields<T> &lin, con
     a.zchunk = b->azc.empty() ? f.zchunk : b->azc[(size_t)i];
     a.ntx = (int)((b->g[i].nx + b->atx - 1) / b->atx);
     a.nty = (int)((b->g[i].ny + adj_tile(b) - 1) / adj_tile(b));
-    a.pad = 0;
+    a.group = b->plane ? b->agroup : 0;
     return a;
 }
 
@@ -1107,6 +1108,12 @@ int build_adjoint(xfdtd_batch_t b)
         cost.clear();
         run.clear();
         b->azc.assign((size_t)b->m, 1);
+        if (b->plane) {  // tiles per work item from the batch's tile count
+            int64_t tiles = 0;
+            for (int64_t i = 0; i < b->m; ++i)
+                tiles += (int64_t)((b->g[i].nx + b->atx - 1) / b->atx) * ((b->g[i].ny + aty - 1) / aty);
+            b->agroup = plane_adj_group(tiles);
+        }
         double total = 0, count = 0;
         for (int64_t i = 0; i < b->m; ++i) {
             const xfdtd_grid &g = b->g[i];
@@ -1114,9 +1121,9 @@ int build_adjoint(xfdtd_batch_t b)
             b->azc[(size_t)i] = zc;
             const double tiles = (double)((g.nx + b->atx - 1) / b->atx) * (double)((g.ny + aty - 1) / aty);
             const int nzc = (int)((g.nz + zc - 1) / zc);
-            if (b->plane) {  // items of kPlaneAdjTiles tiles, one pass each
+            if (b->plane) {  // items of b->agroup tiles, one pass each
                 total += tiles;
-                count += ceil(tiles / kPlaneAdjTiles);
+                count += ceil(tiles / b->agroup);
                 continue;
             }
             total += tiles * ((double)g.nz + (double)nzc * warm);
@@ -1128,8 +1135,8 @@ int build_adjoint(xfdtd_batch_t b)
             const xfdtd_grid &g = b->g[i];
             const size_t r0 = run.size();
             if (b->plane)
-                plane_items((int)i, (int)((g.nx + b->atx - 1) / b->atx) * (int)((g.ny + aty - 1) / aty), run_len,
-                            items, cost, run);
+                plane_items((int)i, (int)((g.nx + b->atx - 1) / b->atx) * (int)((g.ny + aty - 1) / aty), b->agroup,
+                            run_len, items, cost, run);
             else
                 box_items((int)i, (int)((g.nx + b->atx - 1) / b->atx), (int)((g.ny + aty - 1) / aty), (int)g.nz,
                           b->azc[(size_t)i], warm, run_len, items, cost, run);

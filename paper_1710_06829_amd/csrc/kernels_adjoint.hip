@@ -500,13 +500,15 @@ __global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void adjoi
     __shared__ AdjStore<T, C, PLANE> store;
     AdjSmem<T, C> &sm = reinterpret_cast<AdjSmem<T, C> &>(store);
     if constexpr (PLANE) {
-        // kPlaneAdjTiles consecutive tiles, one reduction into the first
-        // one's slot; the others' slots hold zero
+        // consecutive tiles, as many per workgroup as the grid leaves; one
+        // reduction into the first one's slot, the others' slots hold zero
+        const int ntiles = ntx * nty;
+        const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int t0 = (int)blockIdx.x * per, t1 = min(t0 + per, ntiles);
+        if (t0 >= ntiles) return;  // the whole workgroup, before any barrier
         double acc[12];
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] = 0.0;
-        const int ntiles = ntx * nty;
-        const int t0 = (int)blockIdx.x * kPlaneAdjTiles, t1 = min(t0 + kPlaneAdjTiles, ntiles);
         for (int t = t0; t < t1; ++t) {
             adjoint_tile<T, C, true>(lin, lout, en_x, en_y, en_z, d, w, zchunk, ntx, nty, t, sm, nullptr, 0, acc);
             __syncthreads();  // LDS is reused by the next tile
@@ -546,11 +548,11 @@ __global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void batch
         if (j < 0) return;
         const int2 it = items[j];
         const AdjDesc<T> &b = boxes[it.x];
-        if constexpr (PLANE) {  // it.y: a group of kPlaneAdjTiles tiles
+        if constexpr (PLANE) {  // it.y: a group of b.group tiles
             double acc[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) acc[q] = 0.0;
-            const int t0 = it.y * kPlaneAdjTiles, t1 = min(t0 + kPlaneAdjTiles, b.ntx * b.nty);
+            const int t0 = it.y * b.group, t1 = min(t0 + b.group, b.ntx * b.nty);
             for (int t = t0; t < t1; ++t) {
                 adjoint_tile<T, C, true>(b.lin, b.lout, b.en[0], b.en[1], b.en[2], b.d, b.w, b.zchunk, b.ntx, b.nty,
                                          t, sm, nullptr, 0, acc);
@@ -659,15 +661,38 @@ hipError_t launch_adjoint(const Fields<T> &lin, const Fields<T> &lout, const T *
     const int nb = adjoint_blocks(d, tile_x, tile_y, zchunk);
     return with_adj_tile<T>(tile_x, tile_y, [&](auto cfg) {
         using C = decltype(cfg);
-        if (d.nz == 1)  // one plane: the one-plane pass, kPlaneAdjTiles tiles per workgroup (same partial slots)
-            hipLaunchKernelGGL((adjoint_step_kernel<T, C, true>), dim3((nb + kPlaneAdjTiles - 1) / kPlaneAdjTiles),
-                               dim3(C::THREADS), 0, s, lin, lout, en[0], en[1], en[2], d, w, zchunk, ntx, nty,
-                               partials, accumulate);
+        if (d.nz == 1) {  // one plane: the one-plane pass, several tiles per workgroup (same partial slots)
+            const int g = plane_adj_group(nb);
+            hipLaunchKernelGGL((adjoint_step_kernel<T, C, true>), dim3((nb + g - 1) / g), dim3(C::THREADS), 0, s,
+                               lin, lout, en[0], en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
+        }
         else
             hipLaunchKernelGGL((adjoint_step_kernel<T, C>), dim3(nb), dim3(C::THREADS), 0, s, lin, lout, en[0],
                                en[1], en[2], d, w, zchunk, ntx, nty, partials, accumulate);
         return hipGetLastError();
     });
+}
+
+int plane_adj_group(int64_t tiles)
+{
+    static int ncu[64];  // per device, looked up once
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        dev = -1;
+    }
+    int n = dev >= 0 ? __atomic_load_n(&ncu[dev], __ATOMIC_RELAXED) : 0;
+    if (n <= 0) {
+        if (dev < 0 || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0) {
+            (void)hipGetLastError();
+            n = 256;
+        } else {
+            __atomic_store_n(&ncu[dev], n, __ATOMIC_RELAXED);
+        }
+    }
+    const int64_t g = tiles / (2 * (int64_t)n);
+    return (int)(g < 1 ? 1 : g > kPlaneAdjTiles ? kPlaneAdjTiles : g);
 }
 
 template <typename T>

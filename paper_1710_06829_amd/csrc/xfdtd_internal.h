@@ -143,13 +143,17 @@ struct AdjDesc {
     const T *en[3];
     Dims d;
     Weights<T> w;
-    int zchunk, ntx, nty, pad;
+    int zchunk, ntx, nty, group;  // group: tiles per work item of a one-plane box
 };
-// Tiles of one plane per workgroup of the adjoint's one-plane pass (boxes
-// one plane deep): they share one gradient reduction.
-constexpr int kPlaneAdjTiles = 8;
+// Most tiles of one plane per workgroup of the adjoint's one-plane pass
+// (boxes one plane deep): a workgroup's tiles share one gradient reduction.
+constexpr int kPlaneAdjTiles = 16;
+// Tiles per workgroup of the one-plane pass over `tiles` tiles in all: as
+// many as still leave two workgroups per CU of the current device, 1 to
+// kPlaneAdjTiles.
+int plane_adj_group(int64_t tiles);
 // plane: every box is one plane deep, and work item (b, g) is the tiles
-// [g kPlaneAdjTiles, (g + 1) kPlaneAdjTiles) of box b (fewer at its end).
+// [g G, (g + 1) G) of box b (fewer at its end), G = boxes[b].group.
 template <typename T>
 hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, const int *order, int nslots,
                                  double *partials, int accumulate, int tile_x, int tile_y, int grid, hipStream_t s,

@@ -258,11 +258,13 @@ def test_batch_grad_backward_consumes_the_forward():
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_grad_of_plane_boxes(dtype):
     """A batch of boxes one plane deep (forward and recompute on the plane
-    kernel; adjoint work items of up to 8 tiles: 45x150 in 64x8 tiles makes
-    groups of 8, 8 and 2): FP64 against the oracle's adjoint; FP32 bitwise
+    kernel; adjoint work items of several tiles once the batch has at least
+    two per workgroup of every CU: on 256 CUs with 64-wide tiles, 2 in FP32
+    and 4 in FP64, the 17x64 box then in groups of 2 and 1, or 4 and 1):
+    FP64 against the oracle's adjoint; FP32 bitwise
     (states, adjoint fields) against single-box gradient runs, coefficient
     gradients up to the order of the FP64 sums."""
-    shapes = [(1, 45, 150), (1, 17, 64), (1, 1, 5)]
+    shapes = [(1, 45, 150), (1, 17, 64), (1, 1, 5), (1, 520, 1000)]
     n, seg = 9, 3
     boxes = []
     for b, shape in enumerate(shapes):
@@ -300,13 +302,13 @@ def test_batch_grad_of_plane_boxes(dtype):
             assert np.abs(np.asarray(g[i]) - gs).max() <= 1e-12 * np.abs(gs).max(), (i, shape)
 
 
-@pytest.mark.parametrize("plane", [(1, 45, 150), (1, 203, 330)])
+@pytest.mark.parametrize("plane", [(1, 45, 150), (1, 1090, 900)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_one_plane_adjoint_pass_equals_the_z_march(dtype, plane):
-    """A single box one plane deep takes the adjoint's one-plane pass (several
-    tiles per workgroup, one gradient reduction each; the larger plane leaves
-    a ragged last workgroup); the same box in a batch with a deeper box is
-    marched.  States and adjoint fields bitwise equal, coefficient gradients
+    """A single box one plane deep takes the adjoint's one-plane pass (on 256
+    CUs the 1090x900 plane has 2055 tiles of 64x8 in FP32, 4 per workgroup
+    and 3 in the last, and 4095 of 64x4 in FP64, 7 per workgroup); the same
+    box in a batch with a deeper box is marched.  States and adjoint fields bitwise equal, coefficient gradients
     up to the order of the FP64 sums; FP64 also against the oracle's
     adjoint."""
     shapes = [plane, (12, 20, 40)]
