@@ -179,6 +179,22 @@ __device__ __forceinline__ void adj_out(T le[3], const T la[3], T s3a, T s3b, T 
     le[2] = la[2] + ((Sp[1][li] - Sp[1][li - PX]) - (Sp[2][li] - Sp[2][li - 1]));
 }
 
+// Sum of v over the wave's 64 lanes, complete in lane 63 (fixed order, in
+// registers through DPP lane moves): inclusive scans within each row of 16
+// lanes (shifts by 1, 2, 4, 8; lanes shifted in from outside the row add
+// zero), then rows 1 and 3 add the last lane of rows 0 and 2 (row broadcast
+// of lane 15), then rows 2 and 3 add lane 31 (row broadcast of lane 31).
+__device__ __forceinline__ double wave_sum_lane63(double v)
+{
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // The workgroup's 12 gradient sums (FP64, fixed order) into slot: written,
 // or added to when accumulate != 0.
 template <typename C>
@@ -192,9 +208,8 @@ __device__ __forceinline__ void adj_reduce(double acc[12], double (&red)[12][C::
     acc[11] += acc[8];
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
-        double v = acc[j];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[j][wave] = v;
+        const double v = wave_sum_lane63(acc[j]);
+        if (lane == 63) red[j][wave] = v;
     }
     __syncthreads();
     if (threadIdx.x < 12) {
