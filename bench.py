@@ -232,6 +232,66 @@ def fwd_adj_ratio(steps=200):
             "probe-plane misfit loss, gradients w.r.t. 12 coefficients and initial fields"}
 
 
+def plane_2d(steps=200, edge=2048):
+    """A box one plane deep (edge x edge x 1 FP32, the pulse workload):
+    forward rate on the plane kernel, the one-plane adjoint step against 60 B
+    per cell, and the checkpointed forward + backward over the forward with
+    sqrt(N) segments (adjoint seeds drawn uniformly)."""
+    import math
+
+    import torch
+
+    import paper_1710_06829_amd as pkg
+
+    shape = (1, edge, edge)
+    f, coeffs, dt, _ = make_inputs(shape, torch.float32)
+    cells = edge * edge
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    sp = pkg.Solver([x.clone() for x in f], dt, coeffs)
+    sp.run(10)
+    t_fwd = min(timed(lambda: sp.run(steps)) for _ in range(3))
+    seg = int(math.ceil(math.sqrt(2 * steps)))
+    work = [x.clone() for x in f]
+    sg = pkg.Solver(work, dt, coeffs, scratch=False)
+    ws = torch.empty(sg.grad_workspace_bytes(steps, seg), dtype=torch.uint8, device=f[0].device)
+    gen = torch.Generator(device=f[0].device)
+    gen.manual_seed(560)
+    lam0 = [torch.rand(x.shape, device=x.device, generator=gen) * 2 - 1 for x in work]
+    lam = [x.clone() for x in lam0]
+    best = None
+    for rep in range(3):
+        for a in range(6):
+            work[a].copy_(f[a])
+            lam[a].copy_(lam0[a])
+        tf = timed(lambda: sg.grad_forward(steps, ws, seg))
+        tb = timed(lambda: sg.grad_backward(steps, ws, lam, seg))
+        if best is None or tf + tb < sum(best):
+            best = (tf, tb)
+    g = torch.zeros(12, dtype=torch.float64, device=f[0].device)
+    lb = [torch.empty_like(x) for x in lam0]
+    sg.adjoint_step(lam0, lb, f[:3], g)
+    n_adj = 50
+    t_adj = min(timed(lambda: [sg.adjoint_step(lam0, lb, f[:3], g) for _ in range(n_adj)]) for _ in range(3)) / n_adj
+    return {"workload": f"{edge}x{edge}x1 FP32 pulse box (one plane deep), {steps} steps",
+            "forward_us_per_step": round(t_fwd / steps * 1e3, 2),
+            "Gcell_updates_per_s": round(cells * steps / (t_fwd * 1e-3) / 1e9, 2),
+            "hbm_frac_48B": round(48.0 * cells / (t_fwd / steps * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "adjoint_us_per_step": round(t_adj * 1e3, 2),
+            "adjoint_frac_60B": round(60.0 * cells / (t_adj * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "grad_forward_ms": round(best[0], 3), "grad_backward_ms": round(best[1], 3), "segment": seg,
+            "ratio_to_forward": round(sum(best) / t_fwd, 3)}
+
+
 def fp64_step(steps=200):
     """The 512x256x256 pulse workload in FP64 (tuned launch): rate and the
     fraction of 8 TB/s at 96 algorithmic bytes per cell-update."""
@@ -497,6 +557,7 @@ def main():
     ap.add_argument("--norm-only", action="store_true", help="only the dispersion-norm measurement")
     ap.add_argument("--fp64-only", action="store_true", help="only the FP64 512x256x256 measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-box batched measurement")
+    ap.add_argument("--plane-only", action="store_true", help="only the 2048^2 one-plane measurement")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch kernels directly instead of replaying captured graphs")
     ap.add_argument("--no-extra", action="store_true",
@@ -531,6 +592,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batched_64_boxes": batched_boxes()}), flush=True)
+        return
+    if args.plane_only:
+        print(json.dumps({"plane_2048x2048": plane_2d()}), flush=True)
         return
     fields, coeffs, dt, f64 = make_inputs(SHAPE, torch.float32)
     solver = pkg.Solver(fields, dt, coeffs)
@@ -632,6 +696,8 @@ def main():
         line["batched_64_boxes"] = batched_boxes()
         torch.cuda.empty_cache()
         line["batched_grads_16x96cube"] = batched_grads()
+        torch.cuda.empty_cache()
+        line["plane_2048x2048"] = plane_2d()
         torch.cuda.empty_cache()
         line["dispersion_norm"] = norm_bench()
     if args.calib:

@@ -592,6 +592,31 @@ __global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void batch
     }
 }
 
+// Sums of the 12-value slots [i0, i1) of partials by a 256-thread
+// workgroup, fixed order: thread t adds slots i0 + t, i0 + t + 256, ... in
+// turn (all 12 values of a slot loaded together), then a tree over the
+// threads; slot value j's total ends in sm[j][0].
+__device__ __forceinline__ void sum_slots(const double *__restrict__ partials, int i0, int i1,
+                                          double (&sm)[12][256])
+{
+    double v[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) v[j] = 0.0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) {
+        const double *p = partials + (int64_t)i * 12;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) v[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) sm[j][threadIdx.x] = v[j];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int j = 0; j < 12; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + st];
+        __syncthreads();
+    }
+}
+
 // grad[12 b + j] += scale[12 b + j] * sum of partials over box b's items
 // [first[b], first[b+1]); one block per box, fixed order.
 __global__ __launch_bounds__(256) void reduce_boxes_kernel(const double *__restrict__ partials,
@@ -601,18 +626,7 @@ __global__ __launch_bounds__(256) void reduce_boxes_kernel(const double *__restr
 {
     __shared__ double sm[12][256];
     const int b = blockIdx.x;
-    const int i0 = first[b], i1 = first[b + 1];
-    for (int j = 0; j < 12; ++j) {
-        double v = 0.0;
-        for (int i = i0 + threadIdx.x; i < i1; i += 256) v += partials[(int64_t)i * 12 + j];
-        sm[j][threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st)
-            for (int j = 0; j < 12; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + st];
-        __syncthreads();
-    }
+    sum_slots(partials, first[b], first[b + 1], sm);
     if (threadIdx.x < 12) grad[12 * b + threadIdx.x] += scale[12 * b + threadIdx.x] * sm[threadIdx.x][0];
 }
 
@@ -622,17 +636,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
                                                               double *__restrict__ grad)
 {
     __shared__ double sm[12][256];
-    for (int j = 0; j < 12; ++j) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) v += partials[(int64_t)b * 12 + j];
-        sm[j][threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int j = 0; j < 12; ++j) sm[j][threadIdx.x] += sm[j][threadIdx.x + s];
-        __syncthreads();
-    }
+    sum_slots(partials, 0, nblocks, sm);
     if (threadIdx.x < 12) grad[threadIdx.x] += sc.s[threadIdx.x] * sm[threadIdx.x][0];
 }
 
