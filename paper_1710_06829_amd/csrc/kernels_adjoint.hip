@@ -592,18 +592,18 @@ __global__ __launch_bounds__(C::THREADS, (adj_min_waves<C, PLANE>())) void batch
     }
 }
 
-// Sums of the 12-value slots [i0, i1) of partials by a 256-thread
-// workgroup, fixed order: thread t adds slots i0 + t, i0 + t + 256, ... in
-// turn (all 12 values of a slot loaded together), then a tree over the
-// threads; slot value j's total ends in sm[j][0].
-__device__ __forceinline__ void sum_slots(const double *__restrict__ partials, int i0, int i1,
+// Sums of the 12-value slots i0, i0 + stride, ... (count of them) of
+// partials by a 256-thread workgroup, fixed order: thread t adds slots
+// number t, t + 256, ... in turn (all 12 values of a slot loaded together),
+// then a tree over the threads; slot value j's total ends in sm[j][0].
+__device__ __forceinline__ void sum_slots(const double *partials, int i0, int count, int stride,
                                           double (&sm)[12][256])
 {
     double v[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) v[j] = 0.0;
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) {
-        const double *p = partials + (int64_t)i * 12;
+    for (int m = (int)threadIdx.x; m < count; m += 256) {
+        const double *p = partials + ((int64_t)i0 + (int64_t)m * stride) * 12;
 #pragma unroll
         for (int j = 0; j < 12; ++j) v[j] += p[j];
     }
@@ -626,17 +626,28 @@ __global__ __launch_bounds__(256) void reduce_boxes_kernel(const double *__restr
 {
     __shared__ double sm[12][256];
     const int b = blockIdx.x;
-    sum_slots(partials, first[b], first[b + 1], sm);
+    sum_slots(partials, first[b], first[b + 1] - first[b], 1, sm);
     if (threadIdx.x < 12) grad[12 * b + threadIdx.x] += scale[12 * b + threadIdx.x] * sm[threadIdx.x][0];
 }
 
-// grad[j] += scale[j] * sum_b partials[b][j], one block, fixed order.
+// First stage of a long reduction: workgroup k sums the slots [256 k,
+// 256 k + 256) and writes the sums into slot 256 k, in place.
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(double *partials, int nblocks)
+{
+    __shared__ double sm[12][256];
+    const int i0 = (int)blockIdx.x * 256;
+    sum_slots(partials, i0, min(256, nblocks - i0), 1, sm);  // ends with a barrier: slot i0 has been read
+    if (threadIdx.x < 12) partials[(int64_t)i0 * 12 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// grad[j] += scale[j] * sum over the slots 0, stride, ... (nslots of them)
+// of partials[slot][j], one block, fixed order.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ partials,
-                                                              int nblocks, Scale12 sc,
+                                                              int nslots, int stride, Scale12 sc,
                                                               double *__restrict__ grad)
 {
     __shared__ double sm[12][256];
-    sum_slots(partials, 0, nblocks, sm);
+    sum_slots(partials, 0, nslots, stride, sm);
     if (threadIdx.x < 12) grad[threadIdx.x] += sc.s[threadIdx.x] * sm[threadIdx.x][0];
 }
 
@@ -732,10 +743,15 @@ int adjoint_occupancy(int tile_x, int tile_y)
 template int adjoint_occupancy<float>(int, int);
 template int adjoint_occupancy<double>(int, int);
 
-hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
-                                  hipStream_t s)
+hipError_t launch_reduce_partials(double *partials, int nblocks, const Scale12 &sc, double *grad, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, sc, grad);
+    if (nblocks > 1024) {  // chunks of 256 slots first (one workgroup each), then their sums
+        const int nch = (nblocks + 255) / 256;
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3(nch), dim3(256), 0, s, partials, nblocks);
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partials, nch, 256, sc, grad);
+    } else {
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, 1, sc, grad);
+    }
     return hipGetLastError();
 }
 

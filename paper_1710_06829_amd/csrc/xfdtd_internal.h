@@ -161,9 +161,9 @@ hipError_t launch_batched_adjoint(const AdjDesc<T> *boxes, const int2 *items, co
 // grad[12b + j] += scale[12b + j] * sum_{i in [first[b], first[b+1])} partials[12i + j]
 hipError_t launch_reduce_boxes(const double *partials, const int *first, int nboxes, const double *scale,
                                double *grad, hipStream_t s);
-// grad[j] += sc.s[j] * sum over blocks of partials[b*12 + j]
-hipError_t launch_reduce_partials(const double *partials, int nblocks, const Scale12 &sc, double *grad,
-                                  hipStream_t s);
+// grad[j] += sc.s[j] * sum over blocks of partials[b*12 + j]; consumes
+// partials (above 1024 blocks the sums of 256-block chunks overwrite them).
+hipError_t launch_reduce_partials(double *partials, int nblocks, const Scale12 &sc, double *grad, hipStream_t s);
 
 // Diagnostics (kernels_diag.hip).
 template <typename T>
